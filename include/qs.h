@@ -1,0 +1,164 @@
+/*
+ * qs.h -- C ABI of libqs, an MI355X (gfx950) state-vector gate engine.
+ *
+ * The engine applies quantum gates to a full vector of 2^n complex amplitudes held in HBM, following the
+ * state-vector method of mpiQulacs (Imamura et al., "mpiQulacs: A Distributed Quantum Computer Simulator
+ * for A64FX-based Cluster Systems"):
+ *   - Sec. II-A, Eq. 2: the state is 2^n complex amplitudes a_i, sum_i |a_i|^2 = 1; in double precision it
+ *     takes 2^(n+4) bytes;
+ *   - Sec. II-A, Eq. 4: a 1-qubit gate U on qubit q multiplies every amplitude pair whose indices differ
+ *     only in bit q by the 2x2 matrix U; k-qubit gates generalise this to the 2^k amplitudes whose
+ *     indices differ only in the target bits;
+ *   - Sec. III-D, Listing 1: fused_swap(p, q, s) performs swap(p+i, q+i) for i < s, the two ranges
+ *     [p, p+s) and [q, q+s) not overlapping.
+ * On one GPU the fused-swap is an in-place permutation of HBM (the paper moves the same amplitudes
+ * between processes); it exchanges high-order and low-order qubits.
+ *
+ * Conventions shared by every call
+ *   Layout.    Amplitudes are interleaved (re, im): complex128 = 2 doubles (16 B), complex64 = 2 floats
+ *              (8 B), i.e. the layout of torch.complex128 / torch.complex64. Qubit q is bit q of the index
+ *              (qubit 0 = least significant bit).
+ *   Matrices.  A k-qubit matrix U is a host array of 2^k x 2^k complex numbers given as interleaved FP64
+ *              (re, im), row-major, with targets[j] <-> bit j of the row/column index, and psi' = U psi.
+ *              FP64 is used for complex64 states too; the library rounds to FP32.
+ *   Status.    Every call returns QS_OK (0) or a negative QS_E* code; qs_last_error() gives a thread-local
+ *              message for the last failure on the calling thread. No C++ exception or abort crosses the ABI.
+ *   Validation happens before anything is enqueued: a rejected call leaves the state unchanged.
+ *   Ordering.  Calls enqueue work on the state's HIP stream and return without synchronising (except where
+ *              stated). Device faults surface at qs_sync, qs_copy_out or a norm read-back.
+ *   Ownership. The caller owns every host array passed in; the library copies or packs it before returning,
+ *              so it may be freed on return. Device buffers passed in (dev_buf, out_dev) are the caller's and
+ *              must stay alive until the work that uses them has completed on the stream.
+ *   Threads.   A handle may be used by one thread at a time.
+ */
+#ifndef QS_H
+#define QS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define QS_API __attribute__((visibility("default")))
+
+enum {
+    QS_OK = 0,
+    QS_EINVAL = -1,       /* argument out of range, null pointer, overlapping qubits */
+    QS_ENOMEM = -2,       /* device or pinned-host allocation failed */
+    QS_EDEVICE = -3,      /* a HIP runtime call failed (no device, launch failure, fault) */
+    QS_EUNSUPPORTED = -4  /* a valid request this build does not implement */
+};
+
+enum { QS_C128 = 0, QS_C64 = 1 };
+
+#define QS_MAX_QUBITS 40  /* upper bound accepted by qs_alloc; HBM capacity is the practical bound */
+#define QS_MAX_K 6        /* largest dense / controlled target count */
+#define QS_MAX_DIAG_K 12  /* largest diagonal target count */
+#define QS_MAX_CONTROLS 16
+
+typedef struct qs_state qs_state;
+
+/*
+ * qs_alloc -- create a state of n qubits and initialise it to |0...0> (Sec. II-A, Eq. 2).
+ *   out        receives the handle (must not be NULL).
+ *   n          1 <= n <= QS_MAX_QUBITS.
+ *   dtype      QS_C128 or QS_C64.
+ *   dev_buf    NULL: the library allocates 2^n amplitudes on the current device and frees them in qs_free.
+ *              Otherwise a device buffer of at least 2^n * sizeof(amplitude) bytes, 256-byte aligned, that
+ *              the caller owns and keeps alive for the handle's lifetime.
+ *   hip_stream the hipStream_t to enqueue on (NULL = the null stream).
+ * Errors: QS_EINVAL (out NULL, n or dtype out of range, misaligned dev_buf), QS_ENOMEM, QS_EDEVICE.
+ */
+QS_API int qs_alloc(qs_state **out, int n, int dtype, void *dev_buf, void *hip_stream);
+
+/* qs_free -- synchronise the stream, release library-owned memory and the handle. QS_EINVAL if st is NULL. */
+QS_API int qs_free(qs_state *st);
+
+/*
+ * qs_apply_gate -- dense k-qubit gate, 1 <= k <= QS_MAX_K (Sec. II-A, Eq. 4 and its k-qubit form).
+ *   targets  k distinct qubits in [0, n); targets[j] <-> bit j of U's index.
+ *   U        2^k x 2^k complex FP64, row-major, interleaved.
+ * Matrices whose entries are all in {0, 1, -1, i, -i} with one nonzero per row and column (X, CNOT blocks,
+ * SWAP, Y up to the factor, ...) are executed as pure amplitude moves with sign/component exchange: no
+ * arithmetic, bit-exact. Exactly diagonal matrices are executed as qs_apply_diag.
+ * Errors: QS_EINVAL (null pointers, k out of range, target out of range or repeated).
+ */
+QS_API int qs_apply_gate(qs_state *st, const int *targets, int k, const double *U);
+
+/*
+ * qs_apply_diag -- diagonal gate: a_i <- d[a(i)] a_i, a(i) = the target bits of i in targets order
+ * (Eq. 4 with a diagonal U; RZ, CZ, controlled phases). 1 <= k <= QS_MAX_DIAG_K.
+ *   d  2^k complex FP64, interleaved. Entries exactly 1 leave their amplitudes untouched (not even read or
+ *      written); entries exactly -1 are a sign flip (exact).
+ * Errors: as qs_apply_gate.
+ */
+QS_API int qs_apply_diag(qs_state *st, const int *targets, int k, const double *d);
+
+/*
+ * qs_apply_controlled -- U on the targets, restricted to the amplitudes whose control bits are all 1
+ * (CNOT, Toffoli, controlled-U). 1 <= c <= QS_MAX_CONTROLS, 1 <= k <= QS_MAX_K, c + k <= n. Permutation
+ * matrices (see qs_apply_gate) are pure moves, bit-exact.
+ * Errors: QS_EINVAL (null pointers, counts out of range, qubits out of range, repeated, or a control that
+ * is also a target).
+ */
+QS_API int qs_apply_controlled(qs_state *st, const int *controls, int c, const int *targets, int k, const double *U);
+
+/*
+ * qs_fused_swap -- fused_swap(p, q, s) of Sec. III-D, Listing 1: swap(p+i, q+i) for 0 <= i < s, in place:
+ * psi'[sigma(i)] = psi[i] where sigma exchanges bit p+j with bit q+j. Pure moves, bit-exact; the
+ * 2^(n-s) fixed points are neither read nor written. s = 0 is a no-op; p and q may come in either order.
+ * Errors: QS_EINVAL if s < 0, p < 0, q < 0, p+s > n, q+s > n, or the ranges overlap (|p - q| < s).
+ */
+QS_API int qs_fused_swap(qs_state *st, int p, int q, int s);
+
+/*
+ * qs_probs -- out_dev[i] = |a_i|^2 in FP64 (complex64 components are widened first) (Sec. II-A).
+ *   out_dev   device buffer of 2^n doubles (caller-owned), or NULL to compute only the norm.
+ *   norm_out  host pointer, or NULL. When non-NULL the call synchronises the stream and stores
+ *             sum_i |a_i|^2, reduced in FP64 in a fixed order (run-to-run bit-identical).
+ * Errors: QS_EINVAL (st NULL), QS_EDEVICE.
+ */
+QS_API int qs_probs(qs_state *st, double *out_dev, double *norm_out);
+
+/* ---- state management and support calls (used by tests, renormalisation and harnesses) ---- */
+
+/* Reset to |0...0> (a fill kernel, no memset). */
+QS_API int qs_init_zero(qs_state *st);
+/* Copy 2^n amplitudes from / to host memory in the state's dtype layout; synchronous. */
+QS_API int qs_copy_in(qs_state *st, const void *host);
+QS_API int qs_copy_out(qs_state *st, void *host);
+/* Wait for all work enqueued on the state's stream. */
+QS_API int qs_sync(qs_state *st);
+/* a_i <- f a_i with f in FP64 (complex64: product rounded to FP32). */
+QS_API int qs_scale(qs_state *st, double f);
+/* Synchronously compute the FP64 norm sum_i |a_i|^2 (same fixed-order reduction as qs_probs). */
+QS_API int qs_norm(qs_state *st, double *norm_out);
+/* Renormalise: a_i <- a_i / sqrt(sum |a|^2); the factor is formed in FP64. Optionally returns the norm
+ * measured before scaling. Synchronises. */
+QS_API int qs_renormalize(qs_state *st, double *norm_before);
+/* Query handle properties; any output pointer may be NULL. */
+QS_API int qs_get_info(qs_state *st, int *n, int *dtype, void **dev_ptr, void **hip_stream);
+/* Message of the last failing call on this thread ("" if none). */
+QS_API const char *qs_last_error(void);
+
+/* ---- bandwidth probes (the measured HBM ceiling the gate kernels are compared against) ---- */
+
+/* dst[i] = src[i] over `bytes` (multiple of 16, both 16-byte aligned), enqueued on hip_stream. */
+QS_API int qs_probe_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+/* In-place read-modify-write of every 16-byte word of buf (x <- x * 1.0 per double): the traffic pattern of
+ * an in-place gate pass with no arithmetic dependence between words. */
+QS_API int qs_probe_rmw(void *buf, size_t bytes, void *hip_stream);
+
+/* ---- launch tunables (autotuner / sweeps) ----
+ * "dense_gpt"   groups per thread of the 1- and 2-qubit dense kernels: 1, 2 or 4 (default 2);
+ * "nontemporal" 0/1: non-temporal loads and stores in the dense kernels (default 0).
+ * Process-wide; affects launches enqueued after the call. QS_EINVAL for an unknown name or value. */
+QS_API int qs_set_tunable(const char *name, int64_t value);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QS_H */

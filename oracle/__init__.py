@@ -68,8 +68,12 @@ def _check_state(psi: np.ndarray):
     return n
 
 
-def _mat(m: np.ndarray) -> np.ndarray:
-    return np.ascontiguousarray(np.asarray(m, dtype=np.complex128))
+def _mat(m: np.ndarray, k: int, diag: bool = False) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(m, dtype=np.complex128))
+    want = (1 << k,) if diag else (1 << k, 1 << k)
+    if a.shape != want:
+        raise ValueError(f"matrix shape {a.shape} does not match {k} target(s): expected {want}")
+    return a
 
 
 def zero_state(n: int) -> np.ndarray:
@@ -80,7 +84,7 @@ def zero_state(n: int) -> np.ndarray:
 
 def apply_dense(psi: np.ndarray, targets, U) -> None:
     n = _check_state(psi)
-    U = _mat(U)
+    U = _mat(U, len(targets))
     rc = lib().or_apply_dense(_dptr(psi.view(np.float64)), n, _iarr(targets), len(targets), _dptr(U.view(np.float64)))
     if rc:
         raise ValueError(f"or_apply_dense rejected targets={targets}")
@@ -88,7 +92,7 @@ def apply_dense(psi: np.ndarray, targets, U) -> None:
 
 def apply_controlled(psi: np.ndarray, controls, targets, U) -> None:
     n = _check_state(psi)
-    U = _mat(U)
+    U = _mat(U, len(targets))
     rc = lib().or_apply_controlled(_dptr(psi.view(np.float64)), n, _iarr(controls), len(controls), _iarr(targets),
                                    len(targets), _dptr(U.view(np.float64)))
     if rc:
@@ -97,7 +101,7 @@ def apply_controlled(psi: np.ndarray, controls, targets, U) -> None:
 
 def apply_diag(psi: np.ndarray, targets, d) -> None:
     n = _check_state(psi)
-    d = _mat(d)
+    d = _mat(d, len(targets), diag=True)
     rc = lib().or_apply_diag(_dptr(psi.view(np.float64)), n, _iarr(targets), len(targets), _dptr(d.view(np.float64)))
     if rc:
         raise ValueError(f"or_apply_diag rejected targets={targets}")

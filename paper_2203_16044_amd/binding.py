@@ -1,0 +1,194 @@
+"""ctypes binding of libqs (include/qs.h): argument marshalling only.
+
+Every function keeps the C name and forwards to the library; every step of the gate path runs in the HIP
+kernels behind it. PyTorch supplies device memory and streams (``torch.cuda``); it does no state arithmetic.
+The binding fails loudly (ImportError / QSError) when libqs.so is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libqs.so")
+
+QS_OK, QS_EINVAL, QS_ENOMEM, QS_EDEVICE, QS_EUNSUPPORTED = 0, -1, -2, -3, -4
+QS_C128, QS_C64 = 0, 1
+QS_MAX_K, QS_MAX_DIAG_K, QS_MAX_CONTROLS, QS_MAX_QUBITS = 6, 12, 16, 40
+
+_lib = None
+
+
+class QSError(RuntimeError):
+    def __init__(self, code: int, fn: str, msg: str):
+        super().__init__(f"{fn} -> {code}: {msg}")
+        self.code = code
+
+
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_IP = ctypes.POINTER(ctypes.c_int)
+_DP = ctypes.POINTER(ctypes.c_double)
+
+# name -> argtypes (all return int unless listed in _RESTYPES)
+SIGNATURES = {
+    "qs_alloc": [ctypes.POINTER(_P), _I, _I, _P, _P],
+    "qs_free": [_P],
+    "qs_apply_gate": [_P, _IP, _I, _DP],
+    "qs_apply_diag": [_P, _IP, _I, _DP],
+    "qs_apply_controlled": [_P, _IP, _I, _IP, _I, _DP],
+    "qs_fused_swap": [_P, _I, _I, _I],
+    "qs_probs": [_P, _P, _DP],
+    "qs_init_zero": [_P],
+    "qs_copy_in": [_P, _P],
+    "qs_copy_out": [_P, _P],
+    "qs_sync": [_P],
+    "qs_scale": [_P, ctypes.c_double],
+    "qs_norm": [_P, _DP],
+    "qs_renormalize": [_P, _DP],
+    "qs_get_info": [_P, _IP, _IP, ctypes.POINTER(_P), ctypes.POINTER(_P)],
+    "qs_last_error": [],
+    "qs_probe_copy": [_P, _P, ctypes.c_size_t, _P],
+    "qs_probe_rmw": [_P, ctypes.c_size_t, _P],
+    "qs_set_tunable": [ctypes.c_char_p, ctypes.c_int64],
+}
+_RESTYPES = {"qs_last_error": ctypes.c_char_p}
+
+
+def lib():
+    """Load libqs.so (raises ImportError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"libqs.so not found at {LIB_PATH}; run __graft_entry__.build() "
+                              "(python paper_2203_16044_amd/build.py) first")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, args in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = _RESTYPES.get(name, ctypes.c_int)
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, fn: str) -> int:
+    if rc != QS_OK:
+        raise QSError(rc, fn, lib().qs_last_error().decode())
+    return rc
+
+
+def _ints(v: Sequence[int]):
+    v = [int(x) for x in v]
+    return (ctypes.c_int * max(1, len(v)))(*v)
+
+
+def _mat(m, k: int, diag: bool = False) -> np.ndarray:
+    """The matrix (or diagonal) as contiguous complex128, checked against the target count: the C ABI
+    reads exactly 2^k x 2^k (or 2^k) entries from the pointer it is given."""
+    a = np.ascontiguousarray(np.asarray(m, dtype=np.complex128))
+    want = (1 << k,) if diag else (1 << k, 1 << k)
+    if a.shape != want:
+        raise ValueError(f"matrix shape {a.shape} does not match {k} target(s): expected {want}")
+    return a
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(_DP)
+
+
+# ------------------------------------------------------------------------------------------------ C names
+
+def qs_alloc(n: int, dtype: int = QS_C128, dev_buf: Optional[int] = None, hip_stream: Optional[int] = None) -> int:
+    h = _P()
+    _check(lib().qs_alloc(ctypes.byref(h), int(n), int(dtype), dev_buf, hip_stream), "qs_alloc")
+    return h.value
+
+
+def qs_free(h: int) -> None:
+    _check(lib().qs_free(h), "qs_free")
+
+
+def qs_apply_gate(h: int, targets: Sequence[int], U) -> None:
+    U = _mat(U, len(targets))
+    _check(lib().qs_apply_gate(h, _ints(targets), len(targets), _dptr(U.view(np.float64))), "qs_apply_gate")
+
+
+def qs_apply_diag(h: int, targets: Sequence[int], d) -> None:
+    d = _mat(d, len(targets), diag=True)
+    _check(lib().qs_apply_diag(h, _ints(targets), len(targets), _dptr(d.view(np.float64))), "qs_apply_diag")
+
+
+def qs_apply_controlled(h: int, controls: Sequence[int], targets: Sequence[int], U) -> None:
+    U = _mat(U, len(targets))
+    _check(lib().qs_apply_controlled(h, _ints(controls), len(controls), _ints(targets), len(targets),
+                                     _dptr(U.view(np.float64))), "qs_apply_controlled")
+
+
+def qs_fused_swap(h: int, p: int, q: int, s: int) -> None:
+    _check(lib().qs_fused_swap(h, int(p), int(q), int(s)), "qs_fused_swap")
+
+
+def qs_probs(h: int, out_dev: Optional[int] = None, want_norm: bool = False) -> Optional[float]:
+    nrm = ctypes.c_double(0.0)
+    _check(lib().qs_probs(h, out_dev, ctypes.byref(nrm) if want_norm else None), "qs_probs")
+    return nrm.value if want_norm else None
+
+
+def qs_init_zero(h: int) -> None:
+    _check(lib().qs_init_zero(h), "qs_init_zero")
+
+
+def qs_copy_in(h: int, host: np.ndarray) -> None:
+    host = np.ascontiguousarray(host)
+    _check(lib().qs_copy_in(h, host.ctypes.data), "qs_copy_in")
+
+
+def qs_copy_out(h: int, host: np.ndarray) -> None:
+    if not host.flags.c_contiguous:
+        raise ValueError("qs_copy_out needs a C-contiguous array")
+    _check(lib().qs_copy_out(h, host.ctypes.data), "qs_copy_out")
+
+
+def qs_sync(h: int) -> None:
+    _check(lib().qs_sync(h), "qs_sync")
+
+
+def qs_scale(h: int, f: float) -> None:
+    _check(lib().qs_scale(h, float(f)), "qs_scale")
+
+
+def qs_norm(h: int) -> float:
+    v = ctypes.c_double(0.0)
+    _check(lib().qs_norm(h, ctypes.byref(v)), "qs_norm")
+    return v.value
+
+
+def qs_renormalize(h: int, want_norm: bool = False) -> Optional[float]:
+    v = ctypes.c_double(0.0)
+    _check(lib().qs_renormalize(h, ctypes.byref(v) if want_norm else None), "qs_renormalize")
+    return v.value if want_norm else None
+
+
+def qs_get_info(h: int):
+    n, dt, p, s = ctypes.c_int(), ctypes.c_int(), _P(), _P()
+    _check(lib().qs_get_info(h, ctypes.byref(n), ctypes.byref(dt), ctypes.byref(p), ctypes.byref(s)), "qs_get_info")
+    return n.value, dt.value, p.value, s.value
+
+
+def qs_last_error() -> str:
+    return lib().qs_last_error().decode()
+
+
+def qs_probe_copy(dst: int, src: int, nbytes: int, hip_stream: Optional[int] = None) -> None:
+    _check(lib().qs_probe_copy(dst, src, int(nbytes), hip_stream), "qs_probe_copy")
+
+
+def qs_probe_rmw(buf: int, nbytes: int, hip_stream: Optional[int] = None) -> None:
+    _check(lib().qs_probe_rmw(buf, int(nbytes), hip_stream), "qs_probe_rmw")
+
+
+def qs_set_tunable(name: str, value: int) -> None:
+    _check(lib().qs_set_tunable(name.encode(), int(value)), "qs_set_tunable")

@@ -1,0 +1,858 @@
+// Plain gate kernels of libqs for gfx950 (CDNA4, wave64).
+//
+// Every kernel is one in-place pass over the amplitudes it touches (HBM-bound): the gate rule of Sec. II-A,
+// Eq. 4 applied to 2^k-member groups, the fused-swap permutation of Sec. III-D, and the FP64 probability /
+// norm reduction. Group members are located by inserting zero bits at the (sorted) target and control
+// positions of a group counter ("bit insert"); consecutive threads take consecutive counters, so every
+// member stream is a coalesced 16-byte-per-lane stream whenever its bit positions are not the lowest ones.
+#include "qs_internal.h"
+
+namespace {
+
+template <class R> struct CT;
+template <> struct CT<double> { using T = double2; };
+template <> struct CT<float> { using T = float2; };
+
+__device__ __forceinline__ uint64_t ins0(uint64_t g, const InsBits &s)
+{
+    for (int j = 0; j < s.np; ++j) {
+        uint64_t lo = g & s.lowmask[j];
+        g = ((g ^ lo) << 1) | lo;
+    }
+    return g | s.orm;
+}
+
+template <int K> __device__ __forceinline__ uint64_t member_off(int a, const TPos &tp)
+{
+    uint64_t o = 0;
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        o |= (uint64_t)((a >> j) & 1) << tp.tpos[j];
+    return o;
+}
+
+// Loads/stores with an optional non-temporal hint (the nontemporal builtins need native vector types).
+template <class T> struct NativeVec;
+template <> struct NativeVec<double2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct NativeVec<float2> { typedef float type __attribute__((ext_vector_type(2))); };
+
+template <class T> __device__ __forceinline__ T ld(const T *p, int nt)
+{
+    if (!nt)
+        return *p;
+    using N = typename NativeVec<T>::type;
+    const N v = __builtin_nontemporal_load(reinterpret_cast<const N *>(p));
+    T r;
+    r.x = v.x;
+    r.y = v.y;
+    return r;
+}
+template <class T> __device__ __forceinline__ void st(T *p, T v, int nt)
+{
+    if (!nt) {
+        *p = v;
+        return;
+    }
+    using N = typename NativeVec<T>::type;
+    N w;
+    w.x = v.x;
+    w.y = v.y;
+    __builtin_nontemporal_store(w, reinterpret_cast<N *>(p));
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// dense k-qubit gate, k <= 4: the group's 2^k members live in registers; U comes from kernel arguments
+// (k <= 3) or from device memory through uniform (scalar) loads (k = 4).
+// ---------------------------------------------------------------------------------------------------------
+template <class R, int K> struct MatByVal {
+    R v[2 << (2 * K)];
+    __device__ __forceinline__ R re(int i) const { return v[2 * i]; }
+    __device__ __forceinline__ R im(int i) const { return v[2 * i + 1]; }
+};
+template <class R> struct MatByPtr {
+    const R *__restrict__ p;
+    __device__ __forceinline__ R re(int i) const { return p[2 * i]; }
+    __device__ __forceinline__ R im(int i) const { return p[2 * i + 1]; }
+};
+
+template <class R, int K, int G, class MS>
+__global__ __launch_bounds__(256) void k_dense(typename CT<R>::T *__restrict__ psi, uint64_t ngroups, InsBits ins,
+                                               TPos tp, MS ms, int nt)
+{
+    using C2 = typename CT<R>::T;
+    constexpr int D = 1 << K;
+    uint64_t off[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+        off[a] = member_off<K>(a, tp);
+    const uint64_t bs = blockDim.x;
+    const uint64_t stride = (uint64_t)gridDim.x * bs * G;
+    for (uint64_t g0 = (uint64_t)blockIdx.x * bs * G + threadIdx.x; g0 < ngroups; g0 += stride) {
+        C2 x[G][D];
+        uint64_t base[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            uint64_t g = g0 + j * bs;
+            base[j] = ins0(g < ngroups ? g : 0, ins);
+            if (g < ngroups) {
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+                    x[j][a] = ld(psi + base[j] + off[a], nt);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            if (g0 + j * bs < ngroups) {
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    R yr = 0, yi = 0;
+#pragma unroll
+                    for (int b = 0; b < D; ++b) {
+                        const R ur = ms.re(a * D + b), ui = ms.im(a * D + b);
+                        yr = fma(ur, x[j][b].x, yr);
+                        yr = fma(-ui, x[j][b].y, yr);
+                        yi = fma(ur, x[j][b].y, yi);
+                        yi = fma(ui, x[j][b].x, yi);
+                    }
+                    C2 y;
+                    y.x = yr;
+                    y.y = yi;
+                    st(psi + base[j] + off[a], y, nt);
+                }
+            }
+        }
+    }
+}
+
+// dense k = 5, 6 on the vector ALUs: a tile of groups is staged in LDS, each thread forms one output member.
+template <class R, int K>
+__global__ __launch_bounds__(256) void k_dense_lds(typename CT<R>::T *__restrict__ psi, uint64_t ngroups,
+                                                   InsBits ins, TPos tp, const R *__restrict__ U)
+{
+    using C2 = typename CT<R>::T;
+    constexpr int D = 1 << K;
+    constexpr int GPB = 256 / D;  // groups per block
+    __shared__ C2 tile[D][GPB];
+    const int t = threadIdx.x;
+    const int a = t / GPB, gi = t % GPB;
+    const uint64_t oa = member_off<K>(a, tp);
+    for (uint64_t gb = (uint64_t)blockIdx.x * GPB; gb < ngroups; gb += (uint64_t)gridDim.x * GPB) {
+        const uint64_t g = gb + gi;
+        const bool ok = g < ngroups;
+        const uint64_t base = ins0(ok ? g : 0, ins);
+        if (ok)
+            tile[a][gi] = psi[base + oa];
+        __syncthreads();
+        if (ok) {
+            R yr = 0, yi = 0;
+            for (int b = 0; b < D; ++b) {
+                const R ur = U[2 * (a * D + b)], ui = U[2 * (a * D + b) + 1];
+                const C2 xb = tile[b][gi];
+                yr = fma(ur, xb.x, yr);
+                yr = fma(-ui, xb.y, yr);
+                yi = fma(ur, xb.y, yi);
+                yi = fma(ui, xb.x, yi);
+            }
+            C2 y;
+            y.x = yr;
+            y.y = yi;
+            psi[base + oa] = y;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// monomial ("permutation") gates: member a <- phase(a) * member src(a); pure moves, bit-exact.
+// ---------------------------------------------------------------------------------------------------------
+template <class C2> __device__ __forceinline__ C2 apply_phase(C2 x, int ph)
+{
+    C2 y;
+    if (ph == 0) {
+        y = x;
+    } else if (ph == 1) {  // i * x
+        y.x = -x.y;
+        y.y = x.x;
+    } else if (ph == 2) {  // -x
+        y.x = -x.x;
+        y.y = -x.y;
+    } else {  // -i * x
+        y.x = x.y;
+        y.y = -x.x;
+    }
+    return y;
+}
+
+template <class R, int K, int G>
+__global__ __launch_bounds__(256) void k_perm(typename CT<R>::T *__restrict__ psi, uint64_t ngroups, InsBits ins,
+                                              TPos tp, PermTable pt)
+{
+    using C2 = typename CT<R>::T;
+    constexpr int D = 1 << K;
+    const uint64_t bs = blockDim.x;
+    const uint64_t stride = (uint64_t)gridDim.x * bs * G;
+    for (uint64_t g0 = (uint64_t)blockIdx.x * bs * G + threadIdx.x; g0 < ngroups; g0 += stride) {
+        C2 v[G][D];
+        uint64_t base[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            uint64_t g = g0 + j * bs;
+            base[j] = ins0(g < ngroups ? g : 0, ins);
+            if (g < ngroups) {
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+                    if ((pt.moving >> a) & 1)
+                        v[j][a] = psi[base[j] + member_off<K>(pt.src[a], tp)];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            if (g0 + j * bs < ngroups) {
+#pragma unroll
+                for (int a = 0; a < D; ++a)
+                    if ((pt.moving >> a) & 1)
+                        psi[base[j] + member_off<K>(a, tp)] = apply_phase(v[j][a], pt.phase[a]);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// diagonal gates
+// ---------------------------------------------------------------------------------------------------------
+struct DiagSmall {  // k <= 2: entries and classes in kernel arguments (selected, never indexed)
+    double re[4], im[4];
+    int cls[4];  // 0: untouched (entry exactly 1), 1: negate (exactly -1), 2: multiply
+};
+
+template <class R, int K, int G>
+__global__ __launch_bounds__(256) void k_diag_small(typename CT<R>::T *__restrict__ psi, uint64_t dim, DiagArgs da,
+                                                    DiagSmall ds)
+{
+    using C2 = typename CT<R>::T;
+    const uint64_t bs = blockDim.x;
+    const uint64_t stride = (uint64_t)gridDim.x * bs * G;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * bs * G + threadIdx.x; i0 < dim; i0 += stride) {
+        C2 x[G];
+        int cl[G], pa[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const uint64_t i = i0 + j * bs;
+            int a = 0;
+#pragma unroll
+            for (int q = 0; q < K; ++q)
+                a |= (int)((i >> da.t[q]) & 1) << q;
+            pa[j] = a;
+            cl[j] = i < dim ? ds.cls[a] : 0;
+            if (cl[j])
+                x[j] = psi[i];
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            if (!cl[j])
+                continue;
+            const uint64_t i = i0 + j * bs;
+            C2 y;
+            if (cl[j] == 1) {
+                y.x = -x[j].x;
+                y.y = -x[j].y;
+            } else {
+                const R dr = (R)ds.re[pa[j]], di = (R)ds.im[pa[j]];
+                y.x = fma(dr, x[j].x, -di * x[j].y);
+                y.y = fma(dr, x[j].y, di * x[j].x);
+            }
+            psi[i] = y;
+        }
+    }
+}
+
+// k >= 3: the 2^k entries (in the compute precision) and classes come from device memory.
+template <class R>
+__global__ __launch_bounds__(256) void k_diag_table(typename CT<R>::T *__restrict__ psi, uint64_t dim, DiagArgs da,
+                                                    const R *__restrict__ d, const uint8_t *__restrict__ cls)
+{
+    using C2 = typename CT<R>::T;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        int a = 0;
+        for (int q = 0; q < da.k; ++q)
+            a |= (int)((i >> da.t[q]) & 1) << q;
+        const int c = cls[a];
+        if (!c)
+            continue;
+        const C2 x = psi[i];
+        C2 y;
+        if (c == 1) {
+            y.x = -x.x;
+            y.y = -x.y;
+        } else {
+            const R dr = d[2 * a], di = d[2 * a + 1];
+            y.x = fma(dr, x.x, -di * x.y);
+            y.y = fma(dr, x.y, di * x.x);
+        }
+        psi[i] = y;
+    }
+}
+
+struct SparseArgs {
+    int m;
+    DiagSparseEntry e[kMaxSparseDiag];
+};
+
+// Only the subspaces whose pattern has an entry != 1 are visited: blockIdx.y selects the pattern.
+template <class R, int G>
+__global__ __launch_bounds__(256) void k_diag_sparse(typename CT<R>::T *__restrict__ psi, uint64_t nsub,
+                                                     InsBits ins, SparseArgs sa)
+{
+    using C2 = typename CT<R>::T;
+    const DiagSparseEntry &e = sa.e[blockIdx.y];
+    const uint64_t bs = blockDim.x;
+    const uint64_t stride = (uint64_t)gridDim.x * bs * G;
+    for (uint64_t g0 = (uint64_t)blockIdx.x * bs * G + threadIdx.x; g0 < nsub; g0 += stride) {
+        C2 x[G];
+        uint64_t idx[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const uint64_t g = g0 + j * bs;
+            idx[j] = ins0(g < nsub ? g : 0, ins) | e.orm;
+            if (g < nsub)
+                x[j] = psi[idx[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            if (g0 + j * bs >= nsub)
+                continue;
+            C2 y;
+            if (e.cls == 1) {
+                y.x = -x[j].x;
+                y.y = -x[j].y;
+            } else {
+                const R dr = (R)e.re, di = (R)e.im;
+                y.x = fma(dr, x[j].x, -di * x[j].y);
+                y.y = fma(dr, x[j].y, di * x[j].x);
+            }
+            psi[idx[j]] = y;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// fused-swap (Sec. III-D, Listing 1): sigma exchanges bits [lo, lo+s) with [hi, hi+s), lo + s <= hi.
+// Index layout: | top | A = bits [hi, hi+s) | mid | B = bits [lo, lo+s) | e = bits [0, lo) |.
+// ---------------------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t sigma_bits(uint64_t i, int lo, int hi, uint64_t smask)
+{
+    const uint64_t d = ((i >> lo) ^ (i >> hi)) & smask;
+    return i ^ (d << lo) ^ (d << hi);
+}
+
+// Generic form: one thread per index; the member of each moved pair with the smaller index does the swap.
+template <class C2>
+__global__ __launch_bounds__(256) void k_fswap_pairs(C2 *__restrict__ psi, uint64_t dim, int lo, int hi, uint64_t smask)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t j = sigma_bits(i, lo, hi, smask);
+        if (j > i) {
+            const C2 a = psi[i], b = psi[j];
+            psi[i] = b;
+            psi[j] = a;
+        }
+    }
+}
+
+// Run form (2^lo amplitudes per run span at least 256 bytes): thread -> (outer, pair a > b, element e);
+// the runs (A=a, B=b) and (A=b, B=a) are exchanged with coalesced 16-byte lanes along e.
+template <class C2>
+__global__ __launch_bounds__(256) void k_fswap_runs(C2 *__restrict__ psi, uint64_t total, int lo, int hi, int s,
+                                                    uint64_t npairs)
+{
+    const uint64_t E = (uint64_t)1 << lo;
+    const int nmid = hi - lo - s;
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t e = t & (E - 1);
+        const uint64_t r = t >> lo;
+        const uint64_t pr = r % npairs;
+        const uint64_t o = r / npairs;
+        // pr -> (a, b), a > b, pr = a (a - 1) / 2 + b
+        uint64_t a = (uint64_t)((1.0 + sqrt(1.0 + 8.0 * (double)pr)) * 0.5);
+        while (a * (a - 1) / 2 > pr)
+            --a;
+        while ((a + 1) * a / 2 <= pr)
+            ++a;
+        const uint64_t b = pr - a * (a - 1) / 2;
+        const uint64_t mid = o & (((uint64_t)1 << nmid) - 1);
+        const uint64_t top = o >> nmid;
+        const uint64_t common = e | (mid << (lo + s)) | (top << (hi + s));
+        const uint64_t i1 = common | (b << lo) | (a << hi);
+        const uint64_t i2 = common | (a << lo) | (b << hi);
+        const C2 x1 = psi[i1], x2 = psi[i2];
+        psi[i1] = x2;
+        psi[i2] = x1;
+    }
+}
+
+// LDS form (runs shorter than 256 bytes): a workgroup exchanges the sub-tile pair (I, J) / (J, I) of one
+// 2^s x 2^s tile (rows A, contiguous columns B of 2^lo-amplitude runs) through LDS; I == J transposes in
+// place. Rows are read and written as contiguous (B, e) segments.
+template <class C2, int TS>
+__global__ __launch_bounds__(256) void k_fswap_lds(C2 *__restrict__ psi, uint64_t nwork, int lo, int hi, int s,
+                                                   int ntile, uint64_t npairs_t)
+{
+    constexpr int T = 1 << TS;
+    const int E = 1 << lo;
+    const int row = T * E;         // amplitudes per sub-tile row
+    const int rstride = row + 1;   // padded LDS row
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2 *X = reinterpret_cast<C2 *>(smem_raw);
+    C2 *Y = X + (size_t)T * rstride;
+    const int nmid = hi - lo - s;
+    const int nel = T * row;
+    for (uint64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const uint64_t pr = w % npairs_t;
+        const uint64_t o = w / npairs_t;
+        uint64_t I = (uint64_t)((1.0 + sqrt(1.0 + 8.0 * (double)pr)) * 0.5) - 1;  // pr = I (I + 1) / 2 + J, J <= I
+        while (I * (I + 1) / 2 > pr)
+            --I;
+        while ((I + 1) * (I + 2) / 2 <= pr)
+            ++I;
+        const uint64_t J = pr - I * (I + 1) / 2;
+        (void)ntile;
+        const uint64_t mid = o & (((uint64_t)1 << nmid) - 1);
+        const uint64_t top = o >> nmid;
+        const uint64_t common = (mid << (lo + s)) | (top << (hi + s));
+        // X: rows A in I-range, columns B in J-range.  Y: rows A in J-range, columns B in I-range.
+        for (int u = threadIdx.x; u < nel; u += blockDim.x) {
+            const int ra = u / row, rc = u % row;  // rc = cb * E + e
+            const uint64_t cb = rc / E, e = rc % E;
+            const uint64_t ix = common | e | ((J * T + cb) << lo) | ((I * T + ra) << hi);
+            X[ra * rstride + rc] = psi[ix];
+            if (I != J) {
+                const uint64_t iy = common | e | ((I * T + cb) << lo) | ((J * T + ra) << hi);
+                Y[ra * rstride + rc] = psi[iy];
+            }
+        }
+        __syncthreads();
+        for (int u = threadIdx.x; u < nel; u += blockDim.x) {
+            const int ra = u / row, rc = u % row;
+            const int cb = rc / E, e = rc % E;
+            // position (A = I*T + ra, B = J*T + cb) receives the old value at (A = J*T + cb, B = I*T + ra)
+            const uint64_t ix = common | (uint64_t)e | ((J * T + cb) << lo) | ((I * T + ra) << hi);
+            if (I != J) {
+                psi[ix] = Y[cb * rstride + ra * E + e];
+                const uint64_t iy = common | (uint64_t)e | ((I * T + cb) << lo) | ((J * T + ra) << hi);
+                psi[iy] = X[cb * rstride + ra * E + e];
+            } else if (ra != cb) {
+                psi[ix] = X[cb * rstride + ra * E + e];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// probabilities, norm, scale, init
+// ---------------------------------------------------------------------------------------------------------
+__device__ __forceinline__ void kahan_add(double &s, double &c, double v)
+{
+    const double y = v - c;
+    const double t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+// out[i] = |a_i|^2 (FP64); partials[blockIdx.x] = compensated sum of this block's share, reduced in a fixed order.
+template <class R>
+__global__ __launch_bounds__(256) void k_probs(const typename CT<R>::T *__restrict__ psi, uint64_t dim,
+                                               double *__restrict__ out, double *__restrict__ partials)
+{
+    __shared__ double red[256];
+    double s = 0.0, c = 0.0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        const auto x = psi[i];
+        const double re = (double)x.x, im = (double)x.y;
+        const double p = re * re + im * im;
+        if (out)
+            out[i] = p;
+        kahan_add(s, c, p);
+    }
+    red[threadIdx.x] = s - c;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum_partials(const double *__restrict__ partials, int nb,
+                                                      double *__restrict__ result)
+{
+    __shared__ double red[256];
+    double s = 0.0, c = 0.0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x)
+        kahan_add(s, c, partials[i]);
+    red[threadIdx.x] = s - c;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        *result = red[0];
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_scale(typename CT<R>::T *__restrict__ psi, uint64_t dim, double f,
+                                               const double *__restrict__ norm_dev)
+{
+    const double ff = norm_dev ? 1.0 / sqrt(*norm_dev) : f;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        auto x = psi[i];
+        x.x = (R)((double)x.x * ff);
+        x.y = (R)((double)x.y * ff);
+        psi[i] = x;
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_init_zero(typename CT<R>::T *__restrict__ psi, uint64_t dim)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < dim;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        typename CT<R>::T v;
+        v.x = i == 0 ? (R)1 : (R)0;
+        v.y = 0;
+        psi[i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------------------------------------
+// bandwidth probes
+// ---------------------------------------------------------------------------------------------------------
+template <int G>
+__global__ __launch_bounds__(256) void k_probe_copy(double2 *__restrict__ dst, const double2 *__restrict__ src,
+                                                    uint64_t nw)
+{
+    const uint64_t bs = blockDim.x;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * bs * G + threadIdx.x; i0 < nw; i0 += (uint64_t)gridDim.x * bs * G) {
+        double2 v[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if (i0 + j * bs < nw)
+                v[j] = src[i0 + j * bs];
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if (i0 + j * bs < nw)
+                dst[i0 + j * bs] = v[j];
+    }
+}
+
+template <int G>
+__global__ __launch_bounds__(256) void k_probe_rmw(double2 *__restrict__ buf, uint64_t nw)
+{
+    const uint64_t bs = blockDim.x;
+    for (uint64_t i0 = (uint64_t)blockIdx.x * bs * G + threadIdx.x; i0 < nw; i0 += (uint64_t)gridDim.x * bs * G) {
+        double2 v[G];
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if (i0 + j * bs < nw)
+                v[j] = buf[i0 + j * bs];
+#pragma unroll
+        for (int j = 0; j < G; ++j)
+            if (i0 + j * bs < nw) {
+                v[j].x *= 1.0;
+                v[j].y *= 1.0;
+                buf[i0 + j * bs] = v[j];
+            }
+    }
+}
+
+// Grid for a grid-stride loop over `work` items at `per_block` items per block: enough blocks to fill the
+// chip many times over, capped so the total thread count stays far below 2^32.
+unsigned grid_for(uint64_t work, uint64_t per_block)
+{
+    uint64_t b = (work + per_block - 1) / per_block;
+    const uint64_t cap = (uint64_t)1 << 20;
+    if (b > cap)
+        b = cap;
+    if (b == 0)
+        b = 1;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+Tunables &qs_tunables()
+{
+    static Tunables t;
+    return t;
+}
+
+// =============================================================================================================
+// launchers
+// =============================================================================================================
+hipError_t launch_init_zero(int dtype, void *psi, uint64_t dim, hipStream_t s)
+{
+    const unsigned g = grid_for(dim, 256 * 8);
+    if (dtype == QS_C128)
+        hipLaunchKernelGGL(k_init_zero<double>, dim3(g), dim3(256), 0, s, (double2 *)psi, dim);
+    else
+        hipLaunchKernelGGL(k_init_zero<float>, dim3(g), dim3(256), 0, s, (float2 *)psi, dim);
+    return hipGetLastError();
+}
+
+namespace {
+template <class R, int K>
+hipError_t dense_k(void *psi, uint64_t ngroups, const InsBits &ins, const TPos &tp, const double *Uh, const void *Ud,
+                   hipStream_t s)
+{
+    using C2 = typename CT<R>::T;
+    const Tunables &tu = qs_tunables();
+    const int bs = 256;
+    if constexpr (K <= 3) {
+        MatByVal<R, K> m;
+        for (int i = 0; i < (2 << (2 * K)); ++i)
+            m.v[i] = (R)Uh[i];
+        if (K <= 2 && tu.dense_gpt == 4) {
+            hipLaunchKernelGGL((k_dense<R, K, 4, MatByVal<R, K>>), dim3(grid_for(ngroups, bs * 4)), dim3(bs), 0, s,
+                               (C2 *)psi, ngroups, ins, tp, m, tu.nontemporal);
+        } else if (K <= 2 && tu.dense_gpt == 2) {
+            hipLaunchKernelGGL((k_dense<R, K, 2, MatByVal<R, K>>), dim3(grid_for(ngroups, bs * 2)), dim3(bs), 0, s,
+                               (C2 *)psi, ngroups, ins, tp, m, tu.nontemporal);
+        } else {
+            hipLaunchKernelGGL((k_dense<R, K, 1, MatByVal<R, K>>), dim3(grid_for(ngroups, bs)), dim3(bs), 0, s,
+                               (C2 *)psi, ngroups, ins, tp, m, tu.nontemporal);
+        }
+    } else if constexpr (K == 4) {
+        MatByPtr<R> m{(const R *)Ud};
+        hipLaunchKernelGGL((k_dense<R, 4, 1, MatByPtr<R>>), dim3(grid_for(ngroups, bs)), dim3(bs), 0, s, (C2 *)psi,
+                           ngroups, ins, tp, m, tu.nontemporal);
+    } else {
+        constexpr int GPB = 256 / (1 << K);
+        hipLaunchKernelGGL((k_dense_lds<R, K>), dim3(grid_for(ngroups, GPB)), dim3(256), 0, s, (C2 *)psi, ngroups, ins,
+                           tp, (const R *)Ud);
+    }
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t dense_r(int k, void *psi, uint64_t ngroups, const InsBits &ins, const TPos &tp, const double *Uh,
+                   const void *Ud, hipStream_t s)
+{
+    switch (k) {
+    case 1: return dense_k<R, 1>(psi, ngroups, ins, tp, Uh, Ud, s);
+    case 2: return dense_k<R, 2>(psi, ngroups, ins, tp, Uh, Ud, s);
+    case 3: return dense_k<R, 3>(psi, ngroups, ins, tp, Uh, Ud, s);
+    case 4: return dense_k<R, 4>(psi, ngroups, ins, tp, Uh, Ud, s);
+    case 5: return dense_k<R, 5>(psi, ngroups, ins, tp, Uh, Ud, s);
+    case 6: return dense_k<R, 6>(psi, ngroups, ins, tp, Uh, Ud, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <class R, int K>
+hipError_t perm_k(void *psi, uint64_t ngroups, const InsBits &ins, const TPos &tp, const PermTable &pt, hipStream_t s)
+{
+    using C2 = typename CT<R>::T;
+    constexpr int G = K <= 2 ? 2 : 1;
+    hipLaunchKernelGGL((k_perm<R, K, G>), dim3(grid_for(ngroups, 256 * G)), dim3(256), 0, s, (C2 *)psi, ngroups, ins,
+                       tp, pt);
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t perm_r(int k, void *psi, uint64_t ngroups, const InsBits &ins, const TPos &tp, const PermTable &pt,
+                  hipStream_t s)
+{
+    switch (k) {
+    case 1: return perm_k<R, 1>(psi, ngroups, ins, tp, pt, s);
+    case 2: return perm_k<R, 2>(psi, ngroups, ins, tp, pt, s);
+    case 3: return perm_k<R, 3>(psi, ngroups, ins, tp, pt, s);
+    case 4: return perm_k<R, 4>(psi, ngroups, ins, tp, pt, s);
+    case 5: return perm_k<R, 5>(psi, ngroups, ins, tp, pt, s);
+    case 6: return perm_k<R, 6>(psi, ngroups, ins, tp, pt, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
+hipError_t launch_dense(int dtype, int k, void *psi, uint64_t ngroups, const InsBits &ins, const TPos &tp,
+                        const double *U_host_sorted, const void *U_dev, hipStream_t s)
+{
+    return dtype == QS_C128 ? dense_r<double>(k, psi, ngroups, ins, tp, U_host_sorted, U_dev, s)
+                            : dense_r<float>(k, psi, ngroups, ins, tp, U_host_sorted, U_dev, s);
+}
+
+hipError_t launch_perm(int dtype, int k, void *psi, uint64_t ngroups, const InsBits &ins, const TPos &tp,
+                       const PermTable &pt, hipStream_t s)
+{
+    return dtype == QS_C128 ? perm_r<double>(k, psi, ngroups, ins, tp, pt, s)
+                            : perm_r<float>(k, psi, ngroups, ins, tp, pt, s);
+}
+
+hipError_t launch_diag_full(int dtype, void *psi, uint64_t dim, const DiagArgs &da, const double *d_host,
+                            const void *d_dev, const uint8_t *cls_host, const void *cls_dev, hipStream_t s)
+{
+    const int G = 2;
+    if (da.k <= 2) {
+        DiagSmall ds{};
+        for (int a = 0; a < (1 << da.k); ++a) {
+            ds.re[a] = d_host[2 * a];
+            ds.im[a] = d_host[2 * a + 1];
+            ds.cls[a] = cls_host[a];
+        }
+        const unsigned g = grid_for(dim, 256 * G);
+        if (dtype == QS_C128) {
+            if (da.k == 1)
+                hipLaunchKernelGGL((k_diag_small<double, 1, G>), dim3(g), dim3(256), 0, s, (double2 *)psi, dim, da, ds);
+            else
+                hipLaunchKernelGGL((k_diag_small<double, 2, G>), dim3(g), dim3(256), 0, s, (double2 *)psi, dim, da, ds);
+        } else {
+            if (da.k == 1)
+                hipLaunchKernelGGL((k_diag_small<float, 1, G>), dim3(g), dim3(256), 0, s, (float2 *)psi, dim, da, ds);
+            else
+                hipLaunchKernelGGL((k_diag_small<float, 2, G>), dim3(g), dim3(256), 0, s, (float2 *)psi, dim, da, ds);
+        }
+    } else {
+        const unsigned g = grid_for(dim, 256);
+        if (dtype == QS_C128)
+            hipLaunchKernelGGL(k_diag_table<double>, dim3(g), dim3(256), 0, s, (double2 *)psi, dim, da,
+                               (const double *)d_dev, (const uint8_t *)cls_dev);
+        else
+            hipLaunchKernelGGL(k_diag_table<float>, dim3(g), dim3(256), 0, s, (float2 *)psi, dim, da,
+                               (const float *)d_dev, (const uint8_t *)cls_dev);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_diag_sparse(int dtype, void *psi, uint64_t nsub, const InsBits &ins, int m,
+                              const DiagSparseEntry *ent, hipStream_t s)
+{
+    if (m < 1 || m > kMaxSparseDiag)
+        return hipErrorInvalidValue;
+    SparseArgs sa{};
+    sa.m = m;
+    for (int i = 0; i < m; ++i)
+        sa.e[i] = ent[i];
+    const int G = 2;
+    const dim3 grid(grid_for(nsub, 256 * G), m);
+    if (dtype == QS_C128)
+        hipLaunchKernelGGL((k_diag_sparse<double, G>), grid, dim3(256), 0, s, (double2 *)psi, nsub, ins, sa);
+    else
+        hipLaunchKernelGGL((k_diag_sparse<float, G>), grid, dim3(256), 0, s, (float2 *)psi, nsub, ins, sa);
+    return hipGetLastError();
+}
+
+namespace {
+template <class C2>
+hipError_t fswap_t(void *psi_, int n, int lo, int hi, int s_, hipStream_t s)
+{
+    C2 *psi = (C2 *)psi_;
+    const uint64_t dim = (uint64_t)1 << n;
+    const int sz = (int)sizeof(C2);
+    const uint64_t smask = ((uint64_t)1 << s_) - 1;
+    const int run_bytes = (1 << lo) * sz;
+    if (run_bytes >= 256) {
+        const uint64_t S = (uint64_t)1 << s_;
+        const uint64_t npairs = S * (S - 1) / 2;
+        const uint64_t outer = (uint64_t)1 << (n - 2 * s_ - lo);
+        const uint64_t total = outer * npairs * ((uint64_t)1 << lo);
+        hipLaunchKernelGGL(k_fswap_runs<C2>, dim3(grid_for(total, 256)), dim3(256), 0, s, psi, total, lo, hi, s_,
+                           npairs);
+        return hipGetLastError();
+    }
+    // LDS sub-tiles: largest T = 2^ts <= 2^s with T*T*2^lo amplitudes <= 16 KiB per tile
+    int ts = s_;
+    while (ts > 0 && ((size_t)1 << (2 * ts + lo)) * sz > 16384)
+        --ts;
+    if ((1 << (ts + lo)) * sz >= 256 && ts >= 2) {
+        const int T = 1 << ts;
+        const int ntile = 1 << (s_ - ts);
+        const uint64_t npt = (uint64_t)ntile * (ntile + 1) / 2;
+        const uint64_t outer = (uint64_t)1 << (n - 2 * s_ - lo);
+        const uint64_t nwork = outer * npt;
+        const size_t shm = 2 * (size_t)T * (T * (1 << lo) + 1) * sz;
+        const unsigned g = (unsigned)(nwork < (1u << 20) ? nwork : (1u << 20));
+        switch (ts) {
+        case 2: hipLaunchKernelGGL((k_fswap_lds<C2, 2>), dim3(g), dim3(256), shm, s, psi, nwork, lo, hi, s_, ntile, npt); break;
+        case 3: hipLaunchKernelGGL((k_fswap_lds<C2, 3>), dim3(g), dim3(256), shm, s, psi, nwork, lo, hi, s_, ntile, npt); break;
+        case 4: hipLaunchKernelGGL((k_fswap_lds<C2, 4>), dim3(g), dim3(256), shm, s, psi, nwork, lo, hi, s_, ntile, npt); break;
+        default: hipLaunchKernelGGL((k_fswap_lds<C2, 5>), dim3(g), dim3(256), shm, s, psi, nwork, lo, hi, s_, ntile, npt); break;
+        }
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_fswap_pairs<C2>, dim3(grid_for(dim, 256)), dim3(256), 0, s, psi, dim, lo, hi, smask);
+    return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_fused_swap(int dtype, void *psi, int n, int lo, int hi, int s_, hipStream_t s)
+{
+    return dtype == QS_C128 ? fswap_t<double2>(psi, n, lo, hi, s_, s) : fswap_t<float2>(psi, n, lo, hi, s_, s);
+}
+
+int probs_blocks(uint64_t dim)
+{
+    uint64_t b = (dim + 256 * 16 - 1) / (256 * 16);
+    if (b > 4096)
+        b = 4096;
+    return (int)(b ? b : 1);
+}
+
+hipError_t launch_probs(int dtype, const void *psi, uint64_t dim, double *out, double *partials, int nblocks,
+                        double *result, hipStream_t s)
+{
+    if (dtype == QS_C128)
+        hipLaunchKernelGGL(k_probs<double>, dim3(nblocks), dim3(256), 0, s, (const double2 *)psi, dim, out, partials);
+    else
+        hipLaunchKernelGGL(k_probs<float>, dim3(nblocks), dim3(256), 0, s, (const float2 *)psi, dim, out, partials);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, (const double *)partials, nblocks, result);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(int dtype, void *psi, uint64_t dim, double f, hipStream_t s)
+{
+    const unsigned g = grid_for(dim, 256 * 4);
+    if (dtype == QS_C128)
+        hipLaunchKernelGGL(k_scale<double>, dim3(g), dim3(256), 0, s, (double2 *)psi, dim, f, (const double *)nullptr);
+    else
+        hipLaunchKernelGGL(k_scale<float>, dim3(g), dim3(256), 0, s, (float2 *)psi, dim, f, (const double *)nullptr);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale_dev(int dtype, void *psi, uint64_t dim, const double *norm_dev, hipStream_t s)
+{
+    const unsigned g = grid_for(dim, 256 * 4);
+    if (dtype == QS_C128)
+        hipLaunchKernelGGL(k_scale<double>, dim3(g), dim3(256), 0, s, (double2 *)psi, dim, 0.0, norm_dev);
+    else
+        hipLaunchKernelGGL(k_scale<float>, dim3(g), dim3(256), 0, s, (float2 *)psi, dim, 0.0, norm_dev);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_copy(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    const uint64_t nw = bytes / 16;
+    constexpr int G = 4;
+    hipLaunchKernelGGL(k_probe_copy<G>, dim3(grid_for(nw, 256 * G)), dim3(256), 0, s, (double2 *)dst,
+                       (const double2 *)src, nw);
+    return hipGetLastError();
+}
+
+hipError_t launch_probe_rmw(void *buf, size_t bytes, hipStream_t s)
+{
+    const uint64_t nw = bytes / 16;
+    constexpr int G = 4;
+    hipLaunchKernelGGL(k_probe_rmw<G>, dim3(grid_for(nw, 256 * G)), dim3(256), 0, s, (double2 *)buf, nw);
+    return hipGetLastError();
+}

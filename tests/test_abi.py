@@ -1,0 +1,80 @@
+"""The C-ABI library loads, exports every symbol include/qs.h declares, and validates without a GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2203_16044_amd as qs
+from paper_2203_16044_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for fn in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"QS_API\s+[\w\s\*]+?\b(qs_\w+)\s*\(", txt))
+    return names
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for core in ("qs_alloc", "qs_free", "qs_apply_gate", "qs_apply_diag", "qs_apply_controlled", "qs_fused_swap",
+                 "qs_probs"):
+        assert core in names
+
+
+def test_every_declared_symbol_is_exported():
+    L = ctypes.CDLL(B.LIB_PATH)
+    missing = [n for n in sorted(_declared()) if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_declared_symbol():
+    assert _declared() <= set(B.SIGNATURES)
+
+
+def test_null_handles_are_rejected_without_device_work():
+    L = B.lib()
+    one = (ctypes.c_int * 1)(0)
+    U = (ctypes.c_double * 8)(*([0.0] * 8))
+    assert L.qs_apply_gate(None, one, 1, U) == B.QS_EINVAL
+    assert L.qs_apply_diag(None, one, 1, U) == B.QS_EINVAL
+    assert L.qs_apply_controlled(None, one, 1, one, 1, U) == B.QS_EINVAL
+    assert L.qs_fused_swap(None, 0, 1, 1) == B.QS_EINVAL
+    assert L.qs_probs(None, None, None) == B.QS_EINVAL
+    assert L.qs_free(None) == B.QS_EINVAL
+    assert "NULL" in qs.qs_last_error()
+
+
+@pytest.mark.parametrize("n,dtype", [(0, 0), (41, 0), (4, 2), (4, -1)])
+def test_alloc_validates_arguments_first(n, dtype):
+    h = ctypes.c_void_p()
+    assert B.lib().qs_alloc(ctypes.byref(h), n, dtype, None, None) == B.QS_EINVAL
+    assert h.value is None
+
+
+def test_alloc_rejects_misaligned_buffer():
+    h = ctypes.c_void_p()
+    assert B.lib().qs_alloc(ctypes.byref(h), 4, 0, ctypes.c_void_p(0x1008), None) == B.QS_EINVAL
+
+
+def test_tunables_validate():
+    with pytest.raises(qs.QSError):
+        B.qs_set_tunable("no_such_knob", 1)
+    with pytest.raises(qs.QSError):
+        B.qs_set_tunable("dense_gpt", 3)
+    B.qs_set_tunable("dense_gpt", 2)
+
+
+def test_binding_rejects_matrix_shape_mismatch():
+    import numpy as np
+    with pytest.raises(ValueError):
+        B.qs_apply_gate(1, (0, 1), np.eye(2))
+    with pytest.raises(ValueError):
+        B.qs_apply_diag(1, (0,), np.ones(4))
+    with pytest.raises(ValueError):
+        B.qs_apply_controlled(1, (0,), (1, 2), np.eye(2))

@@ -339,3 +339,13 @@ def test_config_shapes():
     assert c3.n == 33 and len(c3) == 40 * (16 + 33) and c3.renorm_after == (10, 20, 30, 40)
     b = C.config4(count=16)
     assert all(10 <= c.n <= 22 for c in b)
+
+
+def test_oracle_rejects_matrix_shape_mismatch():
+    psi = C.random_state(4, 0)
+    with pytest.raises(ValueError):
+        oracle.apply_dense(psi, [0, 1], np.eye(2))
+    with pytest.raises(ValueError):
+        oracle.apply_controlled(psi, [2], [0, 1], np.eye(2))
+    with pytest.raises(ValueError):
+        oracle.apply_diag(psi, [0], np.ones(4))
