@@ -147,13 +147,14 @@ QS_API const char *qs_last_error(void);
 
 /* dst[i] = src[i] over `bytes` (multiple of 16, both 16-byte aligned), enqueued on hip_stream. */
 QS_API int qs_probe_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
-/* In-place read-modify-write of every 16-byte word of buf (x <- x * 1.0 per double): the traffic pattern of
- * an in-place gate pass with no arithmetic dependence between words. */
+/* In-place read-modify-write of every 16-byte word of buf (each double multiplied by a runtime factor of 1.0,
+ * so the stores are real): the traffic pattern of an in-place gate pass without its arithmetic. */
 QS_API int qs_probe_rmw(void *buf, size_t bytes, void *hip_stream);
 
 /* ---- launch tunables (autotuner / sweeps) ----
- * "dense_gpt"   groups per thread of the 1- and 2-qubit dense kernels: 1, 2 or 4 (default 2);
- * "nontemporal" 0/1: non-temporal loads and stores in the dense kernels (default 0).
+ * "dense_gpt"   groups per thread of the 1- and 2-qubit dense kernels: 1, 2 or 4 (default 1);
+ * "nontemporal" 0/1: non-temporal loads and stores in the dense kernels (default 1);
+ * "mfma_wg_per_cu" persistent workgroups per compute unit of the k = 5, 6 MFMA block kernel (1..16, default 2).
  * Process-wide; affects launches enqueued after the call. QS_EINVAL for an unknown name or value. */
 QS_API int qs_set_tunable(const char *name, int64_t value);
 

@@ -621,6 +621,10 @@ QS_API int qs_set_tunable(const char *name, int64_t value)
         t.dense_gpt = (int)value;
     } else if (!std::strcmp(name, "nontemporal")) {
         t.nontemporal = value ? 1 : 0;
+    } else if (!std::strcmp(name, "mfma_wg_per_cu")) {
+        if (value < 1 || value > 16)
+            return qs_fail(QS_EINVAL, "mfma_wg_per_cu must be in [1, 16]");
+        t.mfma_wg_per_cu = (int)value;
     } else {
         return qs_fail(QS_EINVAL, "qs_set_tunable: unknown tunable '%s'", name);
     }

@@ -81,6 +81,8 @@ struct PermTable {
 hipError_t launch_init_zero(int dtype, void *psi, uint64_t dim, hipStream_t s);
 hipError_t launch_dense(int dtype, int k, void *psi, uint64_t ngroups, const InsBits &ins, const TPos &tp,
                         const double *U_host_sorted, const void *U_dev, hipStream_t s);
+hipError_t launch_dense_mfma(int dtype, int k, void *psi, uint64_t ngroups, const InsBits &ins, const TPos &tp,
+                             const void *U_dev, hipStream_t s);
 hipError_t launch_perm(int dtype, int k, void *psi, uint64_t ngroups, const InsBits &ins, const TPos &tp,
                        const PermTable &pt, hipStream_t s);
 
@@ -112,9 +114,8 @@ hipError_t launch_probe_rmw(void *buf, size_t bytes, hipStream_t s);
 
 // tunables (set through qs_set_option-like hooks in tests / autotuner)
 struct Tunables {
-    int dense_block = 256;   // threads per block for group kernels
-    int dense_gpt = 2;       // groups per thread for k = 1, 2
-    int stream_gpt = 4;      // 16-byte words per thread for the streaming probes
-    int nontemporal = 0;     // use non-temporal loads/stores in the plain gate kernels
+    int dense_gpt = 1;       // groups per thread for k = 1, 2
+    int nontemporal = 1;     // use non-temporal loads/stores in the plain gate kernels
+    int mfma_wg_per_cu = 2;  // persistent workgroups per CU for the MFMA block kernel
 };
 Tunables &qs_tunables();

@@ -7,6 +7,8 @@
 // member stream is a coalesced 16-byte-per-lane stream whenever its bit positions are not the lowest ones.
 #include "qs_internal.h"
 
+#include <type_traits>
+
 namespace {
 
 template <class R> struct CT;
@@ -124,44 +126,6 @@ __global__ __launch_bounds__(256) void k_dense(typename CT<R>::T *__restrict__ p
     }
 }
 
-// dense k = 5, 6 on the vector ALUs: a tile of groups is staged in LDS, each thread forms one output member.
-template <class R, int K>
-__global__ __launch_bounds__(256) void k_dense_lds(typename CT<R>::T *__restrict__ psi, uint64_t ngroups,
-                                                   InsBits ins, TPos tp, const R *__restrict__ U)
-{
-    using C2 = typename CT<R>::T;
-    constexpr int D = 1 << K;
-    constexpr int GPB = 256 / D;  // groups per block
-    __shared__ C2 tile[D][GPB];
-    const int t = threadIdx.x;
-    const int a = t / GPB, gi = t % GPB;
-    const uint64_t oa = member_off<K>(a, tp);
-    for (uint64_t gb = (uint64_t)blockIdx.x * GPB; gb < ngroups; gb += (uint64_t)gridDim.x * GPB) {
-        const uint64_t g = gb + gi;
-        const bool ok = g < ngroups;
-        const uint64_t base = ins0(ok ? g : 0, ins);
-        if (ok)
-            tile[a][gi] = psi[base + oa];
-        __syncthreads();
-        if (ok) {
-            R yr = 0, yi = 0;
-            for (int b = 0; b < D; ++b) {
-                const R ur = U[2 * (a * D + b)], ui = U[2 * (a * D + b) + 1];
-                const C2 xb = tile[b][gi];
-                yr = fma(ur, xb.x, yr);
-                yr = fma(-ui, xb.y, yr);
-                yi = fma(ur, xb.y, yi);
-                yi = fma(ui, xb.x, yi);
-            }
-            C2 y;
-            y.x = yr;
-            y.y = yi;
-            psi[base + oa] = y;
-        }
-        __syncthreads();
-    }
-}
-
 // ---------------------------------------------------------------------------------------------------------
 // monomial ("permutation") gates: member a <- phase(a) * member src(a); pure moves, bit-exact.
 // ---------------------------------------------------------------------------------------------------------
@@ -185,7 +149,7 @@ template <class C2> __device__ __forceinline__ C2 apply_phase(C2 x, int ph)
 
 template <class R, int K, int G>
 __global__ __launch_bounds__(256) void k_perm(typename CT<R>::T *__restrict__ psi, uint64_t ngroups, InsBits ins,
-                                              TPos tp, PermTable pt)
+                                              TPos tp, PermTable pt, int nt)
 {
     using C2 = typename CT<R>::T;
     constexpr int D = 1 << K;
@@ -202,7 +166,7 @@ __global__ __launch_bounds__(256) void k_perm(typename CT<R>::T *__restrict__ ps
 #pragma unroll
                 for (int a = 0; a < D; ++a)
                     if ((pt.moving >> a) & 1)
-                        v[j][a] = psi[base[j] + member_off<K>(pt.src[a], tp)];
+                        v[j][a] = ld(psi + base[j] + member_off<K>(pt.src[a], tp), nt);
             }
         }
 #pragma unroll
@@ -211,7 +175,7 @@ __global__ __launch_bounds__(256) void k_perm(typename CT<R>::T *__restrict__ ps
 #pragma unroll
                 for (int a = 0; a < D; ++a)
                     if ((pt.moving >> a) & 1)
-                        psi[base[j] + member_off<K>(a, tp)] = apply_phase(v[j][a], pt.phase[a]);
+                        st(psi + base[j] + member_off<K>(a, tp), apply_phase(v[j][a], pt.phase[a]), nt);
             }
         }
     }
@@ -245,7 +209,7 @@ __global__ __launch_bounds__(256) void k_diag_small(typename CT<R>::T *__restric
             pa[j] = a;
             cl[j] = i < dim ? ds.cls[a] : 0;
             if (cl[j])
-                x[j] = psi[i];
+                x[j] = ld(psi + i, 1);
         }
 #pragma unroll
         for (int j = 0; j < G; ++j) {
@@ -261,7 +225,7 @@ __global__ __launch_bounds__(256) void k_diag_small(typename CT<R>::T *__restric
                 y.x = fma(dr, x[j].x, -di * x[j].y);
                 y.y = fma(dr, x[j].y, di * x[j].x);
             }
-            psi[i] = y;
+            st(psi + i, y, 1);
         }
     }
 }
@@ -316,7 +280,7 @@ __global__ __launch_bounds__(256) void k_diag_sparse(typename CT<R>::T *__restri
             const uint64_t g = g0 + j * bs;
             idx[j] = ins0(g < nsub ? g : 0, ins) | e.orm;
             if (g < nsub)
-                x[j] = psi[idx[j]];
+                x[j] = ld(psi + idx[j], 1);
         }
 #pragma unroll
         for (int j = 0; j < G; ++j) {
@@ -331,7 +295,7 @@ __global__ __launch_bounds__(256) void k_diag_sparse(typename CT<R>::T *__restri
                 y.x = fma(dr, x[j].x, -di * x[j].y);
                 y.y = fma(dr, x[j].y, di * x[j].x);
             }
-            psi[idx[j]] = y;
+            st(psi + idx[j], y, 1);
         }
     }
 }
@@ -554,32 +518,25 @@ __global__ __launch_bounds__(256) void k_probe_copy(double2 *__restrict__ dst, c
     }
 }
 
-template <int G>
-__global__ __launch_bounds__(256) void k_probe_rmw(double2 *__restrict__ buf, uint64_t nw)
+// In-place pass: every 16-byte word is read, scaled by a runtime factor and written back (one word per thread,
+// non-temporal), the access pattern of a gate pass with the arithmetic removed.
+__global__ __launch_bounds__(256) void k_probe_rmw(double2 *__restrict__ buf, uint64_t nw, double f)
 {
-    const uint64_t bs = blockDim.x;
-    for (uint64_t i0 = (uint64_t)blockIdx.x * bs * G + threadIdx.x; i0 < nw; i0 += (uint64_t)gridDim.x * bs * G) {
-        double2 v[G];
-#pragma unroll
-        for (int j = 0; j < G; ++j)
-            if (i0 + j * bs < nw)
-                v[j] = buf[i0 + j * bs];
-#pragma unroll
-        for (int j = 0; j < G; ++j)
-            if (i0 + j * bs < nw) {
-                v[j].x *= 1.0;
-                v[j].y *= 1.0;
-                buf[i0 + j * bs] = v[j];
-            }
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += (uint64_t)gridDim.x * blockDim.x) {
+        double2 v = ld(buf + i, 1);
+        v.x *= f;
+        v.y *= f;
+        st(buf + i, v, 1);
     }
 }
 
-// Grid for a grid-stride loop over `work` items at `per_block` items per block: enough blocks to fill the
-// chip many times over, capped so the total thread count stays far below 2^32.
+// Grid for a grid-stride loop over `work` items at `per_block` items per block. Streaming gate kernels run best
+// with one item per thread and a grid that covers the work in a single sweep; the cap keeps the total thread
+// count at or below 2^31 (the grid-stride loop covers anything larger).
 unsigned grid_for(uint64_t work, uint64_t per_block)
 {
     uint64_t b = (work + per_block - 1) / per_block;
-    const uint64_t cap = (uint64_t)1 << 20;
+    const uint64_t cap = (uint64_t)1 << 23;
     if (b > cap)
         b = cap;
     if (b == 0)
@@ -609,12 +566,24 @@ hipError_t launch_init_zero(int dtype, void *psi, uint64_t dim, hipStream_t s)
 }
 
 namespace {
+// Non-temporal accesses help streams of whole cache lines; when a target sits inside a 128-byte line the
+// members of a group share lines across load instructions, so the loads go through the cache instead.
+template <class R> int nt_for(const TPos &tp, int k)
+{
+    const int line_bits = sizeof(typename CT<R>::T) == 16 ? 3 : 4;
+    for (int j = 0; j < k; ++j)
+        if (tp.tpos[j] < line_bits)
+            return 0;
+    return qs_tunables().nontemporal;
+}
+
 template <class R, int K>
 hipError_t dense_k(void *psi, uint64_t ngroups, const InsBits &ins, const TPos &tp, const double *Uh, const void *Ud,
                    hipStream_t s)
 {
     using C2 = typename CT<R>::T;
-    const Tunables &tu = qs_tunables();
+    Tunables tu = qs_tunables();
+    tu.nontemporal = nt_for<R>(tp, K);
     const int bs = 256;
     if constexpr (K <= 3) {
         MatByVal<R, K> m;
@@ -635,9 +604,7 @@ hipError_t dense_k(void *psi, uint64_t ngroups, const InsBits &ins, const TPos &
         hipLaunchKernelGGL((k_dense<R, 4, 1, MatByPtr<R>>), dim3(grid_for(ngroups, bs)), dim3(bs), 0, s, (C2 *)psi,
                            ngroups, ins, tp, m, tu.nontemporal);
     } else {
-        constexpr int GPB = 256 / (1 << K);
-        hipLaunchKernelGGL((k_dense_lds<R, K>), dim3(grid_for(ngroups, GPB)), dim3(256), 0, s, (C2 *)psi, ngroups, ins,
-                           tp, (const R *)Ud);
+        return launch_dense_mfma(std::is_same<R, double>::value ? QS_C128 : QS_C64, K, psi, ngroups, ins, tp, Ud, s);
     }
     return hipGetLastError();
 }
@@ -661,9 +628,9 @@ template <class R, int K>
 hipError_t perm_k(void *psi, uint64_t ngroups, const InsBits &ins, const TPos &tp, const PermTable &pt, hipStream_t s)
 {
     using C2 = typename CT<R>::T;
-    constexpr int G = K <= 2 ? 2 : 1;
+    constexpr int G = 1;
     hipLaunchKernelGGL((k_perm<R, K, G>), dim3(grid_for(ngroups, 256 * G)), dim3(256), 0, s, (C2 *)psi, ngroups, ins,
-                       tp, pt);
+                       tp, pt, nt_for<R>(tp, K));
     return hipGetLastError();
 }
 
@@ -700,7 +667,7 @@ hipError_t launch_perm(int dtype, int k, void *psi, uint64_t ngroups, const InsB
 hipError_t launch_diag_full(int dtype, void *psi, uint64_t dim, const DiagArgs &da, const double *d_host,
                             const void *d_dev, const uint8_t *cls_host, const void *cls_dev, hipStream_t s)
 {
-    const int G = 2;
+    const int G = 1;
     if (da.k <= 2) {
         DiagSmall ds{};
         for (int a = 0; a < (1 << da.k); ++a) {
@@ -741,7 +708,7 @@ hipError_t launch_diag_sparse(int dtype, void *psi, uint64_t nsub, const InsBits
     sa.m = m;
     for (int i = 0; i < m; ++i)
         sa.e[i] = ent[i];
-    const int G = 2;
+    const int G = 1;
     const dim3 grid(grid_for(nsub, 256 * G), m);
     if (dtype == QS_C128)
         hipLaunchKernelGGL((k_diag_sparse<double, G>), grid, dim3(256), 0, s, (double2 *)psi, nsub, ins, sa);
@@ -772,7 +739,7 @@ hipError_t fswap_t(void *psi_, int n, int lo, int hi, int s_, hipStream_t s)
     int ts = s_;
     while (ts > 0 && ((size_t)1 << (2 * ts + lo)) * sz > 16384)
         --ts;
-    if ((1 << (ts + lo)) * sz >= 256 && ts >= 2) {
+    if ((1 << (ts + lo)) * sz >= 128 && ts >= 2) {
         const int T = 1 << ts;
         const int ntile = 1 << (s_ - ts);
         const uint64_t npt = (uint64_t)ntile * (ntile + 1) / 2;
@@ -852,7 +819,6 @@ hipError_t launch_probe_copy(void *dst, const void *src, size_t bytes, hipStream
 hipError_t launch_probe_rmw(void *buf, size_t bytes, hipStream_t s)
 {
     const uint64_t nw = bytes / 16;
-    constexpr int G = 4;
-    hipLaunchKernelGGL(k_probe_rmw<G>, dim3(grid_for(nw, 256 * G)), dim3(256), 0, s, (double2 *)buf, nw);
+    hipLaunchKernelGGL(k_probe_rmw, dim3(grid_for(nw, 256)), dim3(256), 0, s, (double2 *)buf, nw, 1.0);
     return hipGetLastError();
 }

@@ -67,7 +67,7 @@ def test_tunables_validate():
         B.qs_set_tunable("no_such_knob", 1)
     with pytest.raises(qs.QSError):
         B.qs_set_tunable("dense_gpt", 3)
-    B.qs_set_tunable("dense_gpt", 2)
+    B.qs_set_tunable("dense_gpt", 1)
 
 
 def test_binding_rejects_matrix_shape_mismatch():
