@@ -48,13 +48,57 @@ def _kernel_class(op):
     return op.kind
 
 
-def run_plain(st, ops, events, torch):
+def run_plain(st, ops, events):
     """Apply ops one at a time; events[i] = (start, end) recorded around op i on the state's stream."""
     s = st.stream
     for i, op in enumerate(ops):
         events[i][0].record(s)
         st.apply_op(op)
         events[i][1].record(s)
+
+
+def run_plan(st, plan, npass, events):
+    s = st.stream
+    for i in range(npass):
+        events[i][0].record(s)
+        plan.run(st, i, i + 1)
+        events[i][1].record(s)
+
+
+def time_steps(st, steps, warmup, body, units, torch):
+    """Warm up, then time `steps` steps of reset + body + FP64 probability reduction. body(record) enqueues the
+    work; with record=True it records a (start, end) event pair around every launch unit. Returns
+    (per-step seconds, {class: [seconds, launches, alg_bytes]})."""
+    import paper_2203_16044_amd as qs
+    mk = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    events = [(mk(), mk()) for _ in units]
+    e0, e1 = mk(), mk()
+    for _ in range(warmup):
+        st.init_zero()
+        body(None)
+        qs.binding.qs_probs(st.h, None, False)
+    torch.cuda.synchronize()
+    times, per = [], {}
+    for _ in range(steps):
+        e0.record(st.stream)
+        st.init_zero()
+        body(events)
+        qs.binding.qs_probs(st.h, None, False)
+        e1.record(st.stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+        for (cls, nbytes), (a, b) in zip(units, events):
+            c = per.setdefault(cls, [0.0, 0, 0])
+            c[0] += a.elapsed_time(b) / 1e3
+            c[1] += 1
+            c[2] += nbytes
+    torch.cuda.synchronize()
+    return times, per
+
+
+def summarize(per, steps):
+    return {c: {"launches": v[1] // steps, "avg_ms": v[0] / v[1] * 1e3, "tbs": v[2] / v[0] / 1e12}
+            for c, v in sorted(per.items())}
 
 
 def cpu_baseline(circ, budget_s, torch):
@@ -93,11 +137,15 @@ def cpu_baseline(circ, budget_s, torch):
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=32)
     ap.add_argument("--layers", type=int, default=40)
-    ap.add_argument("--mode", choices=["plain", "tuned"], default="plain")
+    ap.add_argument("--mode", choices=["plain", "tuned"], default="tuned")
+    ap.add_argument("--block-bits", type=int, default=12)
+    ap.add_argument("--low-bits", type=int, default=4)
+    ap.add_argument("--plain-layers", type=int, default=4, help="layers of the circuit timed on the plain path")
+    ap.add_argument("--compare-fuse", type=int, nargs="*", default=[4, 6], help="fused-dense plans also timed")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -112,53 +160,61 @@ def main():
     import paper_2203_16044_amd as qs
 
     torch.cuda.set_device(0)
+    from paper_2203_16044_amd.plan import Circuit, Plan
+
     circ = C.config2(n=args.n, seed=32, layers=args.layers)
     ops = circ.ops
     n = circ.n
+    gates = len(ops)
+    full = 2 * 16 * (1 << n)
     st = qs.State(n, "c128")
-    mk = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-    events = [(mk(), mk()) for _ in ops]
-    step_ev = (mk(), mk())
+    t_wall = time.perf_counter()
 
-    def step(record):
-        st.init_zero()
-        if record:
-            run_plain(st, ops, events, torch)
-        else:
-            for op in ops:
-                st.apply_op(op)
-        return qs.binding.qs_probs(st.h, None, False)
+    # plain: one pass per gate (on a prefix of the circuit in tuned mode: the per-gate rate is layer-invariant)
+    plain_ops = ops if args.mode == "plain" else [o for o in ops if o.layer <= args.plain_layers]
+    units = [(_kernel_class(o), _alg_bytes(o, n, 16)) for o in plain_ops]
+    p_times, p_per = time_steps(st, args.steps if args.mode == "plain" else 1,
+                                args.warmup if args.mode == "plain" else 0,
+                                lambda ev: run_plain(st, plain_ops, ev) if ev else [st.apply_op(o) for o in plain_ops],
+                                units, torch)
+    plain_rate = len(plain_ops) / (sum(p_times) / len(p_times))
 
-    for _ in range(args.warmup):
-        step(False)
-    torch.cuda.synchronize()
-    step_times, per_class = [], {}
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step_ev[0].record(st.stream)
-        step(True)
-        step_ev[1].record(st.stream)
-        step_ev[1].synchronize()
-        step_times.append(step_ev[0].elapsed_time(step_ev[1]) / 1e3)
-        for op, (e0, e1) in zip(ops, events):
-            c = per_class.setdefault(_kernel_class(op), [0.0, 0, 0])
-            c[0] += e0.elapsed_time(e1) / 1e3
-            c[1] += 1
-            c[2] += _alg_bytes(op, n, 16)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    results = {}
+    if args.mode == "tuned":
+        cc = Circuit.from_ops(n, ops)
+        variants = [("block", args.block_bits, args.low_bits)] + [("fuse", k, 0) for k in args.compare_fuse]
+        for mode, bits, low in variants:
+            plan = Plan(cc, mode, bits, low, "c128")
+            info = plan.info()
+            passes = plan.passes()
+            kinds = {0: f"block_b{bits}", 1: "dense_k{}", 2: "fswap", 3: "other"}
+            units = [(kinds[ps["type"]].format(ps["nqubits"]),
+                      int(full * (1 - 2.0 ** -(ps["nqubits"] // 2))) if ps["type"] == 2 else full) for ps in passes]
+            main = mode == "block"
+            times, per = time_steps(st, args.steps if main else 1, args.warmup if main else 1,
+                                    lambda ev, plan=plan, npass=len(passes): run_plan(st, plan, npass, ev) if ev
+                                    else plan.run(st), units, torch)
+            results[f"{mode}{bits}" + (f"_low{low}" if main else "")] = {
+                "passes": info["passes"], "gates_per_s": gates / (sum(times) / len(times)),
+                "ms_per_step": sum(times) / len(times) * 1e3, "per_kernel": summarize(per, len(times)),
+                "_times": times, "_per": per}
+            plan.close()
+        cc.close()
+        head = results[f"block{args.block_bits}_low{args.low_bits}"]
+        step_times, per_class = head["_times"], head["_per"]
+    else:
+        step_times, per_class = p_times, p_per
     nrm = st.norm()
     st.close()
+    wall = time.perf_counter() - t_wall
 
     t_step = sum(step_times) / len(step_times)
-    gates = len(ops)
     dom = max(per_class, key=lambda c: per_class[c][0])
     tsum, cnt, bsum = per_class[dom]
     avg = tsum / cnt
     achieved = (bsum / cnt) / avg / 1e12
-    alg_total = sum(_alg_bytes(o, n, 16) for o in ops)
     out = {
-        "metric": "gates/s, 32-qubit complex128 random circuit (SU(4) pairings + U3, 40 layers)",
+        "metric": "gates/s, 32-qubit complex128 random circuit (SU(4) pairings + U3, 40 layers); tuned vs plain",
         "value": gates / t_step,
         "unit": "gates/s",
         "n_gpus": 1,
@@ -171,15 +227,20 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"random SU(4)+U3 circuit, n={n}, {args.layers} layers, {gates} gates, complex128 "
-                               f"(seed 32)", "n": n, "gates": gates, "mode": args.mode, "parallelism": "none"},
+                               f"(seed 32)", "n": n, "gates": gates, "mode": args.mode,
+                   "plan": (f"LDS block passes, {args.block_bits} local qubits incl. the {args.low_bits} lowest"
+                            if args.mode == "tuned" else "one pass per gate"),
+                   "parallelism": "none"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_TBS, "unit": "TB/s",
                      "frac": achieved / HBM_PEAK_TBS, "traffic": None, "kernel": dom,
-                     "avg_launch_ms": avg * 1e3, "launches_per_step": cnt // args.steps,
+                     "avg_launch_ms": avg * 1e3, "launches_per_step": cnt // len(step_times),
                      "alg_bytes_per_launch": bsum // cnt},
-        "hbm_tbs_whole_step": alg_total / t_step / 1e12,
+        "plain": {"gates_per_s": plain_rate, "gates_timed": len(plain_ops),
+                  "per_kernel": summarize(p_per, len(p_times))},
+        "speedup_vs_plain": (gates / t_step) / plain_rate,
+        "hbm_tbs_whole_step": (sum(v[2] for v in per_class.values()) / len(step_times)) / t_step / 1e12,
         "paper_nominal_tbs": (1 << (n + 5)) * gates / t_step / 1e12,
-        "per_kernel": {c: {"launches": v[1] // args.steps, "avg_ms": v[0] / v[1] * 1e3,
-                           "tbs": v[2] / v[0] / 1e12} for c, v in sorted(per_class.items())},
+        "alternatives": {k: {kk: vv for kk, vv in v.items() if not kk.startswith("_")} for k, v in results.items()},
         "norm_after": nrm,
         "wall_s": wall,
     }

@@ -143,6 +143,55 @@ QS_API int qs_get_info(qs_state *st, int *n, int *dtype, void **dev_ptr, void **
 /* Message of the last failing call on this thread ("" if none). */
 QS_API const char *qs_last_error(void);
 
+/* ---- circuits and execution plans ----
+ * A circuit is an ordered list of operations (Sec. II-A: a circuit applies its gates in sequence); the add
+ * calls take the same arguments, with the same validation, as the qs_apply_* calls, and copy them. */
+typedef struct qs_circuit qs_circuit;
+typedef struct qs_plan qs_plan;
+
+/* Create an empty circuit on n qubits (1 <= n <= QS_MAX_QUBITS). Host only; no device work. */
+QS_API int qs_circuit_create(qs_circuit **out, int n);
+QS_API int qs_circuit_free(qs_circuit *c);
+QS_API int qs_circuit_add_gate(qs_circuit *c, const int *targets, int k, const double *U);
+QS_API int qs_circuit_add_diag(qs_circuit *c, const int *targets, int k, const double *d);
+QS_API int qs_circuit_add_controlled(qs_circuit *c, const int *controls, int nc, const int *targets, int k,
+                                     const double *U);
+QS_API int qs_circuit_add_fused_swap(qs_circuit *c, int p, int q, int s);
+/* Number of operations recorded. */
+QS_API int qs_circuit_size(const qs_circuit *c, int *nops);
+/* Plain execution: exactly the qs_apply_* / qs_fused_swap calls of the circuit, in order (one pass each).
+ * QS_EINVAL if the circuit's qubit count differs from the state's. */
+QS_API int qs_circuit_run(qs_state *st, const qs_circuit *c);
+
+enum {
+    QS_PLAN_BLOCK = 0, /* LDS block passes over a qubit set of block_bits qubits (8..13) */
+    QS_PLAN_FUSE = 1   /* dense fused blocks of at most block_bits qubits (1..6) */
+};
+typedef struct {
+    int mode;       /* QS_PLAN_BLOCK or QS_PLAN_FUSE */
+    int block_bits; /* BLOCK: qubits local to one workgroup; FUSE: largest fused gate */
+    int low_bits;   /* BLOCK: the lowest low_bits qubits are always local (whole cache lines per segment) */
+    int dtype;      /* QS_C128 / QS_C64: precision the plan's matrices are uploaded in */
+} qs_plan_opts;
+
+/* Group the circuit's operations into passes (host only; the circuit may be freed afterwards). A gate joins
+ * a pass only when every earlier gate on its qubits is placed, so running the plan gives the circuit's state up
+ * to rounding (fused matrices are products formed in FP64 on the host). BLOCK mode on fewer than 8 qubits
+ * falls back to FUSE mode with 4-qubit blocks. Errors: QS_EINVAL for out-of-range options. */
+QS_API int qs_plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts);
+/* Enqueue every pass (or passes [begin, end)) on the state's stream. The first run uploads the plan's matrices
+ * to the current device (synchronous copy). QS_EINVAL if n or dtype differ from the plan's. */
+QS_API int qs_plan_run(qs_state *st, qs_plan *p);
+QS_API int qs_plan_run_range(qs_state *st, qs_plan *p, int begin, int end);
+/* Pass counts: all passes, LDS block passes, dense passes, others (fused-swaps, large controlled gates), and the
+ * number of fused operations executed inside the block / dense passes. Any output may be NULL. */
+QS_API int qs_plan_info(const qs_plan *p, int *npasses, int *nblock, int *ndense, int *nother, int *nfused_ops);
+/* Pass i: type (0 block, 1 dense, 2 fused-swap, 3 other), qubits it spans and their mask, fused operations in it
+ * and circuit gates it carries. */
+QS_API int qs_plan_pass_info(const qs_plan *p, int i, int *type, int *nqubits, int64_t *qmask, int *nops,
+                             int *ngates);
+QS_API int qs_plan_free(qs_plan *p);
+
 /* ---- bandwidth probes (the measured HBM ceiling the gate kernels are compared against) ---- */
 
 /* dst[i] = src[i] over `bytes` (multiple of 16, both 16-byte aligned), enqueued on hip_stream. */
@@ -154,7 +203,8 @@ QS_API int qs_probe_rmw(void *buf, size_t bytes, void *hip_stream);
 /* ---- launch tunables (autotuner / sweeps) ----
  * "dense_gpt"   groups per thread of the 1- and 2-qubit dense kernels: 1, 2 or 4 (default 1);
  * "nontemporal" 0/1: non-temporal loads and stores in the dense kernels (default 1);
- * "mfma_wg_per_cu" persistent workgroups per compute unit of the k = 5, 6 MFMA block kernel (1..16, default 2).
+ * "mfma_wg_per_cu" persistent workgroups per compute unit of the k = 5, 6 MFMA block kernel (1..16, default 2);
+ * "block_wg_per_cu" persistent workgroups per compute unit of the LDS block kernel (1..16, default 4).
  * Process-wide; affects launches enqueued after the call. QS_EINVAL for an unknown name or value. */
 QS_API int qs_set_tunable(const char *name, int64_t value);
 

@@ -18,6 +18,12 @@ LIB_PATH = os.path.join(PKG, "libqs.so")
 QS_OK, QS_EINVAL, QS_ENOMEM, QS_EDEVICE, QS_EUNSUPPORTED = 0, -1, -2, -3, -4
 QS_C128, QS_C64 = 0, 1
 QS_MAX_K, QS_MAX_DIAG_K, QS_MAX_CONTROLS, QS_MAX_QUBITS = 6, 12, 16, 40
+QS_PLAN_BLOCK, QS_PLAN_FUSE = 0, 1
+
+
+class qs_plan_opts(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("block_bits", ctypes.c_int), ("low_bits", ctypes.c_int),
+                ("dtype", ctypes.c_int)]
 
 _lib = None
 
@@ -54,6 +60,20 @@ SIGNATURES = {
     "qs_probe_copy": [_P, _P, ctypes.c_size_t, _P],
     "qs_probe_rmw": [_P, ctypes.c_size_t, _P],
     "qs_set_tunable": [ctypes.c_char_p, ctypes.c_int64],
+    "qs_circuit_create": [ctypes.POINTER(_P), _I],
+    "qs_circuit_free": [_P],
+    "qs_circuit_add_gate": [_P, _IP, _I, _DP],
+    "qs_circuit_add_diag": [_P, _IP, _I, _DP],
+    "qs_circuit_add_controlled": [_P, _IP, _I, _IP, _I, _DP],
+    "qs_circuit_add_fused_swap": [_P, _I, _I, _I],
+    "qs_circuit_size": [_P, _IP],
+    "qs_circuit_run": [_P, _P],
+    "qs_plan_create": [ctypes.POINTER(_P), _P, _P],
+    "qs_plan_run": [_P, _P],
+    "qs_plan_run_range": [_P, _P, _I, _I],
+    "qs_plan_info": [_P, _IP, _IP, _IP, _IP, _IP],
+    "qs_plan_pass_info": [_P, _I, _IP, _IP, ctypes.POINTER(ctypes.c_int64), _IP, _IP],
+    "qs_plan_free": [_P],
 }
 _RESTYPES = {"qs_last_error": ctypes.c_char_p}
 
@@ -192,3 +212,81 @@ def qs_probe_rmw(buf: int, nbytes: int, hip_stream: Optional[int] = None) -> Non
 
 def qs_set_tunable(name: str, value: int) -> None:
     _check(lib().qs_set_tunable(name.encode(), int(value)), "qs_set_tunable")
+
+
+# ------------------------------------------------------------------------------------------------ circuits, plans
+
+def qs_circuit_create(n: int) -> int:
+    h = _P()
+    _check(lib().qs_circuit_create(ctypes.byref(h), int(n)), "qs_circuit_create")
+    return h.value
+
+
+def qs_circuit_free(c: int) -> None:
+    _check(lib().qs_circuit_free(c), "qs_circuit_free")
+
+
+def qs_circuit_add_gate(c: int, targets, U) -> None:
+    U = _mat(U, len(targets))
+    _check(lib().qs_circuit_add_gate(c, _ints(targets), len(targets), _dptr(U.view(np.float64))),
+           "qs_circuit_add_gate")
+
+
+def qs_circuit_add_diag(c: int, targets, d) -> None:
+    d = _mat(d, len(targets), diag=True)
+    _check(lib().qs_circuit_add_diag(c, _ints(targets), len(targets), _dptr(d.view(np.float64))),
+           "qs_circuit_add_diag")
+
+
+def qs_circuit_add_controlled(c: int, controls, targets, U) -> None:
+    U = _mat(U, len(targets))
+    _check(lib().qs_circuit_add_controlled(c, _ints(controls), len(controls), _ints(targets), len(targets),
+                                           _dptr(U.view(np.float64))), "qs_circuit_add_controlled")
+
+
+def qs_circuit_add_fused_swap(c: int, p: int, q: int, s: int) -> None:
+    _check(lib().qs_circuit_add_fused_swap(c, int(p), int(q), int(s)), "qs_circuit_add_fused_swap")
+
+
+def qs_circuit_size(c: int) -> int:
+    v = ctypes.c_int()
+    _check(lib().qs_circuit_size(c, ctypes.byref(v)), "qs_circuit_size")
+    return v.value
+
+
+def qs_circuit_run(h: int, c: int) -> None:
+    _check(lib().qs_circuit_run(h, c), "qs_circuit_run")
+
+
+def qs_plan_create(c: int, mode: int, block_bits: int, low_bits: int = 0, dtype: int = QS_C128) -> int:
+    o = qs_plan_opts(int(mode), int(block_bits), int(low_bits), int(dtype))
+    h = _P()
+    _check(lib().qs_plan_create(ctypes.byref(h), c, ctypes.byref(o)), "qs_plan_create")
+    return h.value
+
+
+def qs_plan_run(h: int, p: int) -> None:
+    _check(lib().qs_plan_run(h, p), "qs_plan_run")
+
+
+def qs_plan_run_range(h: int, p: int, begin: int, end: int) -> None:
+    _check(lib().qs_plan_run_range(h, p, int(begin), int(end)), "qs_plan_run_range")
+
+
+def qs_plan_info(p: int):
+    v = [ctypes.c_int() for _ in range(5)]
+    _check(lib().qs_plan_info(p, *[ctypes.byref(x) for x in v]), "qs_plan_info")
+    return {"passes": v[0].value, "block": v[1].value, "dense": v[2].value, "other": v[3].value,
+            "fused_ops": v[4].value}
+
+
+def qs_plan_pass_info(p: int, i: int):
+    t, nq, no, ng = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    m = ctypes.c_int64()
+    _check(lib().qs_plan_pass_info(p, int(i), ctypes.byref(t), ctypes.byref(nq), ctypes.byref(m), ctypes.byref(no),
+                                   ctypes.byref(ng)), "qs_plan_pass_info")
+    return {"type": t.value, "nqubits": nq.value, "qmask": m.value, "nops": no.value, "ngates": ng.value}
+
+
+def qs_plan_free(p: int) -> None:
+    _check(lib().qs_plan_free(p), "qs_plan_free")

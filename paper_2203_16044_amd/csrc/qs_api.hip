@@ -85,6 +85,56 @@ void *qs_stage(qs_state *st, const void *host, size_t bytes)
     return d;
 }
 
+// ---- host helpers shared with the planner ----
+InsBits qs_make_ins(uint64_t mask, uint64_t orm)
+{
+    InsBits ins{};
+    ins.np = 0;
+    for (int p = 0; p < 64; ++p)
+        if ((mask >> p) & 1)
+            ins.lowmask[ins.np++] = ((uint64_t)1 << p) - 1;
+    ins.orm = orm;
+    return ins;
+}
+
+// Sort the targets ascending; perm[j'] = the original matrix bit carried by sorted position j'.
+void qs_sort_targets(const int *t, int k, TPos &tp, int *perm)
+{
+    int idx[QS_MAX_DIAG_K];
+    for (int j = 0; j < k; ++j)
+        idx[j] = j;
+    std::sort(idx, idx + k, [&](int a, int b) { return t[a] < t[b]; });
+    for (int j = 0; j < k; ++j) {
+        perm[j] = idx[j];
+        if (j < QS_MAX_K)
+            tp.tpos[j] = t[idx[j]];
+    }
+}
+
+static inline int map_index(int as, const int *perm, int k)
+{
+    int a = 0;
+    for (int j = 0; j < k; ++j)
+        a |= ((as >> j) & 1) << perm[j];
+    return a;
+}
+
+// U (original bit order) -> U' in sorted bit order, interleaved FP64
+void qs_permute_matrix(const double *U, int k, const int *perm, std::vector<double> &out)
+{
+    const int D = 1 << k;
+    out.resize((size_t)2 * D * D);
+    for (int a = 0; a < D; ++a) {
+        const int oa = map_index(a, perm, k);
+        for (int b = 0; b < D; ++b) {
+            const int ob = map_index(b, perm, k);
+            out[2 * (a * D + b)] = U[2 * (oa * D + ob)];
+            out[2 * (a * D + b) + 1] = U[2 * (oa * D + ob) + 1];
+        }
+    }
+}
+
+
 namespace {
 
 void release(qs_state *st)
@@ -121,54 +171,6 @@ int check_qubits(const qs_state *st, const int *q, int cnt, const char *what, ui
     }
     *mask = m;
     return QS_OK;
-}
-
-InsBits make_ins(uint64_t mask, uint64_t orm)
-{
-    InsBits ins{};
-    ins.np = 0;
-    for (int p = 0; p < 64; ++p)
-        if ((mask >> p) & 1)
-            ins.lowmask[ins.np++] = ((uint64_t)1 << p) - 1;
-    ins.orm = orm;
-    return ins;
-}
-
-// Sort the targets ascending; perm[j'] = the original matrix bit carried by sorted position j'.
-void sort_targets(const int *t, int k, TPos &tp, int *perm)
-{
-    int idx[QS_MAX_DIAG_K];
-    for (int j = 0; j < k; ++j)
-        idx[j] = j;
-    std::sort(idx, idx + k, [&](int a, int b) { return t[a] < t[b]; });
-    for (int j = 0; j < k; ++j) {
-        perm[j] = idx[j];
-        if (j < QS_MAX_K)
-            tp.tpos[j] = t[idx[j]];
-    }
-}
-
-inline int map_index(int as, const int *perm, int k)
-{
-    int a = 0;
-    for (int j = 0; j < k; ++j)
-        a |= ((as >> j) & 1) << perm[j];
-    return a;
-}
-
-// U (original bit order) -> U' in sorted bit order, interleaved FP64
-void permute_matrix(const double *U, int k, const int *perm, std::vector<double> &out)
-{
-    const int D = 1 << k;
-    out.resize((size_t)2 * D * D);
-    for (int a = 0; a < D; ++a) {
-        const int oa = map_index(a, perm, k);
-        for (int b = 0; b < D; ++b) {
-            const int ob = map_index(b, perm, k);
-            out[2 * (a * D + b)] = U[2 * (oa * D + ob)];
-            out[2 * (a * D + b) + 1] = U[2 * (oa * D + ob) + 1];
-        }
-    }
 }
 
 // Monomial matrix with every nonzero in {1, -1, i, -i} (exact) -> move table. Returns false otherwise.
@@ -226,10 +228,10 @@ int matrix_impl(qs_state *st, const int *targets, int k, uint64_t tmask, uint64_
     const int n = st->n;
     TPos tp{};
     int perm[QS_MAX_DIAG_K];
-    sort_targets(targets, k, tp, perm);
+    qs_sort_targets(targets, k, tp, perm);
     std::vector<double> Us;
-    permute_matrix(U, k, perm, Us);
-    const InsBits ins = make_ins(tmask | cmask, cmask);
+    qs_permute_matrix(U, k, perm, Us);
+    const InsBits ins = qs_make_ins(tmask | cmask, cmask);
     const int nins = __builtin_popcountll(tmask | cmask);
     const uint64_t ngroups = (uint64_t)1 << (n - nins);
     PermTable pt;
@@ -286,7 +288,7 @@ int diag_impl(qs_state *st, const int *targets, int k, const double *d)
             ent[e].cls = cls[a];
             ++e;
         }
-        const InsBits ins = make_ins(tmask, 0);
+        const InsBits ins = qs_make_ins(tmask, 0);
         QS_HIP(launch_diag_sparse(st->dtype, st->psi, (uint64_t)1 << (st->n - k), ins, m, ent, st->stream));
         return QS_OK;
     }
@@ -625,6 +627,10 @@ QS_API int qs_set_tunable(const char *name, int64_t value)
         if (value < 1 || value > 16)
             return qs_fail(QS_EINVAL, "mfma_wg_per_cu must be in [1, 16]");
         t.mfma_wg_per_cu = (int)value;
+    } else if (!std::strcmp(name, "block_wg_per_cu")) {
+        if (value < 1 || value > 16)
+            return qs_fail(QS_EINVAL, "block_wg_per_cu must be in [1, 16]");
+        t.block_wg_per_cu = (int)value;
     } else {
         return qs_fail(QS_EINVAL, "qs_set_tunable: unknown tunable '%s'", name);
     }

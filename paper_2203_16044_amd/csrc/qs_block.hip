@@ -1,0 +1,260 @@
+// LDS-staged multi-gate blocks ("local qubits" on one GPU).
+//
+// mpiQulacs splits the qubits of a distributed state into local ones (inside one process's memory, no
+// communication) and global ones (Sec. III-B), and uses fused-swaps to bring global qubits into the local range
+// before operating on them (Sec. III-D). On one GPU the same split appears between a workgroup's LDS and HBM: a
+// workgroup gathers the 2^B amplitudes whose index bits over a chosen qubit set L (|L| = B) vary, the other bits
+// fixed by the block number; every queued gate whose qubits lie in L is then applied in LDS, and the block is
+// written back once. L is arbitrary, so the gather plays the role of the fused-swap remap without an extra pass;
+// it always contains the lowest index bits so that every HBM segment is at least a full cache line.
+//
+// Inside the block the pass's ops are grouped into stages of at most 4 local qubits. In a stage every thread holds
+// the 16 amplitudes of a group (the stage's 4 positions varying) in registers, applies all of the stage's ops there
+// and writes the group back: one LDS round trip and one barrier per stage instead of per op. The stage list (4
+// ascending local positions each) and the op list (a 4-bit mask of the stage positions it acts on, k <= 3, and the
+// offset of its 2^k x 2^k matrix in the compute precision) live in device memory.
+#include "qs_internal.h"
+
+namespace {
+
+template <class R> struct BT;
+template <> struct BT<double> { using C2 = double2; };
+template <> struct BT<float> { using C2 = float2; };
+
+__device__ __forceinline__ uint64_t ins0b(uint64_t g, const InsBits &s)
+{
+    for (int j = 0; j < s.np; ++j) {
+        const uint64_t lo = g & s.lowmask[j];
+        g = ((g ^ lo) << 1) | lo;
+    }
+    return g | s.orm;
+}
+
+// local index m -> global offset: bit t of m goes to global bit lpos[t]
+__device__ __forceinline__ uint64_t spread(uint32_t m, const BlockMap &bm)
+{
+    uint64_t o = 0;
+    for (int t = 0; t < bm.b; ++t)
+        o |= (uint64_t)((m >> t) & 1) << bm.lpos[t];
+    return o;
+}
+
+// LDS slot of local index m: its low 4 bits are XOR-ed with bits 4-7, 8-11 and 12, so local position p moves the
+// 16-byte slot's bank group by the unit vector of class p mod 4. A stage's threads walk one position of each class
+// with their lowest counter bits, so 16 consecutive lanes always touch 16 different bank groups.
+__device__ __forceinline__ uint32_t swz(uint32_t m) { return m ^ (((m >> 4) ^ (m >> 8) ^ (m >> 12)) & 15u); }
+
+// Apply a k-qubit op (k = popcount(MASK) <= 3) to the 16 register amplitudes x[a], a = the 4 stage bits. Matrix bit
+// j <-> the j-th set bit of MASK (ascending); U is 2^k x 2^k, interleaved, in the compute precision.
+template <class R, int MASK>
+__device__ __forceinline__ void reg_op(typename BT<R>::C2 *x, const R *__restrict__ U)
+{
+    using C2 = typename BT<R>::C2;
+    constexpr int K = __builtin_popcount(MASK);
+    constexpr int D = 1 << K;
+    int bitpos[3] = {0, 0, 0};
+    {
+        int j = 0;
+        for (int b = 0; b < 4; ++b)
+            if ((MASK >> b) & 1)
+                bitpos[j++] = b;
+    }
+#pragma unroll
+    for (int rest = 0; rest < 16; ++rest) {
+        if (rest & MASK)
+            continue;  // enumerate the combinations of the other stage bits once
+        C2 v[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            int r = rest;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                r |= ((a >> j) & 1) << bitpos[j];
+            v[a] = x[r];
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            R yr = 0, yi = 0;
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                const R ur = U[2 * (a * D + b)], ui = U[2 * (a * D + b) + 1];
+                yr = fma(ur, v[b].x, yr);
+                yr = fma(-ui, v[b].y, yr);
+                yi = fma(ur, v[b].y, yi);
+                yi = fma(ui, v[b].x, yi);
+            }
+            int r = rest;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                r |= ((a >> j) & 1) << bitpos[j];
+            x[r].x = yr;
+            x[r].y = yi;
+        }
+    }
+}
+
+template <class R>
+__device__ __forceinline__ void reg_op_dispatch(typename BT<R>::C2 *x, int mask, const R *__restrict__ U)
+{
+    switch (mask) {
+    case 1: reg_op<R, 1>(x, U); break;
+    case 2: reg_op<R, 2>(x, U); break;
+    case 3: reg_op<R, 3>(x, U); break;
+    case 4: reg_op<R, 4>(x, U); break;
+    case 5: reg_op<R, 5>(x, U); break;
+    case 6: reg_op<R, 6>(x, U); break;
+    case 7: reg_op<R, 7>(x, U); break;
+    case 8: reg_op<R, 8>(x, U); break;
+    case 9: reg_op<R, 9>(x, U); break;
+    case 10: reg_op<R, 10>(x, U); break;
+    case 11: reg_op<R, 11>(x, U); break;
+    case 12: reg_op<R, 12>(x, U); break;
+    case 13: reg_op<R, 13>(x, U); break;
+    default: reg_op<R, 14>(x, U); break;
+    }
+}
+
+// One stage: every thread takes groups of 16 amplitudes (the 4 stage positions varying), applies the stage's ops
+// in registers and writes the group back.
+template <class R, int B>
+__device__ __forceinline__ void run_stage(typename BT<R>::C2 *s, const BlkStage &stg, const BlkStageOp *__restrict__ sops,
+                                          const R *__restrict__ mats)
+{
+    using C2 = typename BT<R>::C2;
+    constexpr int NG = (1 << B) >> 4;
+    uint32_t off[16];
+#pragma unroll
+    for (int a = 0; a < 16; ++a)
+        off[a] = ((a & 1) << stg.pos[0]) | (((a >> 1) & 1) << stg.pos[1]) | (((a >> 2) & 1) << stg.pos[2]) |
+                 (((a >> 3) & 1) << stg.pos[3]);
+    for (int g = threadIdx.x; g < NG; g += blockDim.x) {
+        uint32_t m = 0;
+#pragma unroll
+        for (int j = 0; j < B - 4; ++j)
+            m |= (((uint32_t)g >> j) & 1u) << stg.order[j];
+        C2 x[16];
+#pragma unroll
+        for (int a = 0; a < 16; ++a)
+            x[a] = s[swz(m + off[a])];
+        for (int o = 0; o < stg.nops; ++o) {
+            const BlkStageOp op = sops[stg.op_begin + o];
+            reg_op_dispatch<R>(x, op.mask, mats + op.mat_off);
+        }
+#pragma unroll
+        for (int a = 0; a < 16; ++a)
+            s[swz(m + off[a])] = x[a];
+    }
+}
+
+template <class R, int B>
+__global__ __launch_bounds__(256) void k_block(typename BT<R>::C2 *__restrict__ psi, uint64_t nblocks, InsBits outer,
+                                               BlockMap bm, const BlkStage *__restrict__ stages, int nstages,
+                                               const BlkStageOp *__restrict__ sops, const R *__restrict__ mats)
+{
+    using C2 = typename BT<R>::C2;
+    extern __shared__ __align__(16) unsigned char smem_blk[];
+    C2 *s = reinterpret_cast<C2 *>(smem_blk);
+    constexpr int N = 1 << B;
+    constexpr int PER = N / 256;  // amplitudes per thread for load / store
+    // local index m = tid + 256 * it: spread(tid) per thread, spread(256 * it) uniform
+    const uint64_t own = spread(threadIdx.x, bm);
+    uint64_t hi[PER];
+#pragma unroll
+    for (int it = 0; it < PER; ++it)
+        hi[it] = spread((uint32_t)(256 * it), bm);
+    // Software pipeline over this workgroup's blocks: the next block's global loads are issued into registers before
+    // the current block's stages run, so HBM traffic overlaps the FP arithmetic.
+    using NV = typename NT2<R>::type;
+    NV pre[PER];
+    uint64_t blk = blockIdx.x;
+    if (blk >= nblocks)
+        return;
+    {
+        const uint64_t base = ins0b(blk, outer) | own;
+#pragma unroll
+        for (int it = 0; it < PER; ++it)
+            pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(psi + base + hi[it]));
+    }
+    for (; blk < nblocks; blk += gridDim.x) {
+        const uint64_t base = ins0b(blk, outer) | own;
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            C2 v;
+            v.x = pre[it].x;
+            v.y = pre[it].y;
+            s[swz(threadIdx.x + 256 * it)] = v;
+        }
+        lds_barrier();
+        const uint64_t nxt = blk + gridDim.x;
+        if (nxt < nblocks) {
+            const uint64_t nbase = ins0b(nxt, outer) | own;
+#pragma unroll
+            for (int it = 0; it < PER; ++it)
+                pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(psi + nbase + hi[it]));
+        }
+        for (int t = 0; t < nstages; ++t) {
+            run_stage<R, B>(s, stages[t], sops, mats);
+            lds_barrier();
+        }
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const C2 v = s[swz(threadIdx.x + 256 * it)];
+            NV w;
+            w.x = v.x;
+            w.y = v.y;
+            __builtin_nontemporal_store(w, reinterpret_cast<NV *>(psi + base + hi[it]));
+        }
+        lds_barrier();
+    }
+}
+
+template <class R, int B>
+hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm, const BlkStage *stages,
+                   int nstages, const BlkStageOp *sops, const void *mats, hipStream_t s)
+{
+    using C2 = typename BT<R>::C2;
+    const size_t shm = sizeof(C2) << B;
+    static bool attr_set = false;
+    if (!attr_set && shm > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_block<R, B>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)shm);
+        if (e != hipSuccess)
+            return e;
+        attr_set = true;
+    }
+    // persistent workgroups (each walks several blocks so its loads can run ahead of its arithmetic)
+    int cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    uint64_t grid = (uint64_t)cus * qs_tunables().block_wg_per_cu;
+    if (grid > nblocks)
+        grid = nblocks;
+    hipLaunchKernelGGL((k_block<R, B>), dim3((unsigned)grid), dim3(256), shm, s, (C2 *)psi, nblocks, outer, bm,
+                       stages, nstages, sops, (const R *)mats);
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t block_r(int b, void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm,
+                   const BlkStage *stages, int nstages, const BlkStageOp *sops, const void *mats, hipStream_t s)
+{
+    switch (b) {
+    case 8: return block_b<R, 8>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
+    case 9: return block_b<R, 9>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
+    case 10: return block_b<R, 10>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
+    case 11: return block_b<R, 11>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
+    case 12: return block_b<R, 12>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
+    case 13: return block_b<R, 13>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_block(int dtype, int b, void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm,
+                        const BlkStage *stages_dev, int nstages, const BlkStageOp *sops_dev, const void *mats_dev,
+                        hipStream_t s)
+{
+    return dtype == QS_C128 ? block_r<double>(b, psi, nblocks, outer, bm, stages_dev, nstages, sops_dev, mats_dev, s)
+                            : block_r<float>(b, psi, nblocks, outer, bm, stages_dev, nstages, sops_dev, mats_dev, s);
+}

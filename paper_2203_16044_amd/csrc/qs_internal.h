@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "qs.h"
 
@@ -51,6 +52,13 @@ struct qs_state {
 void *qs_stage(qs_state *st, const void *host, size_t bytes);
 
 inline size_t amp_bytes(int dtype) { return dtype == QS_C128 ? 16 : 8; }
+
+struct InsBits;
+struct TPos;
+// host helpers (qs_api.hip): bit-insert mask, ascending target order, matrix in ascending target order
+InsBits qs_make_ins(uint64_t mask, uint64_t orm);
+void qs_sort_targets(const int *t, int k, TPos &tp, int *perm);
+void qs_permute_matrix(const double *U, int k, const int *perm, std::vector<double> &out);
 
 // ------------------------------------------------------------------------------------------------------------
 // kernel argument blocks (passed by value)
@@ -109,13 +117,52 @@ int probs_blocks(uint64_t dim);
 hipError_t launch_scale(int dtype, void *psi, uint64_t dim, double f, hipStream_t s);
 hipError_t launch_scale_dev(int dtype, void *psi, uint64_t dim, const double *norm_dev, hipStream_t s);
 
+// LDS block passes: local qubit set L (ascending global positions), op table in device memory
+constexpr int kMaxBlockBits = 13;
+constexpr int kMaxBlockOpK = 3;
+struct BlockMap {
+    int b;
+    int lpos[kMaxBlockBits];  // global bit of local bit t (ascending)
+};
+struct BlkStage {
+    int pos[4];    // local positions held in registers during the stage, ascending
+    int op_begin;  // first op of the stage in the op table
+    int nops;
+    // the other local positions in the order the bits of a thread's group counter fill them: the first four cover
+    // the four residue classes (mod 4) of the LDS swizzle so that 16 consecutive lanes hit 16 distinct bank groups
+    int order[kMaxBlockBits - 4];
+};
+struct BlkStageOp {
+    int mask;          // stage positions the op acts on (bit j of the mask <-> pos[j]); 1..3 bits set
+    uint32_t mat_off;  // offset of its 2^k x 2^k matrix (bit order of the mask's positions) in real elements
+};
+hipError_t launch_block(int dtype, int b, void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm,
+                        const BlkStage *stages_dev, int nstages, const BlkStageOp *sops_dev, const void *mats_dev,
+                        hipStream_t s);
+
 hipError_t launch_probe_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 hipError_t launch_probe_rmw(void *buf, size_t bytes, hipStream_t s);
 
-// tunables (set through qs_set_option-like hooks in tests / autotuner)
+// Workgroup barrier ordering LDS only: waits for this wave's LDS accesses (lgkmcnt) but not for its global loads
+// and stores, so prefetched loads and outstanding stores stay in flight across it (__syncthreads() would drain
+// them). Use only where the barrier protects LDS data.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// native two-element vectors for the non-temporal builtins (which do not accept HIP_vector_type)
+template <class R> struct NT2;
+template <> struct NT2<double> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct NT2<float> { typedef float type __attribute__((ext_vector_type(2))); };
+
+// tunables (set through qs_set_tunable)
 struct Tunables {
     int dense_gpt = 1;       // groups per thread for k = 1, 2
     int nontemporal = 1;     // use non-temporal loads/stores in the plain gate kernels
     int mfma_wg_per_cu = 2;  // persistent workgroups per CU for the MFMA block kernel
+    int block_wg_per_cu = 4; // persistent workgroups per CU for the LDS block kernel
 };
 Tunables &qs_tunables();

@@ -397,7 +397,7 @@ __global__ __launch_bounds__(256) void k_fswap_lds(C2 *__restrict__ psi, uint64_
                 Y[ra * rstride + rc] = psi[iy];
             }
         }
-        __syncthreads();
+        lds_barrier();
         for (int u = threadIdx.x; u < nel; u += blockDim.x) {
             const int ra = u / row, rc = u % row;
             const int cb = rc / E, e = rc % E;
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(256) void k_fswap_lds(C2 *__restrict__ psi, uint64_
                 psi[ix] = X[cb * rstride + ra * E + e];
             }
         }
-        __syncthreads();
+        lds_barrier();
     }
 }
 

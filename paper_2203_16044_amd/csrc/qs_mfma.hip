@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void k_dense_mfma(typename MF<R>::C2 *__restri
             tile[0][(tid >> 4) + 16 * it][tid & 15] = v;
         }
     }
-    __syncthreads();
+    lds_barrier();
     for (; T < ntiles; T += G) {
         const uint64_t Tn = T + G;
         // prefetch the next tile into registers
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(256) void k_dense_mfma(typename MF<R>::C2 *__restri
             for (int it = 0; it < LPT; ++it)
                 tile[buf ^ 1][(tid >> 4) + 16 * it][tid & 15] = pre[it];
         }
-        __syncthreads();
+        lds_barrier();
         buf ^= 1;
     }
 }

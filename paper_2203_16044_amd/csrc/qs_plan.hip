@@ -1,0 +1,853 @@
+// Circuits and execution plans (host C++).
+//
+// A circuit is an ordered list of operations (Sec. II-A: gates applied in sequence). It can be run plainly --
+// one kernel pass per operation, exactly the qs_apply_* calls in order -- or through a plan that groups
+// operations into fewer HBM passes:
+//   QS_PLAN_BLOCK  LDS block passes: each pass picks a set L of `block_bits` qubits (always containing the
+//                  `low_bits` lowest ones) and applies, inside LDS, every pending gate whose qubits lie in L;
+//   QS_PLAN_FUSE   dense fused blocks: each pass multiplies the pending gates on at most `block_bits` (<= 6) qubits
+//                  into one matrix, run by the register kernel (k <= 4) or the MFMA kernel (k = 5, 6).
+// Both respect the circuit's order: a gate joins a pass only when every earlier gate on its qubits has been
+// placed. Fused-swaps and gates too large for a pass run as passes of their own. The plan's final state equals
+// the circuit's (up to rounding): no qubit relabelling is left behind.
+#include <algorithm>
+#include <complex>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "qs_internal.h"
+
+using cd = std::complex<double>;
+
+namespace {
+
+constexpr int kMaxPlanGateQ = 6;  // gates on more qubits (large controlled gates) run through qs_apply_controlled
+
+struct RawOp {
+    int kind;  // 0 dense, 1 diag, 2 controlled, 3 fused-swap
+    std::vector<int> t, c;
+    std::vector<double> m;
+    int p = 0, q = 0, s = 0;
+};
+
+// planner gate: matrix on an ordered qubit list (matrix bit j <-> q[j]); kind 1 = fused-swap, 2 = opaque raw op
+struct PG {
+    int kind = 0;
+    std::vector<int> q;
+    std::vector<cd> m;
+    int raw = -1;  // index of the raw op
+};
+
+std::vector<cd> embed(const PG &g, const std::vector<int> &Q)
+{
+    const int K = (int)Q.size(), D = 1 << K, k = (int)g.q.size(), d = 1 << k;
+    int pos[kMaxPlanGateQ];
+    uint32_t gmask = 0;
+    for (int j = 0; j < k; ++j) {
+        pos[j] = (int)(std::find(Q.begin(), Q.end(), g.q[j]) - Q.begin());
+        gmask |= 1u << pos[j];
+    }
+    std::vector<cd> M((size_t)D * D, cd(0, 0));
+    for (int a = 0; a < D; ++a) {
+        int sa = 0;
+        for (int j = 0; j < k; ++j)
+            sa |= ((a >> pos[j]) & 1) << j;
+        for (int b = 0; b < D; ++b) {
+            if ((a ^ b) & ~gmask)
+                continue;
+            int sb = 0;
+            for (int j = 0; j < k; ++j)
+                sb |= ((b >> pos[j]) & 1) << j;
+            M[(size_t)a * D + b] = g.m[(size_t)sa * d + sb];
+        }
+    }
+    return M;
+}
+
+std::vector<cd> matmul(const std::vector<cd> &A, const std::vector<cd> &B, int D)
+{
+    std::vector<cd> C((size_t)D * D, cd(0, 0));
+    for (int i = 0; i < D; ++i)
+        for (int l = 0; l < D; ++l) {
+            const cd a = A[(size_t)i * D + l];
+            if (a == cd(0, 0))
+                continue;
+            for (int j = 0; j < D; ++j)
+                C[(size_t)i * D + j] += a * B[(size_t)l * D + j];
+        }
+    return C;
+}
+
+bool subset(const std::vector<int> &a, const std::vector<int> &b)
+{
+    for (int x : a)
+        if (std::find(b.begin(), b.end(), x) == b.end())
+            return false;
+    return true;
+}
+
+bool intersects(const std::vector<int> &a, const std::vector<int> &b)
+{
+    for (int x : a)
+        if (std::find(b.begin(), b.end(), x) != b.end())
+            return true;
+    return false;
+}
+
+// re-express a gate on its qubits in ascending order (matrix bits follow)
+PG sorted_gate(const PG &g)
+{
+    PG r = g;
+    std::sort(r.q.begin(), r.q.end());
+    r.m = embed(g, r.q);
+    return r;
+}
+
+}  // namespace
+
+struct qs_circuit {
+    int n = 0;
+    std::vector<RawOp> raw;
+    std::vector<PG> gates;
+};
+
+struct PlanPass {
+    int type = 0;  // 0 block, 1 dense, 2 fused-swap, 3 raw op
+    int b = 0;
+    uint64_t lmask = 0;
+    BlockMap bm{};
+    int op_begin = 0, nops = 0;  // block: fused ops carried
+    int stage_begin = 0, nstages = 0;  // block: range in stages
+    // dense
+    int k = 0;
+    TPos tp{};
+    uint64_t tmask = 0;
+    std::vector<double> Uh;  // sorted FP64 (kernel arguments for k <= 3)
+    size_t mat_off = 0;      // offset in the matrix pool (real elements)
+    int p = 0, q = 0, s = 0;
+    int raw = -1;
+    int ngates = 0;  // circuit gates carried by the pass
+};
+
+struct qs_plan {
+    int n = 0, dtype = QS_C128, mode = 0;
+    std::vector<PlanPass> passes;
+    std::vector<BlkStage> stages;
+    std::vector<BlkStageOp> sops;
+    std::vector<double> pool;  // matrices, FP64 (rounded to FP32 on upload for complex64)
+    std::vector<RawOp> raw;    // copy: the plan stays valid after the circuit is freed
+    BlkStage *dstages = nullptr;
+    BlkStageOp *dsops = nullptr;
+    void *dpool = nullptr;
+    int dev = -1;
+    int nfused_ops = 0;
+};
+
+namespace {
+
+int add_raw(qs_circuit *c, RawOp &&r, PG &&g)
+{
+    g.raw = (int)c->raw.size();
+    c->raw.push_back(std::move(r));
+    c->gates.push_back(std::move(g));
+    return QS_OK;
+}
+
+int check_list(int n, const int *q, int cnt, uint64_t *mask, const char *what)
+{
+    uint64_t m = 0;
+    for (int j = 0; j < cnt; ++j) {
+        if (q[j] < 0 || q[j] >= n)
+            return qs_fail(QS_EINVAL, "%s[%d] = %d is outside [0, %d)", what, j, q[j], n);
+        if (m & ((uint64_t)1 << q[j]))
+            return qs_fail(QS_EINVAL, "%s repeats qubit %d", what, q[j]);
+        m |= (uint64_t)1 << q[j];
+    }
+    *mask = m;
+    return QS_OK;
+}
+
+// ---- pass formation ----------------------------------------------------------------------------------------
+struct Former {
+    const qs_circuit &c;
+    int b, w, max_block_q;
+    std::vector<std::vector<int>> qlist;
+    std::vector<size_t> head;
+    std::vector<char> done;
+
+    Former(const qs_circuit &c_, int b_, int w_, int maxq) : c(c_), b(b_), w(w_), max_block_q(maxq)
+    {
+        qlist.assign(c.n, {});
+        head.assign(c.n, 0);
+        done.assign(c.gates.size(), 0);
+        for (size_t g = 0; g < c.gates.size(); ++g)
+            for (int q : c.gates[g].q)
+                qlist[q].push_back((int)g);
+    }
+    bool ready(int g) const
+    {
+        for (int q : c.gates[g].q)
+            if (head[q] >= qlist[q].size() || qlist[q][head[q]] != g)
+                return false;
+        return true;
+    }
+    void take(int g)
+    {
+        done[g] = 1;
+        for (int q : c.gates[g].q)
+            ++head[q];
+    }
+    bool blockable(int g) const { return c.gates[g].kind == 0 && (int)c.gates[g].q.size() <= max_block_q; }
+    // ready gates, ascending circuit index
+    std::vector<int> front() const
+    {
+        std::vector<int> f;
+        for (int q = 0; q < c.n; ++q)
+            if (head[q] < qlist[q].size()) {
+                const int g = qlist[q][head[q]];
+                if (ready(g) && std::find(f.begin(), f.end(), g) == f.end())
+                    f.push_back(g);
+            }
+        std::sort(f.begin(), f.end());
+        return f;
+    }
+
+    void run(std::vector<std::pair<std::vector<int>, std::vector<int>>> &out_passes, std::vector<int> &singles_order)
+    {
+        // out_passes: (L sorted, gates) for blockable passes; singles are encoded as L empty + one gate
+        size_t remaining = c.gates.size();
+        while (remaining) {
+            std::vector<int> L;
+            for (int q = 0; q < w && q < c.n; ++q)
+                L.push_back(q);
+            std::vector<int> pass;
+            for (;;) {
+                bool changed = true;
+                while (changed) {
+                    changed = false;
+                    for (int g : front())
+                        if (blockable(g) && subset(c.gates[g].q, L)) {
+                            take(g);
+                            pass.push_back(g);
+                            changed = true;
+                        }
+                }
+                int best = -1, bestnew = 1 << 30;
+                for (int g : front()) {
+                    if (!blockable(g))
+                        continue;
+                    int nw = 0;
+                    for (int q : c.gates[g].q)
+                        nw += std::find(L.begin(), L.end(), q) == L.end();
+                    if ((int)L.size() + nw <= b && nw < bestnew) {
+                        best = g;
+                        bestnew = nw;
+                    }
+                }
+                if (best < 0)
+                    break;
+                for (int q : c.gates[best].q)
+                    if (std::find(L.begin(), L.end(), q) == L.end())
+                        L.push_back(q);
+            }
+            if (!pass.empty()) {
+                // fill L up to b with the next qubits the front needs (they cost nothing) -- keep it sorted
+                std::sort(L.begin(), L.end());
+                remaining -= pass.size();
+                out_passes.emplace_back(L, pass);
+                continue;
+            }
+            // nothing blockable is ready: emit the earliest ready non-blockable gate on its own
+            std::vector<int> f = front();
+            if (f.empty())
+                break;  // cannot happen for a well-formed circuit
+            const int g = f[0];
+            take(g);
+            --remaining;
+            out_passes.emplace_back(std::vector<int>(), std::vector<int>{g});
+            singles_order.push_back(g);
+        }
+    }
+};
+
+// Merge gates of one pass: later gates into an earlier op on a superset of their qubits (nothing in between
+// touching them), then earlier small ops forward into a later superset op.
+std::vector<PG> fuse_pass(const qs_circuit &c, const std::vector<int> &gates)
+{
+    std::vector<PG> out;
+    for (int gi : gates) {
+        const PG &g = c.gates[gi];
+        bool merged = false;
+        for (int h = (int)out.size() - 1; h >= 0; --h) {
+            if (subset(g.q, out[h].q)) {
+                out[h].m = matmul(embed(g, out[h].q), out[h].m, 1 << out[h].q.size());
+                merged = true;
+                break;
+            }
+            if (intersects(g.q, out[h].q))
+                break;
+        }
+        if (!merged)
+            out.push_back(g);
+    }
+    for (size_t i = 0; i < out.size();) {
+        bool moved = false;
+        for (size_t j = i + 1; j < out.size(); ++j) {
+            if (subset(out[i].q, out[j].q)) {
+                out[j].m = matmul(out[j].m, embed(out[i], out[j].q), 1 << out[j].q.size());
+                out.erase(out.begin() + i);
+                moved = true;
+                break;
+            }
+            if (intersects(out[i].q, out[j].q))
+                break;
+        }
+        if (!moved)
+            ++i;
+    }
+    return out;
+}
+
+void push_matrix(std::vector<double> &pool, const std::vector<cd> &m)
+{
+    for (const cd &z : m) {
+        pool.push_back(z.real());
+        pool.push_back(z.imag());
+    }
+}
+
+int make_dense_pass(qs_plan *P, const PG &g, PlanPass &pp)
+{
+    const PG sg = sorted_gate(g);
+    pp.type = 1;
+    pp.k = (int)sg.q.size();
+    pp.tmask = 0;
+    for (int j = 0; j < pp.k; ++j) {
+        pp.tp.tpos[j] = sg.q[j];
+        pp.tmask |= (uint64_t)1 << sg.q[j];
+    }
+    pp.Uh.clear();
+    for (const cd &z : sg.m) {
+        pp.Uh.push_back(z.real());
+        pp.Uh.push_back(z.imag());
+    }
+    pp.mat_off = P->pool.size();
+    push_matrix(P->pool, sg.m);
+    return QS_OK;
+}
+
+int run_raw(qs_state *st, const RawOp &r)
+{
+    switch (r.kind) {
+    case 0: return qs_apply_gate(st, r.t.data(), (int)r.t.size(), r.m.data());
+    case 1: return qs_apply_diag(st, r.t.data(), (int)r.t.size(), r.m.data());
+    case 2: return qs_apply_controlled(st, r.c.data(), (int)r.c.size(), r.t.data(), (int)r.t.size(), r.m.data());
+    default: return qs_fused_swap(st, r.p, r.q, r.s);
+    }
+}
+
+int upload(qs_plan *P)
+{
+    int dev = 0;
+    QS_HIP(hipGetDevice(&dev));
+    if (P->dstages || P->dpool) {
+        if (dev == P->dev)
+            return QS_OK;
+        return qs_fail(QS_EINVAL, "qs_plan_run: plan was uploaded to device %d, current device is %d", P->dev, dev);
+    }
+    QS_HIP(hipMalloc((void **)&P->dstages, std::max<size_t>(P->stages.size(), 1) * sizeof(BlkStage)));
+    if (!P->stages.empty())
+        QS_HIP(hipMemcpy(P->dstages, P->stages.data(), P->stages.size() * sizeof(BlkStage), hipMemcpyHostToDevice));
+    QS_HIP(hipMalloc((void **)&P->dsops, std::max<size_t>(P->sops.size(), 1) * sizeof(BlkStageOp)));
+    if (!P->sops.empty())
+        QS_HIP(hipMemcpy(P->dsops, P->sops.data(), P->sops.size() * sizeof(BlkStageOp), hipMemcpyHostToDevice));
+    const size_t npool = std::max<size_t>(P->pool.size(), 2);
+    if (P->dtype == QS_C128) {
+        QS_HIP(hipMalloc(&P->dpool, npool * sizeof(double)));
+        if (!P->pool.empty())
+            QS_HIP(hipMemcpy(P->dpool, P->pool.data(), P->pool.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> f(P->pool.begin(), P->pool.end());
+        QS_HIP(hipMalloc(&P->dpool, npool * sizeof(float)));
+        if (!f.empty())
+            QS_HIP(hipMemcpy(P->dpool, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    P->dev = dev;
+    return QS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+QS_API int qs_circuit_create(qs_circuit **out, int n)
+{
+    qs_clear_error();
+    if (!out)
+        return qs_fail(QS_EINVAL, "qs_circuit_create: out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > QS_MAX_QUBITS)
+        return qs_fail(QS_EINVAL, "qs_circuit_create: n = %d outside [1, %d]", n, QS_MAX_QUBITS);
+    qs_circuit *c = new (std::nothrow) qs_circuit();
+    if (!c)
+        return qs_fail(QS_ENOMEM, "qs_circuit_create: out of host memory");
+    c->n = n;
+    *out = c;
+    return QS_OK;
+}
+
+QS_API int qs_circuit_free(qs_circuit *c)
+{
+    qs_clear_error();
+    if (!c)
+        return qs_fail(QS_EINVAL, "qs_circuit_free: NULL circuit");
+    delete c;
+    return QS_OK;
+}
+
+QS_API int qs_circuit_add_gate(qs_circuit *c, const int *targets, int k, const double *U)
+{
+    qs_clear_error();
+    if (!c || !targets || !U)
+        return qs_fail(QS_EINVAL, "qs_circuit_add_gate: NULL argument");
+    if (k < 1 || k > QS_MAX_K || k > c->n)
+        return qs_fail(QS_EINVAL, "qs_circuit_add_gate: k = %d outside [1, min(%d, n)]", k, QS_MAX_K);
+    uint64_t m;
+    if (int rc = check_list(c->n, targets, k, &m, "targets"))
+        return rc;
+    const int D = 1 << k;
+    RawOp r;
+    r.kind = 0;
+    r.t.assign(targets, targets + k);
+    r.m.assign(U, U + 2 * D * D);
+    PG g;
+    g.q = r.t;
+    g.m.resize((size_t)D * D);
+    for (int i = 0; i < D * D; ++i)
+        g.m[i] = cd(U[2 * i], U[2 * i + 1]);
+    return add_raw(c, std::move(r), std::move(g));
+}
+
+QS_API int qs_circuit_add_diag(qs_circuit *c, const int *targets, int k, const double *d)
+{
+    qs_clear_error();
+    if (!c || !targets || !d)
+        return qs_fail(QS_EINVAL, "qs_circuit_add_diag: NULL argument");
+    if (k < 1 || k > QS_MAX_DIAG_K || k > c->n)
+        return qs_fail(QS_EINVAL, "qs_circuit_add_diag: k = %d outside [1, min(%d, n)]", k, QS_MAX_DIAG_K);
+    uint64_t m;
+    if (int rc = check_list(c->n, targets, k, &m, "targets"))
+        return rc;
+    const int D = 1 << k;
+    RawOp r;
+    r.kind = 1;
+    r.t.assign(targets, targets + k);
+    r.m.assign(d, d + 2 * D);
+    PG g;
+    g.q = r.t;
+    if (k <= kMaxPlanGateQ) {
+        g.m.assign((size_t)D * D, cd(0, 0));
+        for (int a = 0; a < D; ++a)
+            g.m[(size_t)a * D + a] = cd(d[2 * a], d[2 * a + 1]);
+    } else {
+        g.kind = 2;
+    }
+    return add_raw(c, std::move(r), std::move(g));
+}
+
+QS_API int qs_circuit_add_controlled(qs_circuit *c, const int *controls, int nc, const int *targets, int k,
+                                     const double *U)
+{
+    qs_clear_error();
+    if (!c || !controls || !targets || !U)
+        return qs_fail(QS_EINVAL, "qs_circuit_add_controlled: NULL argument");
+    if (k < 1 || k > QS_MAX_K || nc < 1 || nc > QS_MAX_CONTROLS || nc + k > c->n)
+        return qs_fail(QS_EINVAL, "qs_circuit_add_controlled: counts out of range (c = %d, k = %d, n = %d)", nc, k,
+                       c->n);
+    uint64_t tm, cm;
+    if (int rc = check_list(c->n, targets, k, &tm, "targets"))
+        return rc;
+    if (int rc = check_list(c->n, controls, nc, &cm, "controls"))
+        return rc;
+    if (tm & cm)
+        return qs_fail(QS_EINVAL, "qs_circuit_add_controlled: a control is also a target");
+    const int D = 1 << k;
+    RawOp r;
+    r.kind = 2;
+    r.t.assign(targets, targets + k);
+    r.c.assign(controls, controls + nc);
+    r.m.assign(U, U + 2 * D * D);
+    PG g;
+    g.q = r.t;
+    g.q.insert(g.q.end(), controls, controls + nc);
+    if (k + nc <= kMaxPlanGateQ) {
+        const int DD = 1 << (k + nc);
+        g.m.assign((size_t)DD * DD, cd(0, 0));
+        const int cfull = ((1 << nc) - 1) << k;
+        for (int a = 0; a < DD; ++a) {
+            if ((a & cfull) != cfull) {
+                g.m[(size_t)a * DD + a] = cd(1, 0);
+                continue;
+            }
+            for (int b2 = 0; b2 < D; ++b2)
+                g.m[(size_t)a * DD + (cfull | b2)] = cd(U[2 * ((a & (D - 1)) * D + b2)], U[2 * ((a & (D - 1)) * D + b2) + 1]);
+        }
+    } else {
+        g.kind = 2;
+    }
+    return add_raw(c, std::move(r), std::move(g));
+}
+
+QS_API int qs_circuit_add_fused_swap(qs_circuit *c, int p, int q, int s)
+{
+    qs_clear_error();
+    if (!c)
+        return qs_fail(QS_EINVAL, "qs_circuit_add_fused_swap: NULL circuit");
+    if (s < 0 || p < 0 || q < 0 || p + s > c->n || q + s > c->n || std::min(p, q) + s > std::max(p, q))
+        return qs_fail(QS_EINVAL, "qs_circuit_add_fused_swap: invalid (p=%d q=%d s=%d) for n = %d", p, q, s, c->n);
+    if (s == 0)
+        return QS_OK;
+    RawOp r;
+    r.kind = 3;
+    r.p = p;
+    r.q = q;
+    r.s = s;
+    PG g;
+    g.kind = 1;
+    for (int j = 0; j < s; ++j) {
+        g.q.push_back(p + j);
+        g.q.push_back(q + j);
+    }
+    return add_raw(c, std::move(r), std::move(g));
+}
+
+QS_API int qs_circuit_size(const qs_circuit *c, int *nops)
+{
+    qs_clear_error();
+    if (!c || !nops)
+        return qs_fail(QS_EINVAL, "qs_circuit_size: NULL argument");
+    *nops = (int)c->raw.size();
+    return QS_OK;
+}
+
+QS_API int qs_circuit_run(qs_state *st, const qs_circuit *c)
+{
+    qs_clear_error();
+    if (!st || !c)
+        return qs_fail(QS_EINVAL, "qs_circuit_run: NULL argument");
+    if (c->n != st->n)
+        return qs_fail(QS_EINVAL, "qs_circuit_run: circuit has %d qubits, state has %d", c->n, st->n);
+    for (const RawOp &r : c->raw)
+        if (int rc = run_raw(st, r))
+            return rc;
+    return QS_OK;
+}
+
+QS_API int qs_plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts)
+{
+    qs_clear_error();
+    if (!out || !c || !opts)
+        return qs_fail(QS_EINVAL, "qs_plan_create: NULL argument");
+    *out = nullptr;
+    int mode = opts->mode, b = opts->block_bits, w = opts->low_bits;
+    if (opts->dtype != QS_C128 && opts->dtype != QS_C64)
+        return qs_fail(QS_EINVAL, "qs_plan_create: bad dtype %d", opts->dtype);
+    if (mode == QS_PLAN_BLOCK) {
+        if (c->n < 8) {  // a block needs at least 256 amplitudes: plan small states as fused dense blocks
+            mode = QS_PLAN_FUSE;
+            b = std::min(c->n, 4);
+            w = 0;
+        } else {
+            if (b < 8 || b > kMaxBlockBits)
+                return qs_fail(QS_EINVAL, "qs_plan_create: block_bits = %d outside [8, %d]", b, kMaxBlockBits);
+            b = std::min(b, c->n);
+            if (w < 0 || w > b)
+                return qs_fail(QS_EINVAL, "qs_plan_create: low_bits = %d outside [0, block_bits]", w);
+        }
+    } else if (mode == QS_PLAN_FUSE) {
+        if (b < 1 || b > QS_MAX_K)
+            return qs_fail(QS_EINVAL, "qs_plan_create: block_bits = %d outside [1, %d] for fused blocks", b, QS_MAX_K);
+        b = std::min(b, c->n);
+        w = 0;
+    } else {
+        return qs_fail(QS_EINVAL, "qs_plan_create: unknown mode %d", mode);
+    }
+    qs_plan *P = new (std::nothrow) qs_plan();
+    if (!P)
+        return qs_fail(QS_ENOMEM, "qs_plan_create: out of host memory");
+    P->n = c->n;
+    P->dtype = opts->dtype;
+    P->mode = mode;
+    P->raw = c->raw;
+    const int maxq = mode == QS_PLAN_BLOCK ? kMaxBlockOpK : b;
+    Former F(*c, b, w, maxq);
+    std::vector<std::pair<std::vector<int>, std::vector<int>>> passes;
+    std::vector<int> singles;
+    F.run(passes, singles);
+    for (auto &pr : passes) {
+        const std::vector<int> &L = pr.first;
+        const std::vector<int> &gs = pr.second;
+        PlanPass pp;
+        pp.ngates = (int)gs.size();
+        if (L.empty()) {  // a single non-blockable gate
+            const PG &g = c->gates[gs[0]];
+            if (g.kind == 1) {
+                pp.type = 2;
+                const RawOp &r = c->raw[g.raw];
+                pp.p = std::min(r.p, r.q);
+                pp.q = std::max(r.p, r.q);
+                pp.s = r.s;
+            } else if (g.kind == 2 || (int)g.q.size() > QS_MAX_K) {
+                pp.type = 3;
+                pp.raw = g.raw;
+            } else {
+                make_dense_pass(P, g, pp);
+            }
+            P->passes.push_back(std::move(pp));
+            continue;
+        }
+        if (mode == QS_PLAN_FUSE) {
+            PG blk;
+            blk.q = L;
+            const int D = 1 << L.size();
+            blk.m.assign((size_t)D * D, cd(0, 0));
+            for (int a = 0; a < D; ++a)
+                blk.m[(size_t)a * D + a] = cd(1, 0);
+            for (int gi : gs)
+                blk.m = matmul(embed(c->gates[gi], L), blk.m, D);
+            make_dense_pass(P, blk, pp);
+            P->nfused_ops += 1;
+            P->passes.push_back(std::move(pp));
+            continue;
+        }
+        // LDS block pass
+        pp.type = 0;
+        pp.b = b;
+        // pad L to b qubits with unused low qubits (any qubits work; low ones keep segments long)
+        std::vector<int> LL = L;
+        for (int q = 0; (int)LL.size() < b && q < c->n; ++q)
+            if (std::find(LL.begin(), LL.end(), q) == LL.end())
+                LL.push_back(q);
+        std::sort(LL.begin(), LL.end());
+        pp.lmask = 0;
+        pp.bm.b = b;
+        for (int t = 0; t < b; ++t) {
+            pp.bm.lpos[t] = LL[t];
+            pp.lmask |= (uint64_t)1 << LL[t];
+        }
+        std::vector<PG> fused = fuse_pass(*c, gs);
+        pp.nops = (int)fused.size();
+        // local positions of every fused op (ascending, as its sorted matrix expects)
+        std::vector<PG> sorted_ops;
+        std::vector<uint32_t> posmask;
+        for (const PG &f : fused) {
+            sorted_ops.push_back(sorted_gate(f));
+            uint32_t pm = 0;
+            for (int q : sorted_ops.back().q)
+                pm |= 1u << (int)(std::find(LL.begin(), LL.end(), q) - LL.begin());
+            posmask.push_back(pm);
+        }
+        // stages of at most 4 positions: repeatedly take ready ops (every earlier op sharing a position placed)
+        // that keep the stage within 4 positions, fewest new positions first
+        const int nf = (int)fused.size();
+        std::vector<char> placed(nf, 0);
+        int left = nf;
+        pp.stage_begin = (int)P->stages.size();
+        while (left) {
+            uint32_t S = 0;
+            std::vector<int> members;
+            for (;;) {
+                int best = -1, bestnew = 99;
+                for (int i = 0; i < nf; ++i) {
+                    if (placed[i])
+                        continue;
+                    bool rdy = true;
+                    for (int j = 0; j < i && rdy; ++j)
+                        if (!placed[j] && (posmask[j] & posmask[i]))
+                            rdy = false;
+                    if (!rdy)
+                        continue;
+                    const int nw = __builtin_popcount(posmask[i] & ~S);
+                    if (__builtin_popcount(S | posmask[i]) <= 4 && nw < bestnew) {
+                        best = i;
+                        bestnew = nw;
+                    }
+                }
+                if (best < 0)
+                    break;
+                placed[best] = 1;
+                --left;
+                S |= posmask[best];
+                members.push_back(best);
+            }
+            for (int p = 0; __builtin_popcount(S) < 4 && p < b; ++p)
+                S |= 1u << p;  // pad with unused positions
+            BlkStage stg{};
+            int j = 0;
+            for (int p = 0; p < b; ++p)
+                if ((S >> p) & 1)
+                    stg.pos[j++] = p;
+            // group-counter bit order over the other positions: one position of each residue class mod 4 first
+            {
+                std::vector<int> rest;
+                for (int p = 0; p < b; ++p)
+                    if (!((S >> p) & 1))
+                        rest.push_back(p);
+                std::vector<int> ord;
+                for (int cls = 0; cls < 4; ++cls)
+                    for (size_t r = 0; r < rest.size(); ++r)
+                        if (rest[r] % 4 == cls) {
+                            ord.push_back(rest[r]);
+                            rest.erase(rest.begin() + r);
+                            break;
+                        }
+                ord.insert(ord.end(), rest.begin(), rest.end());
+                for (int t = 0; t < b - 4; ++t)
+                    stg.order[t] = ord[t];
+            }
+            stg.op_begin = (int)P->sops.size();
+            stg.nops = (int)members.size();
+            for (int i : members) {
+                BlkStageOp so{};
+                for (int t = 0; t < 4; ++t)
+                    if ((posmask[i] >> stg.pos[t]) & 1)
+                        so.mask |= 1 << t;
+                so.mat_off = (uint32_t)P->pool.size();
+                push_matrix(P->pool, sorted_ops[i].m);
+                P->sops.push_back(so);
+            }
+            P->stages.push_back(stg);
+        }
+        pp.nstages = (int)P->stages.size() - pp.stage_begin;
+        P->nfused_ops += pp.nops;
+        P->passes.push_back(std::move(pp));
+    }
+    *out = P;
+    return QS_OK;
+}
+
+QS_API int qs_plan_run_range(qs_state *st, qs_plan *P, int begin, int end)
+{
+    qs_clear_error();
+    if (!st || !P)
+        return qs_fail(QS_EINVAL, "qs_plan_run: NULL argument");
+    if (st->n != P->n || st->dtype != P->dtype)
+        return qs_fail(QS_EINVAL, "qs_plan_run: plan is for n = %d dtype %d, state is n = %d dtype %d", P->n, P->dtype,
+                       st->n, st->dtype);
+    const int np = (int)P->passes.size();
+    if (begin < 0 || end > np || begin > end)
+        return qs_fail(QS_EINVAL, "qs_plan_run: pass range [%d, %d) outside [0, %d]", begin, end, np);
+    if (int rc = upload(P))
+        return rc;
+    const size_t esz = P->dtype == QS_C128 ? sizeof(double) : sizeof(float);
+    for (int i = begin; i < end; ++i) {
+        const PlanPass &pp = P->passes[i];
+        switch (pp.type) {
+        case 0: {
+            const InsBits outer = qs_make_ins(pp.lmask, 0);
+            QS_HIP(launch_block(st->dtype, pp.b, st->psi, (uint64_t)1 << (P->n - pp.b), outer, pp.bm,
+                                P->dstages + pp.stage_begin, pp.nstages, P->dsops, P->dpool, st->stream));
+            break;
+        }
+        case 1: {
+            const InsBits ins = qs_make_ins(pp.tmask, 0);
+            QS_HIP(launch_dense(st->dtype, pp.k, st->psi, (uint64_t)1 << (P->n - pp.k), ins, pp.tp, pp.Uh.data(),
+                                (const char *)P->dpool + pp.mat_off * esz, st->stream));
+            break;
+        }
+        case 2:
+            QS_HIP(launch_fused_swap(st->dtype, st->psi, P->n, pp.p, pp.q, pp.s, st->stream));
+            break;
+        default:
+            if (int rc = run_raw(st, P->raw[pp.raw]))
+                return rc;
+        }
+    }
+    return QS_OK;
+}
+
+QS_API int qs_plan_run(qs_state *st, qs_plan *P)
+{
+    if (!P) {
+        qs_clear_error();
+        return qs_fail(QS_EINVAL, "qs_plan_run: NULL plan");
+    }
+    return qs_plan_run_range(st, P, 0, (int)P->passes.size());
+}
+
+QS_API int qs_plan_info(const qs_plan *P, int *npasses, int *nblock, int *ndense, int *nother, int *nfused_ops)
+{
+    qs_clear_error();
+    if (!P)
+        return qs_fail(QS_EINVAL, "qs_plan_info: NULL plan");
+    int nb = 0, nd = 0, no = 0;
+    for (const PlanPass &pp : P->passes)
+        (pp.type == 0 ? nb : pp.type == 1 ? nd : no)++;
+    if (npasses)
+        *npasses = (int)P->passes.size();
+    if (nblock)
+        *nblock = nb;
+    if (ndense)
+        *ndense = nd;
+    if (nother)
+        *nother = no;
+    if (nfused_ops)
+        *nfused_ops = P->nfused_ops;
+    return QS_OK;
+}
+
+QS_API int qs_plan_pass_info(const qs_plan *P, int i, int *type, int *nqubits, int64_t *qmask, int *nops, int *ngates)
+{
+    qs_clear_error();
+    if (!P || i < 0 || i >= (int)P->passes.size())
+        return qs_fail(QS_EINVAL, "qs_plan_pass_info: NULL plan or pass index out of range");
+    const PlanPass &pp = P->passes[i];
+    int nq = 0;
+    int64_t m = 0;
+    switch (pp.type) {
+    case 0: nq = pp.b; m = (int64_t)pp.lmask; break;
+    case 1: nq = pp.k; m = (int64_t)pp.tmask; break;
+    case 2:
+        nq = 2 * pp.s;
+        for (int j = 0; j < pp.s; ++j)
+            m |= ((int64_t)1 << (pp.p + j)) | ((int64_t)1 << (pp.q + j));
+        break;
+    default: {
+        const RawOp &r = P->raw[pp.raw];
+        for (int q : r.t)
+            m |= (int64_t)1 << q;
+        for (int q : r.c)
+            m |= (int64_t)1 << q;
+        nq = __builtin_popcountll((uint64_t)m);
+    }
+    }
+    if (type)
+        *type = pp.type;
+    if (nqubits)
+        *nqubits = nq;
+    if (qmask)
+        *qmask = m;
+    if (nops)
+        *nops = pp.type == 0 ? pp.nops : 1;
+    if (ngates)
+        *ngates = pp.ngates;
+    return QS_OK;
+}
+
+QS_API int qs_plan_free(qs_plan *P)
+{
+    qs_clear_error();
+    if (!P)
+        return qs_fail(QS_EINVAL, "qs_plan_free: NULL plan");
+    if (P->dstages)
+        (void)hipFree(P->dstages);
+    if (P->dsops)
+        (void)hipFree(P->dsops);
+    if (P->dpool)
+        (void)hipFree(P->dpool);
+    delete P;
+    return QS_OK;
+}
+
+}  // extern "C"

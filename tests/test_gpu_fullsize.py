@@ -1,0 +1,146 @@
+"""Full-size checks (28 / 32 qubits) in the launch configurations the benchmark times.
+
+The oracle cannot follow a 32-qubit circuit in seconds, so these check what holds at any size: closed forms
+(H on every qubit gives 2^(-n/2) everywhere; a layer of 1-qubit gates on |0..0> gives a product state whose
+amplitudes are products of matrix entries), sampled amplitudes against those closed forms, exact moves under
+the fused-swap (psi'[sigma(i)] = psi[i]), the norm, and echo (C then its inverse returns |0..0>).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import circuits as C
+from paper_2203_16044_amd.plan import Circuit, Plan
+
+pytestmark = pytest.mark.gpu
+
+N = 32
+
+
+def _samples(n, count, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    idx = rng.integers(0, 1 << n, size=count, dtype=np.int64)
+    return np.unique(np.concatenate([idx, [0, (1 << n) - 1, 1, 1 << (n - 1)]]))
+
+
+CHUNK = 1 << 26
+
+
+def _max_abs_dev(buf, value):
+    """max_i |buf_i - value| over the whole state, in chunks (no full-size temporaries)."""
+    m = 0.0
+    for i in range(0, buf.numel(), CHUNK):
+        m = max(m, float((buf[i:i + CHUNK] - value).abs().max()))
+    return m
+
+
+def _nonzero(buf):
+    out = []
+    for i in range(0, buf.numel(), CHUNK):
+        nz = torch.nonzero(buf[i:i + CHUNK] != 0).flatten()
+        out += (nz + i).cpu().tolist()
+    return np.array(out, dtype=np.int64)
+
+
+def _amps(st, idx):
+    t = torch.as_tensor(idx, device=st.buf.device)
+    return st.buf[t].cpu().numpy().astype(np.complex128)
+
+
+@pytest.fixture(scope="module")
+def big_state(gpu):
+    torch.cuda.empty_cache()
+    st = gpu.State(N, "c128")
+    yield st
+    st.close()
+    del st
+    torch.cuda.empty_cache()
+
+
+def _product_reference(us, idx):
+    ref = np.ones(len(idx), dtype=np.complex128)
+    for q, u in enumerate(us):
+        ref *= np.where((idx >> q) & 1, u[1, 0], u[0, 0])
+    return ref
+
+
+@pytest.mark.parametrize("how", ["plain", "block"])
+def test_product_state_sampled_amplitudes(gpu, big_state, how):
+    rng = np.random.Generator(np.random.PCG64(77))
+    us = [C.u3(*rng.uniform(0, 2 * math.pi, 3)) for _ in range(N)]
+    circ = C.Circuit(N, [C.Op("dense", (q,), mat=us[q]) for q in range(N)])
+    st = big_state
+    st.init_zero()
+    if how == "plain":
+        st.run(circ.ops)
+    else:
+        c = Circuit.from_ops(N, circ.ops)
+        p = Plan(c, "block", 12, 4)
+        p.run(st)
+        p.close()
+    idx = _samples(N, 4096, 1)
+    assert np.max(np.abs(_amps(st, idx) - _product_reference(us, idx))) <= 1e-12
+    assert abs(st.norm() - 1.0) <= 1e-12
+    # fused-swap at full size: a pure move, psi'[sigma(i)] = psi[i] bit for bit
+    before = _amps(st, idx)
+    st.fused_swap(0, 26, 6)
+    d = ((idx >> 0) ^ (idx >> 26)) & 63
+    sig = idx ^ d ^ (d << 26)
+    assert _amps(st, sig).tobytes() == before.tobytes()
+
+
+def test_hadamard_x11_uniform_at_32_qubits(gpu, big_state):
+    """Sec. IV-D's benchmark circuit (11 H per qubit) through the block plan: H^11 = H, so all 2^32 amplitudes
+    equal 2^-16."""
+    circ = C.hadamard_x11(N)
+    st = big_state
+    st.init_zero()
+    c = Circuit.from_ops(N, circ.ops)
+    p = Plan(c, "block", 12, 4)
+    p.run(st)
+    p.close()
+    assert _max_abs_dev(st.buf, 2.0 ** -16) <= 1e-15
+    assert abs(st.norm() - 1.0) <= 1e-12
+
+
+def test_ghz_at_32_qubits(gpu, big_state):
+    st = big_state
+    st.init_zero()
+    st.run(C.ghz(N).ops)
+    nz = _nonzero(st.buf)
+    assert nz.tolist() == [0, (1 << N) - 1]
+    assert np.max(np.abs(_amps(st, nz) - 1 / math.sqrt(2))) <= 1e-15
+
+
+def test_random_circuit_norm_and_echo_block_plan(gpu, big_state):
+    """The benchmark's 32-qubit random circuit (40 layers, block plan b=12, 4 low bits) preserves the norm, and
+    running its inverse afterwards returns to |0..0>."""
+    circ = C.config2(n=N, seed=32, layers=40)
+    st = big_state
+    st.init_zero()
+    c = Circuit.from_ops(N, circ.ops)
+    p = Plan(c, "block", 12, 4)
+    p.run(st)
+    assert abs(st.norm() - 1.0) <= 1e-12
+    inv = C.inverse_circuit(circ)
+    ci = Circuit.from_ops(N, inv.ops)
+    pi = Plan(ci, "block", 12, 4)
+    pi.run(st)
+    a0 = _amps(st, np.array([0]))[0]
+    assert abs(a0 - 1.0) <= 1e-12
+    idx = _samples(N, 4096, 2)[1:]
+    assert np.max(np.abs(_amps(st, idx))) <= 1e-12
+    for x in (p, pi, c, ci):
+        x.close()
+
+
+def test_config1_28_qubits_unfused_norm_and_echo(gpu):
+    circ = C.config1()
+    st = gpu.State(28, "c128")
+    st.run(circ.ops)
+    assert abs(st.norm() - 1.0) <= 1e-12
+    st.run(C.inverse_circuit(circ).ops)
+    assert abs(_amps(st, np.array([0]))[0] - 1.0) <= 1e-12
+    st.close()

@@ -1,0 +1,96 @@
+"""GPU parity of planned execution (LDS block passes, fused dense blocks) against the CPU oracle.
+
+A plan reorders nothing that matters: every gate is applied after the earlier gates on its qubits, so the final
+state equals the unfused oracle's up to rounding (complex128: max |d amp| <= 1e-12).
+"""
+import numpy as np
+import pytest
+
+import circuits as C
+import oracle
+from paper_2203_16044_amd.plan import Circuit, Plan
+
+pytestmark = pytest.mark.gpu
+
+TOL128 = 1e-12
+PLANS = [("block", 8, 0), ("block", 8, 3), ("block", 10, 4), ("block", 11, 3), ("block", 12, 4), ("block", 13, 3),
+         ("fuse", 2, 0), ("fuse", 3, 0), ("fuse", 4, 0), ("fuse", 5, 0), ("fuse", 6, 0)]
+
+
+def _run_plan(gpu, circ, mode, bits, low, psi0=None, dtype="c128"):
+    st = gpu.State(circ.n, dtype)
+    if psi0 is not None:
+        st.set(psi0)
+    c = Circuit.from_ops(circ.n, circ.ops)
+    p = Plan(c, mode, bits, low, dtype)
+    p.run(st)
+    got = st.get()
+    info = p.info()
+    p.close()
+    c.close()
+    st.close()
+    return got, info
+
+
+def _maxerr(a, b):
+    return float(np.max(np.abs(np.asarray(a, np.complex128) - np.asarray(b, np.complex128))))
+
+
+@pytest.mark.parametrize("mode,bits,low", PLANS)
+@pytest.mark.parametrize("n", [9, 14])
+def test_plan_random_circuits_every_kind(gpu, mode, bits, low, n):
+    circ = C.random_circuit(n, seed=400 + n, num_ops=120, kmax=4)
+    psi0 = C.random_state(n, n)
+    got, _ = _run_plan(gpu, circ, mode, bits, low, psi0)
+    assert _maxerr(got, oracle.run(circ, psi0)) <= TOL128
+
+
+@pytest.mark.parametrize("mode,bits,low", [("block", 12, 4), ("block", 10, 3), ("fuse", 4, 0), ("fuse", 6, 0)])
+def test_plan_config0_all_amplitudes(gpu, mode, bits, low):
+    circ = C.config0()
+    got, _ = _run_plan(gpu, circ, mode, bits, low)
+    assert _maxerr(got, oracle.run(circ)) <= TOL128
+
+
+@pytest.mark.parametrize("mode,bits,low", [("block", 12, 4), ("block", 13, 3), ("fuse", 5, 0), ("fuse", 6, 0)])
+def test_plan_su4_u3_family_18_qubits(gpu, mode, bits, low):
+    circ = C.config2(n=18, seed=32, layers=14)
+    got, info = _run_plan(gpu, circ, mode, bits, low)
+    assert info["passes"] < len(circ.ops) // 4
+    assert _maxerr(got, oracle.run(circ)) <= TOL128
+
+
+def test_plan_config1_family_18_qubits(gpu):
+    circ = C.config1(n=18, seed=28)
+    got, info = _run_plan(gpu, circ, "block", 12, 4)
+    assert info["other"] == 3  # the circuit's fused-swaps
+    assert _maxerr(got, oracle.run(circ)) <= TOL128
+
+
+def test_plan_small_state_fallback(gpu):
+    circ = C.random_circuit(6, seed=8, num_ops=50, kmax=3)
+    psi0 = C.random_state(6, 1)
+    got, info = _run_plan(gpu, circ, "block", 12, 4, psi0)
+    assert info["block"] == 0
+    assert _maxerr(got, oracle.run(circ, psi0)) <= TOL128
+
+
+def test_plan_complex64_error_against_fp64_oracle(gpu):
+    circ = C.config3(n=18, seed=33, layers=12)
+    got, _ = _run_plan(gpu, circ, "block", 12, 4, dtype="c64")
+    infid, maxd = oracle.error_metrics(got, oracle.run(circ))
+    assert infid <= 1e-8 and maxd <= 1e-5, (infid, maxd)
+
+
+def test_plan_rejects_mismatched_state(gpu):
+    circ = C.config0(n=12)
+    c = Circuit.from_ops(12, circ.ops)
+    p = Plan(c, "block", 10, 3, "c128")
+    st = gpu.State(13)
+    with pytest.raises(gpu.QSError):
+        p.run(st)
+    st.close()
+    st = gpu.State(12, "c64")
+    with pytest.raises(gpu.QSError):
+        p.run(st)
+    st.close()

@@ -1,0 +1,75 @@
+"""Planner (host C++ in libqs) checks that need no GPU: every gate placed once, option validation."""
+import pytest
+
+import circuits as C
+from paper_2203_16044_amd import binding as B
+from paper_2203_16044_amd.plan import Circuit, Plan
+
+
+def _gates_placed(plan):
+    return sum(p["ngates"] for p in plan.passes())
+
+
+@pytest.mark.parametrize("mode,bits,low", [("block", 8, 0), ("block", 10, 3), ("block", 12, 4), ("block", 13, 3),
+                                           ("fuse", 2, 0), ("fuse", 4, 0), ("fuse", 6, 0)])
+def test_every_gate_placed_once(mode, bits, low):
+    for circ in [C.config2(n=20, layers=6), C.config1(n=14), C.config0(n=12), C.random_circuit(12, 3, num_ops=80, kmax=4)]:
+        c = Circuit.from_ops(circ.n, circ.ops)
+        p = Plan(c, mode, bits, low)
+        assert _gates_placed(p) == len(circ.ops)
+        info = p.info()
+        assert info["passes"] == info["block"] + info["dense"] + info["other"]
+        for ps in p.passes():
+            assert bin(ps["qmask"] & ((1 << 64) - 1)).count("1") == ps["nqubits"] or ps["type"] == 0
+            if ps["type"] == 0:
+                assert ps["nqubits"] == min(bits, circ.n)
+                assert ps["qmask"] & ((1 << low) - 1) == (1 << low) - 1  # low bits always local
+            if ps["type"] == 1:  # fused block, or a single gate too large to share a pass
+                assert ps["nqubits"] <= (bits if mode == "fuse" else 6) or ps["ngates"] == 1
+        p.close()
+        c.close()
+
+
+def test_block_plan_cuts_passes_on_the_random_circuit():
+    circ = C.config2(n=32, layers=40)
+    c = Circuit.from_ops(circ.n, circ.ops)
+    p = Plan(c, "block", 12, 4)
+    info = p.info()
+    assert info["passes"] <= 90 and info["dense"] == 0 and info["other"] == 0
+    f = Plan(c, "fuse", 6)
+    assert f.info()["passes"] <= 140
+    assert _gates_placed(p) == _gates_placed(f) == 1920
+
+
+def test_fused_swaps_stay_passes_of_their_own():
+    circ = C.config1(n=16)
+    c = Circuit.from_ops(circ.n, circ.ops)
+    p = Plan(c, "block", 10, 3)
+    swaps = [x for x in p.passes() if x["type"] == 2]
+    assert len(swaps) == 3 and all(x["nqubits"] == 12 for x in swaps)
+
+
+def test_small_states_fall_back_to_fused_blocks():
+    circ = C.random_circuit(6, 1, num_ops=30, kmax=3)
+    p = Plan(Circuit.from_ops(6, circ.ops), "block", 12, 4)
+    assert p.info()["block"] == 0 and _gates_placed(p) == len(circ.ops)
+
+
+@pytest.mark.parametrize("mode,bits,low", [("block", 7, 0), ("block", 14, 3), ("block", 10, 11), ("fuse", 0, 0),
+                                           ("fuse", 7, 0)])
+def test_plan_options_validated(mode, bits, low):
+    c = Circuit(16)
+    with pytest.raises(B.QSError):
+        Plan(c, mode, bits, low)
+
+
+def test_circuit_add_validates():
+    c = Circuit(5)
+    import numpy as np
+    with pytest.raises(B.QSError):
+        B.qs_circuit_add_gate(c.h, (5,), np.eye(2))
+    with pytest.raises(B.QSError):
+        B.qs_circuit_add_controlled(c.h, (1,), (1,), np.eye(2))
+    with pytest.raises(B.QSError):
+        B.qs_circuit_add_fused_swap(c.h, 0, 1, 2)
+    assert len(c) == 0
