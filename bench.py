@@ -145,6 +145,7 @@ def main():
     ap.add_argument("--block-bits", type=int, default=12)
     ap.add_argument("--low-bits", type=int, default=4)
     ap.add_argument("--plain-layers", type=int, default=4, help="layers of the circuit timed on the plain path")
+    ap.add_argument("--greedy", action="store_true", help="headline the greedy plan instead of the learned one")
     ap.add_argument("--compare-fuse", type=int, nargs="*", default=[4, 6], help="fused-dense plans also timed")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -181,27 +182,39 @@ def main():
 
     results = {}
     if args.mode == "tuned":
+        from paper_2203_16044_amd import costmodel as CM
         cc = Circuit.from_ops(n, ops)
-        variants = [("block", args.block_bits, args.low_bits)] + [("fuse", k, 0) for k in args.compare_fuse]
-        for mode, bits, low in variants:
+        learned = None
+        if not args.greedy and os.path.exists(CM.WEIGHTS):
+            model = CM.CostModel.load()
+            lp, learned, pred = CM.choose_plan(cc, "c128", model)
+            lp.close()
+            model.close()
+        head_v = learned or ("block", args.block_bits, args.low_bits)
+        variants = [head_v] + [v for v in [("block", args.block_bits, args.low_bits)] + [("fuse", k, 0) for k in
+                                                                                          args.compare_fuse]
+                               if v != head_v]
+        for vi, (mode, bits, low) in enumerate(variants):
             plan = Plan(cc, mode, bits, low, "c128")
             info = plan.info()
             passes = plan.passes()
             kinds = {0: f"block_b{bits}", 1: "dense_k{}", 2: "fswap", 3: "other"}
             units = [(kinds[ps["type"]].format(ps["nqubits"]),
                       int(full * (1 - 2.0 ** -(ps["nqubits"] // 2))) if ps["type"] == 2 else full) for ps in passes]
-            main = mode == "block"
+            main = vi == 0
             times, per = time_steps(st, args.steps if main else 1, args.warmup if main else 1,
                                     lambda ev, plan=plan, npass=len(passes): run_plan(st, plan, npass, ev) if ev
                                     else plan.run(st), units, torch)
-            results[f"{mode}{bits}" + (f"_low{low}" if main else "")] = {
+            results[f"{mode}{bits}" + (f"_low{low}" if mode == "block" else "")] = {
                 "passes": info["passes"], "gates_per_s": gates / (sum(times) / len(times)),
                 "ms_per_step": sum(times) / len(times) * 1e3, "per_kernel": summarize(per, len(times)),
                 "_times": times, "_per": per}
             plan.close()
         cc.close()
-        head = results[f"block{args.block_bits}_low{args.low_bits}"]
+        hm, hb, hl = head_v
+        head = results[f"{hm}{hb}" + (f"_low{hl}" if hm == "block" else "")]
         step_times, per_class = head["_times"], head["_per"]
+        greedy_key = f"block{args.block_bits}_low{args.low_bits}"
     else:
         step_times, per_class = p_times, p_per
     nrm = st.norm()
@@ -228,8 +241,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"random SU(4)+U3 circuit, n={n}, {args.layers} layers, {gates} gates, complex128 "
                                f"(seed 32)", "n": n, "gates": gates, "mode": args.mode,
-                   "plan": (f"LDS block passes, {args.block_bits} local qubits incl. the {args.low_bits} lowest"
-                            if args.mode == "tuned" else "one pass per gate"),
+                   "plan": (("learned: " if args.mode == "tuned" and learned else "greedy: ") +
+                            (f"{head_v[0]} b={head_v[1]} low={head_v[2]}" if args.mode == "tuned"
+                             else "one pass per gate")),
                    "parallelism": "none"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_TBS, "unit": "TB/s",
                      "frac": achieved / HBM_PEAK_TBS, "traffic": None, "kernel": dom,
@@ -238,6 +252,8 @@ def main():
         "plain": {"gates_per_s": plain_rate, "gates_timed": len(plain_ops),
                   "per_kernel": summarize(p_per, len(p_times))},
         "speedup_vs_plain": (gates / t_step) / plain_rate,
+        "speedup_vs_greedy_plan": ((gates / t_step) / results[greedy_key]["gates_per_s"]
+                                   if args.mode == "tuned" else None),
         "hbm_tbs_whole_step": (sum(v[2] for v in per_class.values()) / len(step_times)) / t_step / 1e12,
         "paper_nominal_tbs": (1 << (n + 5)) * gates / t_step / 1e12,
         "alternatives": {k: {kk: vv for kk, vv in v.items() if not kk.startswith("_")} for k, v in results.items()},

@@ -192,6 +192,35 @@ QS_API int qs_plan_pass_info(const qs_plan *p, int i, int *type, int *nqubits, i
                              int *ngates);
 QS_API int qs_plan_free(qs_plan *p);
 
+/* ---- learned cost model (an MLP trained on the simulator's own pass timings) ----
+ * Features of plan pass i (QS_PLAN_NFEAT floats): [0-3] pass type one-hot (block, dense, fused-swap, other),
+ * [4] n/40, [5] dtype (0 complex128, 1 complex64), [6] qubits spanned/16, [7] fused ops/32, [8] register
+ * stages/16, [9] contiguous low qubits in the span/16, [10] lowest and [11] highest qubit/40, [12] low-4-qubit
+ * count/4, [13] log2(state bytes)/40, [14] flops per amplitude/256, [15] circuit gates carried/64, [16-19] block
+ * size one-hot (10..13 qubits), [20-23] dense target-count one-hot (3..6), [24] fused-swap s/16, [25] span holds
+ * the 4 lowest qubits, [26-47] span mask bits 0..21. */
+#define QS_PLAN_NFEAT 48
+QS_API int qs_plan_features(const qs_plan *p, int i, float *features);
+
+/* An MLP nin -> hidden -> hidden -> 1 (ReLU between layers), FP32, trained with MSE loss and Adam on the GPU by
+ * the library's own kernels (deterministic fixed-order reductions). Parameters are one flat array:
+ * W1[hidden][nin], b1[hidden], W2[hidden][hidden], b2[hidden], W3[hidden], b3. Batches hold 1..4096 samples;
+ * X is row-major (sample, feature); host arrays are copied during the call. All calls synchronise. */
+typedef struct qs_mlp qs_mlp;
+QS_API int qs_mlp_create(qs_mlp **out, int nin, int hidden, void *hip_stream);
+QS_API int qs_mlp_free(qs_mlp *m);
+QS_API int qs_mlp_num_params(const qs_mlp *m, int *nparams);
+/* Set the parameters (and reset the optimiser state) / read them back. */
+QS_API int qs_mlp_set_params(qs_mlp *m, const float *params);
+QS_API int qs_mlp_get_params(qs_mlp *m, float *params);
+/* Y[s] = network(X[s]) for s < B. */
+QS_API int qs_mlp_predict(qs_mlp *m, const float *X, int B, float *Y);
+/* Forward + backward of the mean squared error against targets T: gradients (nparams floats, same layout as the
+ * parameters) and loss, without updating; either output may be NULL. */
+QS_API int qs_mlp_grad(qs_mlp *m, const float *X, const float *T, int B, float *grads, float *loss);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the batch; loss before the step (nullable). */
+QS_API int qs_mlp_train_step(qs_mlp *m, const float *X, const float *T, int B, float lr, float *loss);
+
 /* ---- bandwidth probes (the measured HBM ceiling the gate kernels are compared against) ---- */
 
 /* dst[i] = src[i] over `bytes` (multiple of 16, both 16-byte aligned), enqueued on hip_stream. */

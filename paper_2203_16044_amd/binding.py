@@ -19,6 +19,7 @@ QS_OK, QS_EINVAL, QS_ENOMEM, QS_EDEVICE, QS_EUNSUPPORTED = 0, -1, -2, -3, -4
 QS_C128, QS_C64 = 0, 1
 QS_MAX_K, QS_MAX_DIAG_K, QS_MAX_CONTROLS, QS_MAX_QUBITS = 6, 12, 16, 40
 QS_PLAN_BLOCK, QS_PLAN_FUSE = 0, 1
+QS_PLAN_NFEAT = 48
 
 
 class qs_plan_opts(ctypes.Structure):
@@ -74,6 +75,17 @@ SIGNATURES = {
     "qs_plan_info": [_P, _IP, _IP, _IP, _IP, _IP],
     "qs_plan_pass_info": [_P, _I, _IP, _IP, ctypes.POINTER(ctypes.c_int64), _IP, _IP],
     "qs_plan_free": [_P],
+    "qs_plan_features": [_P, _I, ctypes.POINTER(ctypes.c_float)],
+    "qs_mlp_create": [ctypes.POINTER(_P), _I, _I, _P],
+    "qs_mlp_free": [_P],
+    "qs_mlp_num_params": [_P, _IP],
+    "qs_mlp_set_params": [_P, ctypes.POINTER(ctypes.c_float)],
+    "qs_mlp_get_params": [_P, ctypes.POINTER(ctypes.c_float)],
+    "qs_mlp_predict": [_P, ctypes.POINTER(ctypes.c_float), _I, ctypes.POINTER(ctypes.c_float)],
+    "qs_mlp_grad": [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), _I,
+                    ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
+    "qs_mlp_train_step": [_P, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float), _I, ctypes.c_float,
+                          ctypes.POINTER(ctypes.c_float)],
 }
 _RESTYPES = {"qs_last_error": ctypes.c_char_p}
 
@@ -290,3 +302,71 @@ def qs_plan_pass_info(p: int, i: int):
 
 def qs_plan_free(p: int) -> None:
     _check(lib().qs_plan_free(p), "qs_plan_free")
+
+
+# ------------------------------------------------------------------------------------------------ cost model
+
+_FP = ctypes.POINTER(ctypes.c_float)
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+
+
+def qs_plan_features(p: int, i: int) -> np.ndarray:
+    out = np.empty(QS_PLAN_NFEAT, dtype=np.float32)
+    _check(lib().qs_plan_features(p, int(i), out.ctypes.data_as(_FP)), "qs_plan_features")
+    return out
+
+
+def qs_mlp_create(nin: int, hidden: int, hip_stream: Optional[int] = None) -> int:
+    h = _P()
+    _check(lib().qs_mlp_create(ctypes.byref(h), int(nin), int(hidden), hip_stream), "qs_mlp_create")
+    return h.value
+
+
+def qs_mlp_free(m: int) -> None:
+    _check(lib().qs_mlp_free(m), "qs_mlp_free")
+
+
+def qs_mlp_num_params(m: int) -> int:
+    v = ctypes.c_int()
+    _check(lib().qs_mlp_num_params(m, ctypes.byref(v)), "qs_mlp_num_params")
+    return v.value
+
+
+def qs_mlp_set_params(m: int, params) -> None:
+    p = _f32(params)
+    if p.size != qs_mlp_num_params(m):
+        raise ValueError("parameter vector has the wrong size")
+    _check(lib().qs_mlp_set_params(m, p.ctypes.data_as(_FP)), "qs_mlp_set_params")
+
+
+def qs_mlp_get_params(m: int) -> np.ndarray:
+    out = np.empty(qs_mlp_num_params(m), dtype=np.float32)
+    _check(lib().qs_mlp_get_params(m, out.ctypes.data_as(_FP)), "qs_mlp_get_params")
+    return out
+
+
+def qs_mlp_predict(m: int, X) -> np.ndarray:
+    X = _f32(X)
+    out = np.empty(X.shape[0], dtype=np.float32)
+    _check(lib().qs_mlp_predict(m, X.ctypes.data_as(_FP), X.shape[0], out.ctypes.data_as(_FP)), "qs_mlp_predict")
+    return out
+
+
+def qs_mlp_grad(m: int, X, T):
+    X, T = _f32(X), _f32(T)
+    g = np.empty(qs_mlp_num_params(m), dtype=np.float32)
+    loss = ctypes.c_float()
+    _check(lib().qs_mlp_grad(m, X.ctypes.data_as(_FP), T.ctypes.data_as(_FP), X.shape[0], g.ctypes.data_as(_FP),
+                             ctypes.byref(loss)), "qs_mlp_grad")
+    return g, loss.value
+
+
+def qs_mlp_train_step(m: int, X, T, lr: float) -> float:
+    X, T = _f32(X), _f32(T)
+    loss = ctypes.c_float()
+    _check(lib().qs_mlp_train_step(m, X.ctypes.data_as(_FP), T.ctypes.data_as(_FP), X.shape[0], float(lr),
+                                   ctypes.byref(loss)), "qs_mlp_train_step")
+    return loss.value

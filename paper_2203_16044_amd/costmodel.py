@@ -1,0 +1,264 @@
+"""Learned cost model for the planner: an MLP (trained and run by libqs's own GPU kernels) predicts the time of a
+plan pass from its features; the planner scores candidate plans with it and keeps the cheapest. The greedy plan
+(LDS blocks of 12 qubits incl. the 4 lowest) is the fallback and the reference the model is judged against.
+
+Data: the simulator times every pass of candidate plans of 20-30-qubit circuits with HIP events on the state's
+stream (the target is log(pass milliseconds)). Features come from ``qs_plan_features`` (QS_PLAN_NFEAT floats).
+Usage on a GPU machine:  python -m paper_2203_16044_amd.costmodel --out <weights.npz>
+"""
+from __future__ import annotations
+
+import argparse
+import math
+import os
+import time
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import binding as B
+
+NIN = B.QS_PLAN_NFEAT
+HIDDEN = 64
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "costmodel_weights.npz")
+GREEDY = ("block", 12, 4)
+
+
+def candidates(n: int) -> List[Tuple[str, int, int]]:
+    out = [("block", b, w) for b in (10, 11, 12, 13) for w in (3, 4) if b <= n and n >= 8]
+    out += [("fuse", k, 0) for k in (2, 3, 4, 5, 6) if k <= n]
+    return out
+
+
+def greedy_for(n: int) -> Tuple[str, int, int]:
+    return GREEDY if n >= 12 else ("block", max(8, n), min(4, n)) if n >= 8 else ("fuse", min(4, n), 0)
+
+
+def plan_features(plan) -> np.ndarray:
+    return np.stack([B.qs_plan_features(plan.h, i) for i in range(plan.info()["passes"])])
+
+
+def time_plan_passes(state, plan, reps: int = 2) -> np.ndarray:
+    """Per-pass milliseconds (the last of `reps` runs), recorded with events on the state's stream."""
+    import torch
+    npass = plan.info()["passes"]
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(npass)]
+    s = state.stream
+    for _ in range(reps):
+        state.init_zero()
+        for i in range(npass):
+            ev[i][0].record(s)
+            plan.run(state, i, i + 1)
+            ev[i][1].record(s)
+        torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) for a, b in ev], dtype=np.float64)
+
+
+def training_circuits(seed: int = 1000):
+    """The circuit families the model is trained on (20-30 qubits), kept short: pass times do not depend on depth."""
+    import circuits as C
+    out = []
+    for n in range(20, 31):
+        out.append(C.config2(n=n, seed=seed + n, layers=3))
+        out.append(C.config1(n=n, seed=seed + 100 + n, layers=3, toffolis=8, swap_s=min(6, n // 4)))
+        out.append(C.random_circuit(n, seed=seed + 200 + n, num_ops=60, kmax=3,
+                                    kinds=("dense", "diag", "ctrl")))
+    return out
+
+
+def collect(circs, dtypes=("c128", "c64"), log=print, groups=None):
+    """Time every pass of every candidate plan of every circuit: returns (features, log-ms targets). If `groups` is
+    a list, one id per pass (circuit/dtype index, candidate index) is appended to it."""
+    import torch
+
+    from .plan import Circuit, Plan
+    from .state import State
+    X, y = [], []
+    gid = 0
+    for dt in dtypes:
+        for circ in circs:
+            n = circ.n
+            st = State(n, dt)
+            c = Circuit.from_ops(n, circ.ops)
+            t0 = time.perf_counter()
+            for ci, (mode, bits, low) in enumerate(candidates(n)):
+                p = Plan(c, mode, bits, low, dt)
+                ms = time_plan_passes(st, p)
+                X.append(plan_features(p))
+                y.append(np.log(np.maximum(ms, 1e-4)))
+                if groups is not None:
+                    groups.extend([(gid, ci)] * len(ms))
+                p.close()
+            gid += 1
+            c.close()
+            st.close()
+            del st
+            torch.cuda.empty_cache()
+            log(f"collected {circ.name} {dt}: {sum(len(v) for v in y)} samples so far "
+                f"({time.perf_counter() - t0:.1f} s)")
+    return np.concatenate(X).astype(np.float32), np.concatenate(y).astype(np.float32)
+
+
+class CostModel:
+    """MLP over standardised pass features predicting log(ms); runs on libqs's kernels."""
+
+    def __init__(self, params: Optional[np.ndarray] = None, mean=None, std=None, hidden: int = HIDDEN):
+        self.hidden = hidden
+        self.h = B.qs_mlp_create(NIN, hidden)
+        self.mean = np.zeros(NIN, np.float32) if mean is None else np.asarray(mean, np.float32)
+        self.std = np.ones(NIN, np.float32) if std is None else np.asarray(std, np.float32)
+        if params is None:
+            params = self.init_params(hidden)
+        B.qs_mlp_set_params(self.h, params)
+
+    @staticmethod
+    def init_params(hidden: int, seed: int = 0) -> np.ndarray:
+        rng = np.random.Generator(np.random.PCG64(seed))
+        parts = [rng.standard_normal(hidden * NIN) * math.sqrt(2.0 / NIN), np.zeros(hidden),
+                 rng.standard_normal(hidden * hidden) * math.sqrt(2.0 / hidden), np.zeros(hidden),
+                 rng.standard_normal(hidden) * math.sqrt(1.0 / hidden), np.zeros(1)]
+        return np.concatenate(parts).astype(np.float32)
+
+    def _norm(self, X):
+        return (np.asarray(X, np.float32) - self.mean) / self.std
+
+    def fit(self, X, y, epochs: int = 300, batch: int = 256, lr: float = 2e-3, seed: int = 0, log=None):
+        X = np.asarray(X, np.float32)
+        self.mean = X.mean(axis=0)
+        self.std = np.where(X.std(axis=0) > 1e-6, X.std(axis=0), 1.0).astype(np.float32)
+        Xn = self._norm(X)
+        y = np.asarray(y, np.float32)
+        rng = np.random.Generator(np.random.PCG64(seed))
+        hist = []
+        for ep in range(epochs):
+            perm = rng.permutation(len(y))
+            tot = 0.0
+            for i in range(0, len(y), batch):
+                idx = perm[i:i + batch]
+                tot += B.qs_mlp_train_step(self.h, Xn[idx], y[idx], lr) * len(idx)
+            hist.append(tot / len(y))
+            if log and (ep % 50 == 0 or ep == epochs - 1):
+                log(f"epoch {ep}: train mse {hist[-1]:.4f}")
+        return hist
+
+    def fit_more(self, X, y, epochs: int = 100, batch: int = 256, lr: float = 3e-4, seed: int = 1):
+        """Continue training with the current standardisation (a lower learning rate for the last epochs)."""
+        Xn = self._norm(X)
+        y = np.asarray(y, np.float32)
+        rng = np.random.Generator(np.random.PCG64(seed))
+        for _ in range(epochs):
+            perm = rng.permutation(len(y))
+            for i in range(0, len(y), batch):
+                idx = perm[i:i + batch]
+                B.qs_mlp_train_step(self.h, Xn[idx], y[idx], lr)
+
+    def predict_log_ms(self, X) -> np.ndarray:
+        X = self._norm(X)
+        out = []
+        for i in range(0, len(X), 4096):
+            out.append(B.qs_mlp_predict(self.h, X[i:i + 4096]))
+        return np.concatenate(out) if out else np.zeros(0, np.float32)
+
+    def predict_plan_ms(self, plan) -> float:
+        return float(np.exp(self.predict_log_ms(plan_features(plan)).astype(np.float64)).sum())
+
+    def save(self, path: str) -> None:
+        np.savez(path, params=B.qs_mlp_get_params(self.h), mean=self.mean, std=self.std, hidden=self.hidden,
+                 nin=NIN)
+
+    @classmethod
+    def load(cls, path: str = WEIGHTS) -> "CostModel":
+        d = np.load(path, allow_pickle=False)
+        if int(d["nin"]) != NIN:
+            raise ValueError("cost-model weights were trained for a different feature layout")
+        return cls(d["params"], d["mean"], d["std"], int(d["hidden"]))
+
+    def close(self):
+        if getattr(self, "h", None):
+            B.qs_mlp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+MARGIN = 0.03  # switch away from the greedy plan only for a predicted saving above this fraction
+
+
+def choose_plan(circuit, dtype: str = "c128", model: Optional[CostModel] = None,
+                cands: Optional[Sequence[Tuple[str, int, int]]] = None, margin: float = MARGIN):
+    """The candidate plan with the lowest predicted time, if it beats the greedy plan's prediction by more than
+    `margin`; otherwise (and without a model) the greedy plan. Returns (plan, (mode, bits, low), predicted ms)."""
+    from .plan import Plan
+    n = circuit.n
+    g = greedy_for(n)
+    if model is None:
+        return Plan(circuit, *g, dtype), g, None
+    gp = Plan(circuit, *g, dtype)
+    gt = model.predict_plan_ms(gp)
+    best = (gp, g, gt)
+    for cand in (cands or candidates(n)):
+        if cand == g:
+            continue
+        p = Plan(circuit, *cand, dtype)
+        t = model.predict_plan_ms(p)
+        if t < (1.0 - margin) * gt and t < best[2]:
+            if best[0] is not gp:
+                best[0].close()
+            best = (p, cand, t)
+        else:
+            p.close()
+    if best[0] is not gp:
+        gp.close()
+    return best
+
+
+def main():
+    ap = argparse.ArgumentParser(description="Collect pass timings on the GPU and train the cost model.")
+    ap.add_argument("--out", default=WEIGHTS)
+    ap.add_argument("--epochs", type=int, default=300)
+    ap.add_argument("--data", default=None, help="save / reuse the timing dataset (.npz)")
+    args = ap.parse_args()
+    if args.data and os.path.exists(args.data):
+        d = np.load(args.data, allow_pickle=False)
+        X, y = d["X"], d["y"]
+    else:
+        groups = []
+        X, y = collect(training_circuits(), log=lambda m: print(m, flush=True), groups=groups)
+        if args.data:
+            np.savez(args.data, X=X, y=y, groups=np.array(groups, dtype=np.int32))
+    print(f"dataset: {len(y)} passes", flush=True)
+    rng = np.random.Generator(np.random.PCG64(7))
+    perm = rng.permutation(len(y))
+    cut = int(0.85 * len(y))
+    tr, va = perm[:cut], perm[cut:]
+    m = CostModel()
+    m.fit(X[tr], y[tr], epochs=args.epochs, log=lambda s: print(s, flush=True))
+    m.fit_more(X[tr], y[tr], epochs=args.epochs // 3, lr=3e-4)
+    pv = m.predict_log_ms(X[va])
+    mse = float(np.mean((pv - y[va]) ** 2))
+    rel = float(np.median(np.abs(np.exp(pv - y[va]) - 1)))
+    print(f"validation mse(log ms) {mse:.4f}, median relative error {rel:.3f}", flush=True)
+    if "groups" in locals() or (args.data and os.path.exists(args.data)):
+        g = np.asarray(groups if "groups" in locals() else np.load(args.data)["groups"])
+        pall = np.exp(m.predict_log_ms(X).astype(np.float64))
+        tall = np.exp(np.asarray(y, np.float64))
+        agree, regret = 0, []
+        for gid in np.unique(g[:, 0]):
+            sel = g[:, 0] == gid
+            cands = np.unique(g[sel, 1])
+            pt = np.array([pall[sel & (g[:, 1] == c)].sum() for c in cands])
+            tt = np.array([tall[sel & (g[:, 1] == c)].sum() for c in cands])
+            agree += int(np.argmin(pt) == np.argmin(tt))
+            regret.append(tt[np.argmin(pt)] / tt.min() - 1)
+        print(f"plan choice: model picks the fastest candidate in {agree}/{len(regret)} circuit runs, "
+              f"mean regret {100 * np.mean(regret):.1f} %", flush=True)
+    m.save(args.out)
+    print(f"saved {args.out}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -835,6 +835,58 @@ QS_API int qs_plan_pass_info(const qs_plan *P, int i, int *type, int *nqubits, i
     return QS_OK;
 }
 
+QS_API int qs_plan_features(const qs_plan *P, int i, float *f)
+{
+    qs_clear_error();
+    if (!P || !f || i < 0 || i >= (int)P->passes.size())
+        return qs_fail(QS_EINVAL, "qs_plan_features: NULL argument or pass index out of range");
+    const PlanPass &pp = P->passes[i];
+    int type = 0, nq = 0, nops = 0, ng = 0;
+    int64_t m = 0;
+    if (int rc = qs_plan_pass_info(P, i, &type, &nq, &m, &nops, &ng))
+        return rc;
+    for (int j = 0; j < QS_PLAN_NFEAT; ++j)
+        f[j] = 0.0f;
+    f[type < 4 ? type : 3] = 1.0f;
+    f[4] = P->n / 40.0f;
+    f[5] = P->dtype == QS_C64 ? 1.0f : 0.0f;
+    f[6] = nq / 16.0f;
+    f[7] = nops / 32.0f;
+    f[8] = (pp.type == 0 ? pp.nstages : 0) / 16.0f;
+    int contig = 0;
+    while (contig < 64 && ((uint64_t)m >> contig) & 1)
+        ++contig;
+    f[9] = contig / 16.0f;
+    int lo = 0, hi = 0;
+    if (m) {
+        lo = __builtin_ctzll((uint64_t)m);
+        hi = 63 - __builtin_clzll((uint64_t)m);
+    }
+    f[10] = lo / 40.0f;
+    f[11] = hi / 40.0f;
+    f[12] = __builtin_popcountll((uint64_t)m & 15) / 4.0f;
+    f[13] = (P->n + (P->dtype == QS_C64 ? 3 : 4)) / 40.0f;  // log2 of the state's bytes
+    double flops = 0.0;                                     // per amplitude
+    if (pp.type == 0) {
+        for (int t = pp.stage_begin; t < pp.stage_begin + pp.nstages; ++t)
+            for (int o = P->stages[t].op_begin; o < P->stages[t].op_begin + P->stages[t].nops; ++o)
+                flops += 8.0 * (1 << __builtin_popcount(P->sops[o].mask));
+    } else if (pp.type == 1) {
+        flops = 8.0 * (1 << pp.k);
+    }
+    f[14] = (float)(flops / 256.0);
+    f[15] = ng / 64.0f;
+    if (pp.type == 0 && pp.b >= 10 && pp.b <= 13)
+        f[16 + pp.b - 10] = 1.0f;  // block size one-hot
+    if (pp.type == 1 && pp.k >= 3 && pp.k <= 6)
+        f[20 + pp.k - 3] = 1.0f;  // dense target count one-hot
+    f[24] = pp.type == 2 ? pp.s / 16.0f : 0.0f;
+    f[25] = contig >= 4 ? 1.0f : 0.0f;
+    for (int b = 0; b < 22; ++b)
+        f[26 + b] = ((uint64_t)m >> b) & 1 ? 1.0f : 0.0f;
+    return QS_OK;
+}
+
 QS_API int qs_plan_free(qs_plan *P)
 {
     qs_clear_error();
