@@ -221,6 +221,27 @@ QS_API int qs_mlp_grad(qs_mlp *m, const float *X, const float *T, int B, float *
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on the batch; loss before the step (nullable). */
 QS_API int qs_mlp_train_step(qs_mlp *m, const float *X, const float *T, int B, float lr, float *loss);
 
+/* ---- batches of independent circuits (serving form) ----
+ * Many circuits (8..30 qubits each, gates on at most 3 qubits, no fused-swaps) run in ONE persistent kernel
+ * launch: each workgroup takes the next circuit (longest first) from an atomic counter and runs it start to
+ * finish -- entirely in LDS for circuits of at most block_bits qubits, otherwise through the block passes of its
+ * plan over its own HBM slice -- and writes its FP64 output probabilities. No workgroup waits for another.
+ *   block_bits 10..12 (the LDS block), low_bits the always-local low qubits, wg_per_cu 1..8 persistent
+ *   workgroups per compute unit (tile and schedule parameters chosen by the autotuner). */
+typedef struct qs_batch qs_batch;
+QS_API int qs_batch_create(qs_batch **out, int dtype, int block_bits, int low_bits, int wg_per_cu, void *hip_stream);
+/* Plan and append a circuit (host only). QS_EUNSUPPORTED for circuits outside the batch's scope. */
+QS_API int qs_batch_add(qs_batch *b, const qs_circuit *c);
+/* Order the circuits (longest first), allocate state and probability slices, upload the tables (synchronous). */
+QS_API int qs_batch_finalize(qs_batch *b);
+/* Enqueue the whole batch: a counter-reset kernel and the persistent launch. use_graph != 0 captures them once into
+ * a HIP graph (no memset nodes) and replays it on later calls. Finalizes the batch if needed. */
+QS_API int qs_batch_run(qs_batch *b, int use_graph);
+QS_API int qs_batch_info(const qs_batch *b, int *ncirc, int64_t *state_bytes, int64_t *prob_count, int *npasses);
+/* Circuit i's 2^n probabilities (in the order circuits were added): device pointer and/or a synchronous copy. */
+QS_API int qs_batch_probs(qs_batch *b, int i, double **dev_ptr, double *host_out);
+QS_API int qs_batch_free(qs_batch *b);
+
 /* ---- bandwidth probes (the measured HBM ceiling the gate kernels are compared against) ---- */
 
 /* dst[i] = src[i] over `bytes` (multiple of 16, both 16-byte aligned), enqueued on hip_stream. */

@@ -76,6 +76,13 @@ SIGNATURES = {
     "qs_plan_pass_info": [_P, _I, _IP, _IP, ctypes.POINTER(ctypes.c_int64), _IP, _IP],
     "qs_plan_free": [_P],
     "qs_plan_features": [_P, _I, ctypes.POINTER(ctypes.c_float)],
+    "qs_batch_create": [ctypes.POINTER(_P), _I, _I, _I, _I, _P],
+    "qs_batch_add": [_P, _P],
+    "qs_batch_finalize": [_P],
+    "qs_batch_run": [_P, _I],
+    "qs_batch_info": [_P, _IP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), _IP],
+    "qs_batch_probs": [_P, _I, ctypes.POINTER(_P), _DP],
+    "qs_batch_free": [_P],
     "qs_mlp_create": [ctypes.POINTER(_P), _I, _I, _P],
     "qs_mlp_free": [_P],
     "qs_mlp_num_params": [_P, _IP],
@@ -370,3 +377,47 @@ def qs_mlp_train_step(m: int, X, T, lr: float) -> float:
     _check(lib().qs_mlp_train_step(m, X.ctypes.data_as(_FP), T.ctypes.data_as(_FP), X.shape[0], float(lr),
                                    ctypes.byref(loss)), "qs_mlp_train_step")
     return loss.value
+
+
+# ------------------------------------------------------------------------------------------------ batches
+
+def qs_batch_create(dtype: int = QS_C128, block_bits: int = 12, low_bits: int = 4, wg_per_cu: int = 2,
+                    hip_stream: Optional[int] = None) -> int:
+    h = _P()
+    _check(lib().qs_batch_create(ctypes.byref(h), int(dtype), int(block_bits), int(low_bits), int(wg_per_cu),
+                                 hip_stream), "qs_batch_create")
+    return h.value
+
+
+def qs_batch_add(b: int, c: int) -> None:
+    _check(lib().qs_batch_add(b, c), "qs_batch_add")
+
+
+def qs_batch_finalize(b: int) -> None:
+    _check(lib().qs_batch_finalize(b), "qs_batch_finalize")
+
+
+def qs_batch_run(b: int, use_graph: bool = False) -> None:
+    _check(lib().qs_batch_run(b, 1 if use_graph else 0), "qs_batch_run")
+
+
+def qs_batch_info(b: int):
+    n, sb, pc, npass = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
+    _check(lib().qs_batch_info(b, ctypes.byref(n), ctypes.byref(sb), ctypes.byref(pc), ctypes.byref(npass)),
+           "qs_batch_info")
+    return {"circuits": n.value, "state_bytes": sb.value, "prob_count": pc.value, "passes": npass.value}
+
+
+def qs_batch_probs(b: int, i: int, n: Optional[int] = None):
+    """Device pointer of circuit i's probabilities; with n given, also a host copy of its 2^n values."""
+    p = _P()
+    out = None
+    if n is not None:
+        out = np.empty(1 << int(n), dtype=np.float64)
+    _check(lib().qs_batch_probs(b, int(i), ctypes.byref(p), _dptr(out) if out is not None else None),
+           "qs_batch_probs")
+    return p.value, out
+
+
+def qs_batch_free(b: int) -> None:
+    _check(lib().qs_batch_free(b), "qs_batch_free")

@@ -146,6 +146,36 @@ __device__ __forceinline__ void run_stage(typename BT<R>::C2 *s, const BlkStage 
     }
 }
 
+// The same stage for a block of 2^nb amplitudes, nb <= B chosen at run time (whole small circuits held in LDS).
+template <class R>
+__device__ __forceinline__ void run_stage_n(typename BT<R>::C2 *s, const BlkStage &stg,
+                                            const BlkStageOp *__restrict__ sops, const R *__restrict__ mats, int nb)
+{
+    using C2 = typename BT<R>::C2;
+    const int ng = (1 << nb) >> 4;
+    uint32_t off[16];
+#pragma unroll
+    for (int a = 0; a < 16; ++a)
+        off[a] = ((a & 1) << stg.pos[0]) | (((a >> 1) & 1) << stg.pos[1]) | (((a >> 2) & 1) << stg.pos[2]) |
+                 (((a >> 3) & 1) << stg.pos[3]);
+    for (int g = threadIdx.x; g < ng; g += blockDim.x) {
+        uint32_t m = 0;
+        for (int j = 0; j < nb - 4; ++j)
+            m |= (((uint32_t)g >> j) & 1u) << stg.order[j];
+        C2 x[16];
+#pragma unroll
+        for (int a = 0; a < 16; ++a)
+            x[a] = s[swz(m + off[a])];
+        for (int o = 0; o < stg.nops; ++o) {
+            const BlkStageOp op = sops[stg.op_begin + o];
+            reg_op_dispatch<R>(x, op.mask, mats + op.mat_off);
+        }
+#pragma unroll
+        for (int a = 0; a < 16; ++a)
+            s[swz(m + off[a])] = x[a];
+    }
+}
+
 template <class R, int B>
 __global__ __launch_bounds__(256) void k_block(typename BT<R>::C2 *__restrict__ psi, uint64_t nblocks, InsBits outer,
                                                BlockMap bm, const BlkStage *__restrict__ stages, int nstages,
@@ -208,6 +238,141 @@ __global__ __launch_bounds__(256) void k_block(typename BT<R>::C2 *__restrict__ 
     }
 }
 
+// Batched circuits in one persistent launch. Each workgroup repeatedly takes the next circuit (longest first) from
+// an atomic counter and runs it alone, start to finish: a circuit of at most B qubits is initialised, evolved and
+// turned into FP64 probabilities entirely in LDS; a larger one is initialised in its HBM slice and evolved by the
+// block passes of its plan (the workgroup walks all blocks of a pass; a full workgroup barrier with a memory fence
+// separates passes), then its probabilities are written. Every workgroup leaves the loop once the counter passes
+// the number of circuits; no workgroup waits for another.
+template <class R, int B>
+__global__ __launch_bounds__(256) void k_batch(typename BT<R>::C2 *__restrict__ psi_base, double *__restrict__ prob_base,
+                                               const BatchCirc *__restrict__ circs, const int *__restrict__ order,
+                                               int ncirc, int *__restrict__ counter,
+                                               const BatchPass *__restrict__ passes,
+                                               const BlkStage *__restrict__ stages,
+                                               const BlkStageOp *__restrict__ sops, const R *__restrict__ mats)
+{
+    using C2 = typename BT<R>::C2;
+    extern __shared__ __align__(16) unsigned char smem_blk[];
+    C2 *s = reinterpret_cast<C2 *>(smem_blk);
+    __shared__ int job_sh;
+    constexpr int PER = (1 << B) / 256;
+    for (;;) {
+        if (threadIdx.x == 0)
+            job_sh = atomicAdd(counter, 1);
+        __syncthreads();
+        const int job = job_sh;
+        __syncthreads();
+        if (job >= ncirc)
+            break;
+        const BatchCirc c = circs[order[job]];
+        double *out = prob_base + c.prob_off;
+        const uint32_t N = 1u << c.n;
+        if (c.n <= B) {
+            for (uint32_t m = threadIdx.x; m < N; m += blockDim.x) {
+                C2 v;
+                v.x = m == 0 ? (R)1 : (R)0;
+                v.y = 0;
+                s[swz(m)] = v;
+            }
+            lds_barrier();
+            for (int p = 0; p < c.npass; ++p) {
+                const BatchPass &bp = passes[c.pass_begin + p];
+                for (int t = 0; t < bp.nstages; ++t) {
+                    run_stage_n<R>(s, stages[bp.stage_begin + t], sops, mats, c.n);
+                    lds_barrier();
+                }
+            }
+            for (uint32_t m = threadIdx.x; m < N; m += blockDim.x) {
+                const C2 v = s[swz(m)];
+                const double re = (double)v.x, im = (double)v.y;
+                out[m] = re * re + im * im;
+            }
+            lds_barrier();
+            continue;
+        }
+        C2 *psi = psi_base + c.state_off;
+        for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) {
+            C2 v;
+            v.x = i == 0 ? (R)1 : (R)0;
+            v.y = 0;
+            psi[i] = v;
+        }
+        __syncthreads();
+        const uint32_t nblk = 1u << (c.n - B);
+        for (int p = 0; p < c.npass; ++p) {
+            const BatchPass &bp = passes[c.pass_begin + p];
+            const uint64_t own = spread(threadIdx.x, bp.bm);
+            for (uint32_t blk = 0; blk < nblk; ++blk) {
+                const uint64_t base = ins0b(blk, bp.outer) | own;
+#pragma unroll
+                for (int it = 0; it < PER; ++it)
+                    s[swz(threadIdx.x + 256 * it)] = psi[base + spread((uint32_t)(256 * it), bp.bm)];
+                lds_barrier();
+                for (int t = 0; t < bp.nstages; ++t) {
+                    run_stage<R, B>(s, stages[bp.stage_begin + t], sops, mats);
+                    lds_barrier();
+                }
+#pragma unroll
+                for (int it = 0; it < PER; ++it)
+                    psi[base + spread((uint32_t)(256 * it), bp.bm)] = s[swz(threadIdx.x + 256 * it)];
+                lds_barrier();
+            }
+            __syncthreads();  // the next pass reads what other threads of this workgroup wrote
+        }
+        for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) {
+            const C2 v = psi[i];
+            const double re = (double)v.x, im = (double)v.y;
+            out[i] = re * re + im * im;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_reset_counter(int *counter) { *counter = 0; }
+
+template <class R, int B>
+hipError_t batch_b(void *psi, double *probs, const BatchCirc *circs, const int *order, int ncirc, int *counter,
+                   const BatchPass *passes, const BlkStage *stages, const BlkStageOp *sops, const void *mats,
+                   int wg_per_cu, hipStream_t s)
+{
+    using C2 = typename BT<R>::C2;
+    const size_t shm = sizeof(C2) << B;
+    static bool attr_set = false;
+    if (!attr_set && shm > 65536) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_batch<R, B>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)shm);
+        if (e != hipSuccess)
+            return e;
+        attr_set = true;
+    }
+    int cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        cus = 256;
+    unsigned grid = (unsigned)(cus * wg_per_cu);
+    if ((int)grid > ncirc)
+        grid = (unsigned)ncirc;
+    if (grid == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
+    hipLaunchKernelGGL((k_batch<R, B>), dim3(grid), dim3(256), shm, s, (C2 *)psi, probs, circs, order, ncirc, counter,
+                       passes, stages, sops, (const R *)mats);
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t batch_r(int b, void *psi, double *probs, const BatchCirc *circs, const int *order, int ncirc, int *counter,
+                   const BatchPass *passes, const BlkStage *stages, const BlkStageOp *sops, const void *mats,
+                   int wg_per_cu, hipStream_t s)
+{
+    switch (b) {
+    case 10: return batch_b<R, 10>(psi, probs, circs, order, ncirc, counter, passes, stages, sops, mats, wg_per_cu, s);
+    case 11: return batch_b<R, 11>(psi, probs, circs, order, ncirc, counter, passes, stages, sops, mats, wg_per_cu, s);
+    case 12: return batch_b<R, 12>(psi, probs, circs, order, ncirc, counter, passes, stages, sops, mats, wg_per_cu, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <class R, int B>
 hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm, const BlkStage *stages,
                    int nstages, const BlkStageOp *sops, const void *mats, hipStream_t s)
@@ -250,6 +415,16 @@ hipError_t block_r(int b, void *psi, uint64_t nblocks, const InsBits &outer, con
 }
 
 }  // namespace
+
+hipError_t launch_batch(int dtype, int b, void *psi, double *probs, const BatchCirc *circs, const int *order, int ncirc,
+                        int *counter, const BatchPass *passes, const BlkStage *stages, const BlkStageOp *sops,
+                        const void *mats, int wg_per_cu, hipStream_t s)
+{
+    return dtype == QS_C128 ? batch_r<double>(b, psi, probs, circs, order, ncirc, counter, passes, stages, sops, mats,
+                                              wg_per_cu, s)
+                            : batch_r<float>(b, psi, probs, circs, order, ncirc, counter, passes, stages, sops, mats,
+                                             wg_per_cu, s);
+}
 
 hipError_t launch_block(int dtype, int b, void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm,
                         const BlkStage *stages_dev, int nstages, const BlkStageOp *sops_dev, const void *mats_dev,

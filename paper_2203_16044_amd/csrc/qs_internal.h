@@ -140,6 +140,22 @@ hipError_t launch_block(int dtype, int b, void *psi, uint64_t nblocks, const Ins
                         const BlkStage *stages_dev, int nstages, const BlkStageOp *sops_dev, const void *mats_dev,
                         hipStream_t s);
 
+// batched circuits: one persistent launch, one workgroup per circuit (see qs_block.hip)
+struct BatchCirc {
+    uint64_t state_off;  // amplitude offset of the circuit's state (unused when it lives in LDS)
+    uint64_t prob_off;   // offset of its 2^n FP64 probabilities
+    int n;
+    int pass_begin, npass;
+};
+struct BatchPass {
+    InsBits outer;  // block number -> base index (zeros at the local positions)
+    BlockMap bm;
+    int stage_begin, nstages;
+};
+hipError_t launch_batch(int dtype, int b, void *psi, double *probs, const BatchCirc *circs, const int *order, int ncirc,
+                        int *counter, const BatchPass *passes, const BlkStage *stages, const BlkStageOp *sops,
+                        const void *mats, int wg_per_cu, hipStream_t s);
+
 hipError_t launch_probe_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 hipError_t launch_probe_rmw(void *buf, size_t bytes, hipStream_t s);
 

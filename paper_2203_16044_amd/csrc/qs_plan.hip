@@ -903,3 +903,266 @@ QS_API int qs_plan_free(qs_plan *P)
 }
 
 }  // extern "C"
+
+// ============================================================================================================
+// batches: many circuits, one persistent launch (optionally replayed from a captured HIP graph)
+// ============================================================================================================
+struct qs_batch {
+    int dtype = QS_C128, b = 12, low = 4, wg_per_cu = 2;
+    hipStream_t stream = nullptr;
+    std::vector<BatchCirc> circs;
+    std::vector<int> nops;  // fused ops per circuit (schedule cost)
+    std::vector<BatchPass> passes;
+    std::vector<BlkStage> stages;
+    std::vector<BlkStageOp> sops;
+    std::vector<double> pool;
+    std::vector<int> order;
+    uint64_t state_amps = 0, prob_count = 0;
+    bool finalized = false;
+    void *psi = nullptr;
+    double *probs = nullptr;
+    BatchCirc *dcircs = nullptr;
+    int *dorder = nullptr, *counter = nullptr;
+    BatchPass *dpasses = nullptr;
+    BlkStage *dstages = nullptr;
+    BlkStageOp *dsops = nullptr;
+    void *dmats = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+void batch_release(qs_batch *Bt)
+{
+    if (!Bt)
+        return;
+    (void)hipStreamSynchronize(Bt->stream);
+    if (Bt->exec)
+        (void)hipGraphExecDestroy(Bt->exec);
+    if (Bt->graph)
+        (void)hipGraphDestroy(Bt->graph);
+    void *bufs[] = {Bt->psi, Bt->probs, Bt->dcircs, Bt->dorder, Bt->counter, Bt->dpasses, Bt->dstages, Bt->dsops,
+                    Bt->dmats};
+    for (void *p : bufs)
+        if (p)
+            (void)hipFree(p);
+    delete Bt;
+}
+
+template <class T> int upload_vec(T **dst, const std::vector<T> &v)
+{
+    QS_HIP(hipMalloc((void **)dst, std::max<size_t>(v.size(), 1) * sizeof(T)));
+    if (!v.empty())
+        QS_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return QS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+QS_API int qs_batch_create(qs_batch **out, int dtype, int block_bits, int low_bits, int wg_per_cu, void *hip_stream)
+{
+    qs_clear_error();
+    if (!out)
+        return qs_fail(QS_EINVAL, "qs_batch_create: out is NULL");
+    *out = nullptr;
+    if (dtype != QS_C128 && dtype != QS_C64)
+        return qs_fail(QS_EINVAL, "qs_batch_create: bad dtype %d", dtype);
+    if (block_bits < 10 || block_bits > 12)
+        return qs_fail(QS_EINVAL, "qs_batch_create: block_bits = %d outside [10, 12]", block_bits);
+    if (low_bits < 0 || low_bits > block_bits || wg_per_cu < 1 || wg_per_cu > 8)
+        return qs_fail(QS_EINVAL, "qs_batch_create: low_bits or wg_per_cu out of range");
+    qs_batch *Bt = new (std::nothrow) qs_batch();
+    if (!Bt)
+        return qs_fail(QS_ENOMEM, "qs_batch_create: out of host memory");
+    Bt->dtype = dtype;
+    Bt->b = block_bits;
+    Bt->low = low_bits;
+    Bt->wg_per_cu = wg_per_cu;
+    Bt->stream = (hipStream_t)hip_stream;
+    *out = Bt;
+    return QS_OK;
+}
+
+QS_API int qs_batch_add(qs_batch *Bt, const qs_circuit *c)
+{
+    qs_clear_error();
+    if (!Bt || !c)
+        return qs_fail(QS_EINVAL, "qs_batch_add: NULL argument");
+    if (Bt->finalized)
+        return qs_fail(QS_EINVAL, "qs_batch_add: the batch is finalized");
+    if (c->n < 8 || c->n > 30)
+        return qs_fail(QS_EINVAL, "qs_batch_add: circuits of %d qubits are outside [8, 30]", c->n);
+    const int bb = std::min(c->n, Bt->b);
+    qs_plan_opts o{QS_PLAN_BLOCK, bb, std::min(Bt->low, bb), Bt->dtype};
+    qs_plan *P = nullptr;
+    if (int rc = qs_plan_create(&P, c, &o))
+        return rc;
+    for (const PlanPass &pp : P->passes)
+        if (pp.type != 0) {
+            qs_plan_free(P);
+            return qs_fail(QS_EUNSUPPORTED, "qs_batch_add: batched circuits may hold gates on at most 3 qubits and "
+                                            "no fused-swaps (pass of type %d)", pp.type);
+        }
+    BatchCirc bc{};
+    bc.n = c->n;
+    bc.pass_begin = (int)Bt->passes.size();
+    bc.npass = (int)P->passes.size();
+    bc.prob_off = Bt->prob_count;
+    Bt->prob_count += (uint64_t)1 << c->n;
+    if (c->n > Bt->b) {
+        bc.state_off = Bt->state_amps;
+        Bt->state_amps += (uint64_t)1 << c->n;
+    }
+    const int s0 = (int)Bt->stages.size(), o0 = (int)Bt->sops.size();
+    const uint32_t m0 = (uint32_t)Bt->pool.size();
+    for (const PlanPass &pp : P->passes) {
+        BatchPass bp{};
+        bp.outer = qs_make_ins(pp.lmask, 0);
+        bp.bm = pp.bm;
+        bp.stage_begin = s0 + pp.stage_begin;
+        bp.nstages = pp.nstages;
+        Bt->passes.push_back(bp);
+    }
+    for (BlkStage st : P->stages) {
+        st.op_begin += o0;
+        Bt->stages.push_back(st);
+    }
+    for (BlkStageOp so : P->sops) {
+        so.mat_off += m0;
+        Bt->sops.push_back(so);
+    }
+    Bt->pool.insert(Bt->pool.end(), P->pool.begin(), P->pool.end());
+    int fused = 0;
+    for (const PlanPass &pp : P->passes)
+        fused += pp.nops;
+    Bt->nops.push_back(fused);
+    Bt->circs.push_back(bc);
+    qs_plan_free(P);
+    return QS_OK;
+}
+
+QS_API int qs_batch_finalize(qs_batch *Bt)
+{
+    qs_clear_error();
+    if (!Bt)
+        return qs_fail(QS_EINVAL, "qs_batch_finalize: NULL batch");
+    if (Bt->finalized)
+        return QS_OK;
+    if (Bt->pool.size() >= ((size_t)1 << 32))
+        return qs_fail(QS_EUNSUPPORTED, "qs_batch_finalize: matrix pool too large");
+    // longest first: HBM passes and in-LDS arithmetic, both proportional to the state size
+    std::vector<double> cost(Bt->circs.size());
+    for (size_t i = 0; i < Bt->circs.size(); ++i) {
+        const BatchCirc &c = Bt->circs[i];
+        cost[i] = std::ldexp(1.0, c.n) * ((c.n > Bt->b ? 4.0 * c.npass : 0.0) + 0.25 * Bt->nops[i]);
+    }
+    Bt->order.resize(Bt->circs.size());
+    for (size_t i = 0; i < Bt->order.size(); ++i)
+        Bt->order[i] = (int)i;
+    std::stable_sort(Bt->order.begin(), Bt->order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    const size_t esz = Bt->dtype == QS_C128 ? 16 : 8;
+    QS_HIP(hipMalloc(&Bt->psi, std::max<uint64_t>(Bt->state_amps, 1) * esz));
+    QS_HIP(hipMalloc((void **)&Bt->probs, std::max<uint64_t>(Bt->prob_count, 1) * sizeof(double)));
+    QS_HIP(hipMalloc((void **)&Bt->counter, sizeof(int)));
+    if (int rc = upload_vec(&Bt->dcircs, Bt->circs))
+        return rc;
+    if (int rc = upload_vec(&Bt->dorder, Bt->order))
+        return rc;
+    if (int rc = upload_vec(&Bt->dpasses, Bt->passes))
+        return rc;
+    if (int rc = upload_vec(&Bt->dstages, Bt->stages))
+        return rc;
+    if (int rc = upload_vec(&Bt->dsops, Bt->sops))
+        return rc;
+    if (Bt->dtype == QS_C128) {
+        double *d = nullptr;
+        if (int rc = upload_vec(&d, Bt->pool))
+            return rc;
+        Bt->dmats = d;
+    } else {
+        std::vector<float> f(Bt->pool.begin(), Bt->pool.end());
+        float *d = nullptr;
+        if (int rc = upload_vec(&d, f))
+            return rc;
+        Bt->dmats = d;
+    }
+    Bt->finalized = true;
+    return QS_OK;
+}
+
+QS_API int qs_batch_run(qs_batch *Bt, int use_graph)
+{
+    qs_clear_error();
+    if (!Bt)
+        return qs_fail(QS_EINVAL, "qs_batch_run: NULL batch");
+    if (!Bt->finalized)
+        if (int rc = qs_batch_finalize(Bt))
+            return rc;
+    auto enqueue = [&]() {
+        return launch_batch(Bt->dtype, Bt->b, Bt->psi, Bt->probs, Bt->dcircs, Bt->dorder, (int)Bt->circs.size(),
+                            Bt->counter, Bt->dpasses, Bt->dstages, Bt->dsops, Bt->dmats, Bt->wg_per_cu, Bt->stream);
+    };
+    if (!use_graph) {
+        QS_HIP(enqueue());
+        return QS_OK;
+    }
+    if (!Bt->exec) {
+        QS_HIP(hipStreamBeginCapture(Bt->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = enqueue();
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(Bt->stream, &g);
+        if (e != hipSuccess)
+            return qs_hip_fail(e, "batch launch during capture");
+        QS_HIP(e2);
+        Bt->graph = g;
+        QS_HIP(hipGraphInstantiate(&Bt->exec, Bt->graph, nullptr, nullptr, 0));
+    }
+    QS_HIP(hipGraphLaunch(Bt->exec, Bt->stream));
+    return QS_OK;
+}
+
+QS_API int qs_batch_info(const qs_batch *Bt, int *ncirc, int64_t *state_bytes, int64_t *prob_count, int *npasses)
+{
+    qs_clear_error();
+    if (!Bt)
+        return qs_fail(QS_EINVAL, "qs_batch_info: NULL batch");
+    if (ncirc)
+        *ncirc = (int)Bt->circs.size();
+    if (state_bytes)
+        *state_bytes = (int64_t)(Bt->state_amps * (Bt->dtype == QS_C128 ? 16 : 8));
+    if (prob_count)
+        *prob_count = (int64_t)Bt->prob_count;
+    if (npasses)
+        *npasses = (int)Bt->passes.size();
+    return QS_OK;
+}
+
+QS_API int qs_batch_probs(qs_batch *Bt, int i, double **dev_ptr, double *host_out)
+{
+    qs_clear_error();
+    if (!Bt || i < 0 || i >= (int)Bt->circs.size())
+        return qs_fail(QS_EINVAL, "qs_batch_probs: NULL batch or circuit index out of range");
+    if (!Bt->finalized)
+        return qs_fail(QS_EINVAL, "qs_batch_probs: the batch has not run");
+    const BatchCirc &c = Bt->circs[i];
+    if (dev_ptr)
+        *dev_ptr = Bt->probs + c.prob_off;
+    if (host_out) {
+        QS_HIP(hipStreamSynchronize(Bt->stream));
+        QS_HIP(hipMemcpy(host_out, Bt->probs + c.prob_off, ((size_t)1 << c.n) * sizeof(double),
+                         hipMemcpyDeviceToHost));
+    }
+    return QS_OK;
+}
+
+QS_API int qs_batch_free(qs_batch *Bt)
+{
+    qs_clear_error();
+    if (!Bt)
+        return qs_fail(QS_EINVAL, "qs_batch_free: NULL batch");
+    batch_release(Bt);
+    return QS_OK;
+}
+
+}  // extern "C"

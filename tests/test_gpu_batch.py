@@ -1,0 +1,84 @@
+"""Batched serving form: many circuits in one persistent launch (and its captured-graph replays) against the
+oracle and the per-circuit plain path."""
+import numpy as np
+import pytest
+import torch
+
+import circuits as C
+import oracle
+from paper_2203_16044_amd import batch as BT
+
+pytestmark = pytest.mark.gpu
+
+
+def _oracle_probs(circ):
+    P, _ = oracle.probs(oracle.run(circ))
+    return P
+
+
+@pytest.mark.parametrize("params", [{"block_bits": 12, "low_bits": 4, "wg_per_cu": 2},
+                                    {"block_bits": 10, "low_bits": 3, "wg_per_cu": 1},
+                                    {"block_bits": 11, "low_bits": 4, "wg_per_cu": 4}])
+def test_batch_matches_oracle(gpu, params):
+    circs = C.config4(count=24, seed=77, nmin=10, nmax=16, dmin=4, dmax=12)
+    b = BT.Batch(circs, "c128", **params)
+    b.run()
+    for i, circ in enumerate(circs):
+        assert np.max(np.abs(b.probs(i) - _oracle_probs(circ))) <= 1e-12, (i, circ.n)
+    b.close()
+
+
+def test_batch_complex64_error(gpu):
+    circs = C.config4(count=12, seed=78, nmin=10, nmax=15, dmin=4, dmax=10)
+    b = BT.Batch(circs, "c64")
+    b.run()
+    worst = 0.0
+    for i, circ in enumerate(circs):
+        P = b.probs(i)
+        worst = max(worst, float(np.max(np.abs(P - _oracle_probs(circ)))))
+        assert abs(P.sum() - 1.0) <= 1e-5
+    assert worst <= 1e-5, worst
+    b.close()
+
+
+def test_graph_replays_match_eager(gpu):
+    circs = C.config4(count=40, seed=79, nmin=10, nmax=18, dmin=4, dmax=10)
+    b = BT.Batch(circs, "c128")
+    b.run(graph=False)
+    ref = [b.probs(i).copy() for i in range(len(circs))]
+    x = torch.ones(1 << 20, dtype=torch.float64, device="cuda")
+    for rep in range(3):
+        b.run(graph=True)
+        x.mul_(1.0000001)  # unrelated eager work between replays
+        b.sync()
+        torch.cuda.synchronize()
+        for i in range(len(circs)):
+            assert b.probs(i).tobytes() == ref[i].tobytes(), (rep, i)
+    b.close()
+
+
+def test_full_512_circuit_batch_against_plain_loop(gpu):
+    """The 512-circuit workload (10..22 qubits, 10..40 layers): every output is a distribution, and sampled circuits
+    match the per-circuit plain path (itself checked against the oracle) to 1e-12."""
+    circs = C.config4()
+    b = BT.Batch(circs, "c128")
+    b.run(graph=True)
+    b.sync()
+    sample = list(range(0, 512, 37)) + [int(np.argmax([c.n for c in circs]))]
+    _, plain = BT.plain_loop([circs[i] for i in sample], "c128", keep=range(len(sample)))
+    for j, i in enumerate(sample):
+        P = b.probs(i)
+        assert abs(P.sum() - 1.0) <= 1e-12
+        assert np.max(np.abs(P - plain[j])) <= 1e-12, (i, circs[i].n)
+    sums = [b.probs(i).sum() for i in range(0, 512, 5)]
+    assert max(abs(s - 1.0) for s in sums) <= 1e-12
+    b.close()
+
+
+def test_autotuner_picks_a_measured_candidate(gpu, tmp_path):
+    circs = C.config4(count=20, seed=80, nmin=10, nmax=16, dmin=4, dmax=8)
+    space = [{"block_bits": 10, "low_bits": 3, "wg_per_cu": 1}, {"block_bits": 12, "low_bits": 4, "wg_per_cu": 2}]
+    best, times = BT.autotune(circs, "c128", cache=str(tmp_path / "cache.json"), space=space)
+    assert best in space and len(times) == 2
+    best2, _ = BT.autotune(circs, "c128", cache=str(tmp_path / "cache.json"), space=space)
+    assert best2 == best  # served from the cache

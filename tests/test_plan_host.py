@@ -73,3 +73,26 @@ def test_circuit_add_validates():
     with pytest.raises(B.QSError):
         B.qs_circuit_add_fused_swap(c.h, 0, 1, 2)
     assert len(c) == 0
+
+
+def test_batch_host_validation():
+    """Batch creation and planning are host-only: argument checks and scope checks need no GPU."""
+    with pytest.raises(B.QSError):
+        B.qs_batch_create(B.QS_C128, 13, 4, 2)
+    with pytest.raises(B.QSError):
+        B.qs_batch_create(B.QS_C128, 12, 4, 9)
+    b = B.qs_batch_create(B.QS_C128, 12, 4, 2)
+    small = Circuit.from_ops(6, C.random_circuit(6, 1, num_ops=10, kmax=2, kinds=("dense",)).ops)
+    with pytest.raises(B.QSError) as ei:
+        B.qs_batch_add(b, small.h)
+    assert ei.value.code == B.QS_EINVAL
+    swapping = Circuit.from_ops(16, C.config0(n=16).ops)  # holds a fused-swap
+    with pytest.raises(B.QSError) as ei:
+        B.qs_batch_add(b, swapping.h)
+    assert ei.value.code == B.QS_EUNSUPPORTED
+    keep = [Circuit.from_ops(circ.n, circ.ops) for circ in C.config4(count=6, nmax=15)]
+    for c in keep:
+        B.qs_batch_add(b, c.h)
+    info = B.qs_batch_info(b)
+    assert info["circuits"] == 6 and info["prob_count"] == sum(1 << c.n for c in C.config4(count=6, nmax=15))
+    B.qs_batch_free(b)
