@@ -12,6 +12,10 @@ oracle timed on the host's cores over a bounded sample of the same circuit.
 
 Modes: "plain" applies the circuit gate by gate (one HBM pass per gate); "tuned" runs the fused plan (see
 paper_2203_16044_amd.plan) and also reports plain on a prefix of the circuit for the speedup.
+
+Further legs in the same JSON line: "c64" (the 33-qubit complex64 circuit of the same family with FP64
+renormalisation every 10 layers, and the complex64 error at 24 qubits) and "batch" (512 small circuits in one
+persistent launch, autotuned, eager and graph-replayed, against the per-circuit plain loop).
 """
 import argparse
 import json
@@ -134,6 +138,94 @@ def cpu_baseline(circ, budget_s, torch):
             "seconds": round(dt, 2)}
 
 
+def bench_c64(head_rate, steps, torch):
+    """complex64 engine: the 33-qubit circuit of the same family (64 GiB state, as large as the 32-qubit complex128
+    one) through the block plan with FP64 renormalisation after layers 10/20/30/40, and its error on the 24-qubit
+    run against the complex128 path."""
+    import numpy as np
+
+    import circuits as C
+    import paper_2203_16044_amd as qs
+    from paper_2203_16044_amd.plan import Circuit, Plan, SegmentedPlan
+
+    circ = C.config3()
+    st = qs.State(circ.n, "c64")
+    sp = SegmentedPlan(circ.n, circ.ops, circ.renorm_after, "block", 12, 4, "c64")
+    mk = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
+    st.init_zero()
+    sp.run(st)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(steps):
+        e0, e1 = mk(), mk()
+        e0.record(st.stream)
+        st.init_zero()
+        sp.run(st)
+        qs.binding.qs_probs(st.h, None, False)
+        e1.record(st.stream)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    nrm = st.norm()
+    info = sp.info()
+    sp.close()
+    st.close()
+    del st
+    torch.cuda.empty_cache()
+    t = sum(times) / len(times)
+    # error of the complex64 engine on the 24-qubit run, against the complex128 path
+    e = C.config3_error_run()
+    a = qs.State(e.n, "c64")
+    sp = SegmentedPlan(e.n, e.ops, e.renorm_after, "block", 12, 4, "c64")
+    sp.run(a)
+    b = qs.State(e.n, "c128")
+    c = Circuit.from_ops(e.n, e.ops)
+    p = Plan(c, "block", 12, 4, "c128")
+    p.run(b)
+    x, y = a.get().astype(np.complex128), b.get()
+    infid = max(0.0, 1.0 - abs(np.vdot(y, x)) ** 2 / (np.vdot(x, x).real * np.vdot(y, y).real))
+    maxd = float(np.max(np.abs(x - y)))
+    for h in (sp, p, c, a, b):
+        h.close()
+    return {"workload": f"random SU(4)+U3 circuit, n={circ.n}, 40 layers, {len(circ.ops)} gates, complex64, "
+                        f"renormalised after layers {list(circ.renorm_after)} (seed 33)",
+            "gates_per_s": len(circ.ops) / t, "ms_per_step": t * 1e3, "passes": info["passes"],
+            "renormalisations": info["renormalisations"], "norm_after": nrm,
+            "gates_per_s_vs_c128_headline": len(circ.ops) / t / head_rate,
+            "error_24q": {"infidelity": infid, "max_abs_amp_diff": maxd,
+                          "against": "complex128 path (n=24, 40 layers, seed 24)"}}
+
+
+def bench_batch(torch, log):
+    """Batched serving form: 512 independent circuits (10..22 qubits, 10..40 layers) in one persistent launch,
+    autotuned, eager and replayed from a HIP graph, against the per-circuit plain loop."""
+    import circuits as C
+    from paper_2203_16044_amd import batch as BT
+
+    circs = C.config4()
+    rec = BT.record(circs)
+    out = {"workload": "512 circuits, n ~ U{10..22}, depth ~ U{10..40} (U3 / CNOT-or-CZ / RZ layers, seed 512), "
+                       "FP64 probabilities of every circuit", "circuits": len(circs),
+           "gates": sum(len(c.ops) for c in circs)}
+    for dt in ("c128", "c64"):
+        t0 = time.perf_counter()
+        best, times = BT.autotune(rec, dt, log=log)
+        tune_s = time.perf_counter() - t0
+        b = BT.Batch(rec, dt, **best)
+        t_eager = BT.time_batch(b, graph=False, reps=3)
+        t_graph = BT.time_batch(b, graph=True, reps=3)
+        b.close()
+        out[dt] = {"params": best, "circuits_per_s_graph": len(circs) / t_graph,
+                   "circuits_per_s_eager": len(circs) / t_eager, "ms_graph": t_graph * 1e3,
+                   "ms_eager": t_eager * 1e3, "autotune_s": round(tune_s, 1),
+                   "autotune_ms": {k: round(v * 1e3, 3) for k, v in times.items()}}
+        t_plain, _ = BT.plain_loop(circs, dt)
+        out[dt]["plain_loop_circuits_per_s"] = len(circs) / t_plain
+        out[dt]["speedup_vs_plain_loop"] = t_plain / t_graph
+    for c in rec:
+        c.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -149,6 +241,8 @@ def main():
     ap.add_argument("--compare-fuse", type=int, nargs="*", default=[4, 6], help="fused-dense plans also timed")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-c64", action="store_true", help="skip the 33-qubit complex64 leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-circuit batched leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the gate path is single-GPU (multi-GPU sharding is a design note only). "
@@ -171,6 +265,8 @@ def main():
     st = qs.State(n, "c128")
     t_wall = time.perf_counter()
 
+    log0 = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    log0("bench: plain leg")
     # plain: one pass per gate (on a prefix of the circuit in tuned mode: the per-gate rate is layer-invariant)
     plain_ops = ops if args.mode == "plain" else [o for o in ops if o.layer <= args.plain_layers]
     units = [(_kernel_class(o), _alg_bytes(o, n, 16)) for o in plain_ops]
@@ -195,6 +291,7 @@ def main():
                                                                                           args.compare_fuse]
                                if v != head_v]
         for vi, (mode, bits, low) in enumerate(variants):
+            log0(f"bench: plan {mode} {bits} {low}")
             plan = Plan(cc, mode, bits, low, "c128")
             info = plan.info()
             passes = plan.passes()
@@ -260,8 +357,17 @@ def main():
         "norm_after": nrm,
         "wall_s": wall,
     }
+    log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    if not args.no_c64:
+        log("bench: complex64 leg")
+        out["c64"] = bench_c64(gates / t_step, 1, torch)
+    if not args.no_batch:
+        log("bench: batched leg")
+        out["batch"] = bench_batch(torch, log)
     if not args.no_cpu_baseline:
+        log("bench: cpu baseline")
         out["cpu_baseline"] = cpu_baseline(circ, args.cpu_seconds, torch)
+    out["wall_s"] = time.perf_counter() - t_wall
     print(json.dumps(out), flush=True)
 
 

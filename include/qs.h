@@ -222,22 +222,28 @@ QS_API int qs_mlp_grad(qs_mlp *m, const float *X, const float *T, int B, float *
 QS_API int qs_mlp_train_step(qs_mlp *m, const float *X, const float *T, int B, float lr, float *loss);
 
 /* ---- batches of independent circuits (serving form) ----
- * Many circuits (8..30 qubits each, gates on at most 3 qubits, no fused-swaps) run in ONE persistent kernel
- * launch: each workgroup takes the next circuit (longest first) from an atomic counter and runs it start to
- * finish -- entirely in LDS for circuits of at most block_bits qubits, otherwise through the block passes of its
- * plan over its own HBM slice -- and writes its FP64 output probabilities. No workgroup waits for another.
+ * Many circuits (8..30 qubits each, gates on at most 3 qubits, no fused-swaps) run as one short sequence of
+ * persistent launches, one per pass level: launch k runs pass k of every circuit that has more than k block passes,
+ * all of their blocks forming one index space that the whole grid walks (so a large circuit is spread over every
+ * compute unit). Circuits of at most block_bits qubits run start to finish inside one workgroup's LDS during the
+ * first launch. Every circuit starts in |0..0>, generated in the first pass, and its last pass writes its FP64
+ * output probabilities instead of amplitudes.
  *   block_bits 10..12 (the LDS block), low_bits the always-local low qubits, wg_per_cu 1..8 persistent
  *   workgroups per compute unit (tile and schedule parameters chosen by the autotuner). */
 typedef struct qs_batch qs_batch;
 QS_API int qs_batch_create(qs_batch **out, int dtype, int block_bits, int low_bits, int wg_per_cu, void *hip_stream);
 /* Plan and append a circuit (host only). QS_EUNSUPPORTED for circuits outside the batch's scope. */
 QS_API int qs_batch_add(qs_batch *b, const qs_circuit *c);
-/* Order the circuits (longest first), allocate state and probability slices, upload the tables (synchronous). */
+/* Build the pass levels, allocate state and probability slices, upload the tables (synchronous). QS_EUNSUPPORTED if
+ * one level would exceed 2^31 blocks. */
 QS_API int qs_batch_finalize(qs_batch *b);
-/* Enqueue the whole batch: a counter-reset kernel and the persistent launch. use_graph != 0 captures them once into
- * a HIP graph (no memset nodes) and replays it on later calls. Finalizes the batch if needed. */
+/* Enqueue the whole batch (one launch per level) on the batch's stream. use_graph != 0 captures the launches once
+ * into a HIP graph (kernel nodes only) and replays it on later calls. Finalizes the batch if needed. */
 QS_API int qs_batch_run(qs_batch *b, int use_graph);
-QS_API int qs_batch_info(const qs_batch *b, int *ncirc, int64_t *state_bytes, int64_t *prob_count, int *npasses);
+/* Any output may be NULL: circuits, bytes of HBM state, FP64 probabilities, block passes, levels (0 before
+ * finalize). */
+QS_API int qs_batch_info(const qs_batch *b, int *ncirc, int64_t *state_bytes, int64_t *prob_count, int *npasses,
+                         int *nlevels);
 /* Circuit i's 2^n probabilities (in the order circuits were added): device pointer and/or a synchronous copy. */
 QS_API int qs_batch_probs(qs_batch *b, int i, double **dev_ptr, double *host_out);
 QS_API int qs_batch_free(qs_batch *b);

@@ -24,7 +24,14 @@ DEFAULT = {"block_bits": 12, "low_bits": 4, "wg_per_cu": 2}
 SPACE = [{"block_bits": b, "low_bits": w, "wg_per_cu": g} for b in (10, 11, 12) for w in (3, 4) for g in (1, 2, 4)]
 
 
+def record(circuits) -> List[Circuit]:
+    """Record gate-list circuits in the library once, so several batches (autotuner candidates) can share them."""
+    return [c if isinstance(c, Circuit) else Circuit.from_ops(c.n, c.ops) for c in circuits]
+
+
 class Batch:
+    """`circuits` holds gate-list circuits or already recorded library circuits (the batch copies what it needs)."""
+
     def __init__(self, circuits, dtype: str = "c128", block_bits: int = 12, low_bits: int = 4, wg_per_cu: int = 2,
                  stream=None):
         import torch
@@ -36,9 +43,12 @@ class Batch:
         self.params = {"block_bits": block_bits, "low_bits": low_bits, "wg_per_cu": wg_per_cu}
         self.h = B.qs_batch_create(self.qs_dtype, block_bits, low_bits, wg_per_cu, self.stream.cuda_stream)
         for circ in circuits:
-            c = Circuit.from_ops(circ.n, circ.ops)
-            B.qs_batch_add(self.h, c.h)
-            c.close()
+            if isinstance(circ, Circuit):
+                B.qs_batch_add(self.h, circ.h)
+            else:
+                c = Circuit.from_ops(circ.n, circ.ops)
+                B.qs_batch_add(self.h, c.h)
+                c.close()
         B.qs_batch_finalize(self.h)
 
     def run(self, graph: bool = False) -> None:
@@ -82,7 +92,8 @@ def time_batch(batch: Batch, graph: bool = False, reps: int = 3) -> float:
 
 
 def signature(circuits, dtype: str) -> str:
-    key = dtype + ":" + ",".join(f"{c.n}/{len(c.ops)}" for c in sorted(circuits, key=lambda c: (c.n, len(c.ops))))
+    sizes = sorted((c.n, len(c.ops) if hasattr(c, "ops") else len(c)) for c in circuits)
+    key = dtype + ":" + ",".join(f"{n}/{g}" for n, g in sizes)
     return hashlib.sha1(key.encode()).hexdigest()
 
 
@@ -100,8 +111,9 @@ def autotune(circuits, dtype: str = "c128", cache: Optional[str] = CACHE, space:
     if sig in data:
         return data[sig]["best"], data[sig]["times"]
     times = {}
+    recorded = record(circuits)
     for cand in (space or SPACE):
-        b = Batch(circuits, dtype, **cand)
+        b = Batch(recorded, dtype, **cand)
         t = time_batch(b, reps=2)
         b.close()
         times[json.dumps(cand, sort_keys=True)] = t
@@ -125,7 +137,7 @@ def plain_loop(circuits, dtype: str = "c128", keep: Iterable[int] = ()) -> Tuple
     from .state import State
     keep = set(keep)
     s = torch.cuda.current_stream()
-    handles = [Circuit.from_ops(c.n, c.ops) for c in circuits]
+    handles = [Circuit.from_ops(c.n, c.ops) for c in circuits]  # recorded before the timed region
     states = {}
     out = {}
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

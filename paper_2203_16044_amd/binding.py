@@ -80,7 +80,7 @@ SIGNATURES = {
     "qs_batch_add": [_P, _P],
     "qs_batch_finalize": [_P],
     "qs_batch_run": [_P, _I],
-    "qs_batch_info": [_P, _IP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), _IP],
+    "qs_batch_info": [_P, _IP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), _IP, _IP],
     "qs_batch_probs": [_P, _I, ctypes.POINTER(_P), _DP],
     "qs_batch_free": [_P],
     "qs_mlp_create": [ctypes.POINTER(_P), _I, _I, _P],
@@ -402,10 +402,11 @@ def qs_batch_run(b: int, use_graph: bool = False) -> None:
 
 
 def qs_batch_info(b: int):
-    n, sb, pc, npass = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int()
-    _check(lib().qs_batch_info(b, ctypes.byref(n), ctypes.byref(sb), ctypes.byref(pc), ctypes.byref(npass)),
-           "qs_batch_info")
-    return {"circuits": n.value, "state_bytes": sb.value, "prob_count": pc.value, "passes": npass.value}
+    n, sb, pc, npass, nlev = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int(), ctypes.c_int()
+    _check(lib().qs_batch_info(b, ctypes.byref(n), ctypes.byref(sb), ctypes.byref(pc), ctypes.byref(npass),
+                               ctypes.byref(nlev)), "qs_batch_info")
+    return {"circuits": n.value, "state_bytes": sb.value, "prob_count": pc.value, "passes": npass.value,
+            "levels": nlev.value}
 
 
 def qs_batch_probs(b: int, i: int, n: Optional[int] = None):

@@ -238,101 +238,152 @@ __global__ __launch_bounds__(256) void k_block(typename BT<R>::C2 *__restrict__ 
     }
 }
 
-// Batched circuits in one persistent launch. Each workgroup repeatedly takes the next circuit (longest first) from
-// an atomic counter and runs it alone, start to finish: a circuit of at most B qubits is initialised, evolved and
-// turned into FP64 probabilities entirely in LDS; a larger one is initialised in its HBM slice and evolved by the
-// block passes of its plan (the workgroup walks all blocks of a pass; a full workgroup barrier with a memory fence
-// separates passes), then its probabilities are written. Every workgroup leaves the loop once the counter passes
-// the number of circuits; no workgroup waits for another.
+// Batched circuits, level by level. A batch runs as a short sequence of persistent launches; launch k ("level k")
+// executes pass k of every circuit that has more than k passes, all of those passes' blocks forming one flat index
+// space that the whole grid walks, so a large circuit is spread over every CU instead of one workgroup. The items of
+// a level are sorted by their first flat block; a workgroup finds the item of block g by binary search.
+//   * a SMALL item (level 0 only, placed first) is a whole circuit of at most B qubits: one workgroup initialises,
+//     evolves and measures it in LDS (FP64 probabilities written straight from LDS);
+//   * any other item is one pass over a circuit of more than B qubits held in HBM: its FIRST pass generates the
+//     basis state |0..0> in registers instead of reading it, its LAST pass writes |amp|^2 in FP64 instead of the
+//     amplitudes. Passes of one circuit are ordered by the launch boundaries between levels.
+// As in k_block, the next block's loads are issued before the current block's stages run.
+__device__ __forceinline__ int find_item(const BatchItem *__restrict__ items, int nitems, uint32_t g)
+{
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].blk_begin <= g)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
 template <class R, int B>
-__global__ __launch_bounds__(256) void k_batch(typename BT<R>::C2 *__restrict__ psi_base, double *__restrict__ prob_base,
-                                               const BatchCirc *__restrict__ circs, const int *__restrict__ order,
-                                               int ncirc, int *__restrict__ counter,
-                                               const BatchPass *__restrict__ passes,
-                                               const BlkStage *__restrict__ stages,
-                                               const BlkStageOp *__restrict__ sops, const R *__restrict__ mats)
+__device__ __forceinline__ void batch_small(typename BT<R>::C2 *s, const BatchItem &it, double *__restrict__ prob_base,
+                                            const BatchPass *__restrict__ passes, const BlkStage *__restrict__ stages,
+                                            const BlkStageOp *__restrict__ sops, const R *__restrict__ mats)
 {
     using C2 = typename BT<R>::C2;
-    extern __shared__ __align__(16) unsigned char smem_blk[];
-    C2 *s = reinterpret_cast<C2 *>(smem_blk);
-    __shared__ int job_sh;
+    const uint32_t N = 1u << it.n;
+    for (uint32_t m = threadIdx.x; m < N; m += blockDim.x) {
+        C2 v;
+        v.x = m == 0 ? (R)1 : (R)0;
+        v.y = 0;
+        s[swz(m)] = v;
+    }
+    lds_barrier();
+    for (int p = 0; p < it.npass; ++p) {
+        const BatchPass &bp = passes[it.pass + p];
+        for (int t = 0; t < bp.nstages; ++t) {
+            run_stage_n<R>(s, stages[bp.stage_begin + t], sops, mats, it.n);
+            lds_barrier();
+        }
+    }
+    double *out = prob_base + it.prob_off;
+    for (uint32_t m = threadIdx.x; m < N; m += blockDim.x) {
+        const C2 v = s[swz(m)];
+        const double re = (double)v.x, im = (double)v.y;
+        out[m] = re * re + im * im;
+    }
+    lds_barrier();
+}
+
+template <class R, int B>
+__device__ __forceinline__ void batch_fetch(typename NT2<R>::type *pre, const typename BT<R>::C2 *__restrict__ psi,
+                                            uint64_t base, const BlockMap &bm, bool first)
+{
+    using NV = typename NT2<R>::type;
     constexpr int PER = (1 << B) / 256;
-    for (;;) {
-        if (threadIdx.x == 0)
-            job_sh = atomicAdd(counter, 1);
-        __syncthreads();
-        const int job = job_sh;
-        __syncthreads();
-        if (job >= ncirc)
-            break;
-        const BatchCirc c = circs[order[job]];
-        double *out = prob_base + c.prob_off;
-        const uint32_t N = 1u << c.n;
-        if (c.n <= B) {
-            for (uint32_t m = threadIdx.x; m < N; m += blockDim.x) {
-                C2 v;
-                v.x = m == 0 ? (R)1 : (R)0;
-                v.y = 0;
-                s[swz(m)] = v;
-            }
-            lds_barrier();
-            for (int p = 0; p < c.npass; ++p) {
-                const BatchPass &bp = passes[c.pass_begin + p];
-                for (int t = 0; t < bp.nstages; ++t) {
-                    run_stage_n<R>(s, stages[bp.stage_begin + t], sops, mats, c.n);
-                    lds_barrier();
-                }
-            }
-            for (uint32_t m = threadIdx.x; m < N; m += blockDim.x) {
-                const C2 v = s[swz(m)];
-                const double re = (double)v.x, im = (double)v.y;
-                out[m] = re * re + im * im;
-            }
-            lds_barrier();
-            continue;
-        }
-        C2 *psi = psi_base + c.state_off;
-        for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) {
-            C2 v;
-            v.x = i == 0 ? (R)1 : (R)0;
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+        const uint64_t idx = base + spread((uint32_t)(256 * it), bm);
+        if (first) {
+            NV v;
+            v.x = idx == 0 ? (R)1 : (R)0;
             v.y = 0;
-            psi[i] = v;
+            pre[it] = v;
+        } else {
+            pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(psi + idx));
         }
-        __syncthreads();
-        const uint32_t nblk = 1u << (c.n - B);
-        for (int p = 0; p < c.npass; ++p) {
-            const BatchPass &bp = passes[c.pass_begin + p];
-            const uint64_t own = spread(threadIdx.x, bp.bm);
-            for (uint32_t blk = 0; blk < nblk; ++blk) {
-                const uint64_t base = ins0b(blk, bp.outer) | own;
-#pragma unroll
-                for (int it = 0; it < PER; ++it)
-                    s[swz(threadIdx.x + 256 * it)] = psi[base + spread((uint32_t)(256 * it), bp.bm)];
-                lds_barrier();
-                for (int t = 0; t < bp.nstages; ++t) {
-                    run_stage<R, B>(s, stages[bp.stage_begin + t], sops, mats);
-                    lds_barrier();
-                }
-#pragma unroll
-                for (int it = 0; it < PER; ++it)
-                    psi[base + spread((uint32_t)(256 * it), bp.bm)] = s[swz(threadIdx.x + 256 * it)];
-                lds_barrier();
-            }
-            __syncthreads();  // the next pass reads what other threads of this workgroup wrote
-        }
-        for (uint32_t i = threadIdx.x; i < N; i += blockDim.x) {
-            const C2 v = psi[i];
-            const double re = (double)v.x, im = (double)v.y;
-            out[i] = re * re + im * im;
-        }
-        __syncthreads();
     }
 }
 
-__global__ void k_reset_counter(int *counter) { *counter = 0; }
+template <class R, int B>
+__global__ __launch_bounds__(256) void k_batch_level(typename BT<R>::C2 *__restrict__ psi_base,
+                                                     double *__restrict__ prob_base,
+                                                     const BatchItem *__restrict__ items, int nitems, uint32_t nblocks,
+                                                     const BatchPass *__restrict__ passes,
+                                                     const BlkStage *__restrict__ stages,
+                                                     const BlkStageOp *__restrict__ sops, const R *__restrict__ mats)
+{
+    using C2 = typename BT<R>::C2;
+    using NV = typename NT2<R>::type;
+    extern __shared__ __align__(16) unsigned char smem_blk[];
+    C2 *s = reinterpret_cast<C2 *>(smem_blk);
+    constexpr int PER = (1 << B) / 256;
+    NV pre[PER];
+    bool have = false;  // pre[] holds the loads of block g
+    for (uint32_t g = blockIdx.x; g < nblocks; g += gridDim.x) {
+        const BatchItem it = items[find_item(items, nitems, g)];
+        if (it.flags & kBatchSmall) {
+            batch_small<R, B>(s, it, prob_base, passes, stages, sops, mats);
+            continue;
+        }
+        const BatchPass &bp = passes[it.pass];
+        C2 *psi = psi_base + it.state_off;
+        const uint64_t own = spread(threadIdx.x, bp.bm);
+        const uint64_t base = ins0b(g - it.blk_begin, bp.outer) | own;
+        if (!have)
+            batch_fetch<R, B>(pre, psi, base, bp.bm, (it.flags & kBatchFirst) != 0);
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            C2 v;
+            v.x = pre[k].x;
+            v.y = pre[k].y;
+            s[swz(threadIdx.x + 256 * k)] = v;
+        }
+        lds_barrier();
+        // items after a non-small item are non-small: prefetch the next block of this workgroup
+        have = false;
+        const uint32_t nx = g + gridDim.x;
+        if (nx < nblocks) {
+            const BatchItem nt = items[find_item(items, nitems, nx)];
+            const BatchPass &np = passes[nt.pass];
+            const uint64_t nbase = ins0b(nx - nt.blk_begin, np.outer) | spread(threadIdx.x, np.bm);
+            batch_fetch<R, B>(pre, psi_base + nt.state_off, nbase, np.bm, (nt.flags & kBatchFirst) != 0);
+            have = true;
+        }
+        for (int t = 0; t < bp.nstages; ++t) {
+            run_stage<R, B>(s, stages[bp.stage_begin + t], sops, mats);
+            lds_barrier();
+        }
+        if (it.flags & kBatchLast) {
+            double *out = prob_base + it.prob_off;
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const C2 v = s[swz(threadIdx.x + 256 * k)];
+                const double re = (double)v.x, im = (double)v.y;
+                out[base + spread((uint32_t)(256 * k), bp.bm)] = re * re + im * im;
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const C2 v = s[swz(threadIdx.x + 256 * k)];
+                NV w;
+                w.x = v.x;
+                w.y = v.y;
+                __builtin_nontemporal_store(w, reinterpret_cast<NV *>(psi + base + spread((uint32_t)(256 * k), bp.bm)));
+            }
+        }
+        lds_barrier();
+    }
+}
 
 template <class R, int B>
-hipError_t batch_b(void *psi, double *probs, const BatchCirc *circs, const int *order, int ncirc, int *counter,
+hipError_t batch_b(void *psi, double *probs, const BatchItem *items, int nitems, uint32_t nblocks,
                    const BatchPass *passes, const BlkStage *stages, const BlkStageOp *sops, const void *mats,
                    int wg_per_cu, hipStream_t s)
 {
@@ -340,8 +391,8 @@ hipError_t batch_b(void *psi, double *probs, const BatchCirc *circs, const int *
     const size_t shm = sizeof(C2) << B;
     static bool attr_set = false;
     if (!attr_set && shm > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_batch<R, B>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)shm);
+        hipError_t e = hipFuncSetAttribute((const void *)k_batch_level<R, B>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess)
             return e;
         attr_set = true;
@@ -349,26 +400,25 @@ hipError_t batch_b(void *psi, double *probs, const BatchCirc *circs, const int *
     int cus = 0, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
-    unsigned grid = (unsigned)(cus * wg_per_cu);
-    if ((int)grid > ncirc)
-        grid = (unsigned)ncirc;
+    uint64_t grid = (uint64_t)cus * wg_per_cu;
+    if (grid > nblocks)
+        grid = nblocks;
     if (grid == 0)
         return hipSuccess;
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
-    hipLaunchKernelGGL((k_batch<R, B>), dim3(grid), dim3(256), shm, s, (C2 *)psi, probs, circs, order, ncirc, counter,
-                       passes, stages, sops, (const R *)mats);
+    hipLaunchKernelGGL((k_batch_level<R, B>), dim3((unsigned)grid), dim3(256), shm, s, (C2 *)psi, probs, items, nitems,
+                       nblocks, passes, stages, sops, (const R *)mats);
     return hipGetLastError();
 }
 
 template <class R>
-hipError_t batch_r(int b, void *psi, double *probs, const BatchCirc *circs, const int *order, int ncirc, int *counter,
+hipError_t batch_r(int b, void *psi, double *probs, const BatchItem *items, int nitems, uint32_t nblocks,
                    const BatchPass *passes, const BlkStage *stages, const BlkStageOp *sops, const void *mats,
                    int wg_per_cu, hipStream_t s)
 {
     switch (b) {
-    case 10: return batch_b<R, 10>(psi, probs, circs, order, ncirc, counter, passes, stages, sops, mats, wg_per_cu, s);
-    case 11: return batch_b<R, 11>(psi, probs, circs, order, ncirc, counter, passes, stages, sops, mats, wg_per_cu, s);
-    case 12: return batch_b<R, 12>(psi, probs, circs, order, ncirc, counter, passes, stages, sops, mats, wg_per_cu, s);
+    case 10: return batch_b<R, 10>(psi, probs, items, nitems, nblocks, passes, stages, sops, mats, wg_per_cu, s);
+    case 11: return batch_b<R, 11>(psi, probs, items, nitems, nblocks, passes, stages, sops, mats, wg_per_cu, s);
+    case 12: return batch_b<R, 12>(psi, probs, items, nitems, nblocks, passes, stages, sops, mats, wg_per_cu, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -416,13 +466,13 @@ hipError_t block_r(int b, void *psi, uint64_t nblocks, const InsBits &outer, con
 
 }  // namespace
 
-hipError_t launch_batch(int dtype, int b, void *psi, double *probs, const BatchCirc *circs, const int *order, int ncirc,
-                        int *counter, const BatchPass *passes, const BlkStage *stages, const BlkStageOp *sops,
-                        const void *mats, int wg_per_cu, hipStream_t s)
+hipError_t launch_batch_level(int dtype, int b, void *psi, double *probs, const BatchItem *items, int nitems,
+                              uint32_t nblocks, const BatchPass *passes, const BlkStage *stages, const BlkStageOp *sops,
+                              const void *mats, int wg_per_cu, hipStream_t s)
 {
-    return dtype == QS_C128 ? batch_r<double>(b, psi, probs, circs, order, ncirc, counter, passes, stages, sops, mats,
+    return dtype == QS_C128 ? batch_r<double>(b, psi, probs, items, nitems, nblocks, passes, stages, sops, mats,
                                               wg_per_cu, s)
-                            : batch_r<float>(b, psi, probs, circs, order, ncirc, counter, passes, stages, sops, mats,
+                            : batch_r<float>(b, psi, probs, items, nitems, nblocks, passes, stages, sops, mats,
                                              wg_per_cu, s);
 }
 

@@ -140,7 +140,7 @@ hipError_t launch_block(int dtype, int b, void *psi, uint64_t nblocks, const Ins
                         const BlkStage *stages_dev, int nstages, const BlkStageOp *sops_dev, const void *mats_dev,
                         hipStream_t s);
 
-// batched circuits: one persistent launch, one workgroup per circuit (see qs_block.hip)
+// batched circuits: one persistent launch per pass level (see qs_block.hip)
 struct BatchCirc {
     uint64_t state_off;  // amplitude offset of the circuit's state (unused when it lives in LDS)
     uint64_t prob_off;   // offset of its 2^n FP64 probabilities
@@ -152,9 +152,22 @@ struct BatchPass {
     BlockMap bm;
     int stage_begin, nstages;
 };
-hipError_t launch_batch(int dtype, int b, void *psi, double *probs, const BatchCirc *circs, const int *order, int ncirc,
-                        int *counter, const BatchPass *passes, const BlkStage *stages, const BlkStageOp *sops,
-                        const void *mats, int wg_per_cu, hipStream_t s);
+// one work item of a level: a whole small circuit in LDS, or one pass of a circuit held in HBM
+constexpr int kBatchFirst = 1;  // first pass: generate |0..0> instead of reading the state
+constexpr int kBatchLast = 2;   // last pass: write FP64 probabilities instead of amplitudes
+constexpr int kBatchSmall = 4;  // whole circuit of at most B qubits, one workgroup, in LDS
+struct BatchItem {
+    uint64_t state_off;  // amplitude offset of the circuit's HBM state
+    uint64_t prob_off;   // offset of its 2^n FP64 probabilities
+    uint32_t blk_begin;  // first flat block of the item within its level (small items take one block)
+    int pass;            // global index of the item's pass (small: of its first pass)
+    int npass;           // small: number of passes; otherwise 1
+    int n;
+    int flags;
+};
+hipError_t launch_batch_level(int dtype, int b, void *psi, double *probs, const BatchItem *items, int nitems,
+                              uint32_t nblocks, const BatchPass *passes, const BlkStage *stages, const BlkStageOp *sops,
+                              const void *mats, int wg_per_cu, hipStream_t s);
 
 hipError_t launch_probe_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 hipError_t launch_probe_rmw(void *buf, size_t bytes, hipStream_t s);

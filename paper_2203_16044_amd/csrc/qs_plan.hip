@@ -916,13 +916,14 @@ struct qs_batch {
     std::vector<BlkStage> stages;
     std::vector<BlkStageOp> sops;
     std::vector<double> pool;
-    std::vector<int> order;
+    std::vector<BatchItem> items;      // all levels, level after level
+    std::vector<int> level_begin;      // items of level k: [level_begin[k], level_begin[k + 1])
+    std::vector<uint32_t> level_blocks;
     uint64_t state_amps = 0, prob_count = 0;
     bool finalized = false;
     void *psi = nullptr;
     double *probs = nullptr;
-    BatchCirc *dcircs = nullptr;
-    int *dorder = nullptr, *counter = nullptr;
+    BatchItem *ditems = nullptr;
     BatchPass *dpasses = nullptr;
     BlkStage *dstages = nullptr;
     BlkStageOp *dsops = nullptr;
@@ -941,8 +942,7 @@ void batch_release(qs_batch *Bt)
         (void)hipGraphExecDestroy(Bt->exec);
     if (Bt->graph)
         (void)hipGraphDestroy(Bt->graph);
-    void *bufs[] = {Bt->psi, Bt->probs, Bt->dcircs, Bt->dorder, Bt->counter, Bt->dpasses, Bt->dstages, Bt->dsops,
-                    Bt->dmats};
+    void *bufs[] = {Bt->psi, Bt->probs, Bt->ditems, Bt->dpasses, Bt->dstages, Bt->dsops, Bt->dmats};
     for (void *p : bufs)
         if (p)
             (void)hipFree(p);
@@ -1024,6 +1024,18 @@ QS_API int qs_batch_add(qs_batch *Bt, const qs_circuit *c)
         bp.nstages = pp.nstages;
         Bt->passes.push_back(bp);
     }
+    if (P->passes.empty() && c->n > Bt->b) {
+        // a circuit held in HBM needs one pass to initialise and measure its state: an empty one over the low qubits
+        BatchPass bp{};
+        bp.outer = qs_make_ins(((uint64_t)1 << Bt->b) - 1, 0);
+        bp.bm.b = Bt->b;
+        for (int t = 0; t < Bt->b; ++t)
+            bp.bm.lpos[t] = t;
+        bp.stage_begin = s0;
+        bp.nstages = 0;
+        Bt->passes.push_back(bp);
+        bc.npass = 1;
+    }
     for (BlkStage st : P->stages) {
         st.op_begin += o0;
         Bt->stages.push_back(st);
@@ -1051,23 +1063,54 @@ QS_API int qs_batch_finalize(qs_batch *Bt)
         return QS_OK;
     if (Bt->pool.size() >= ((size_t)1 << 32))
         return qs_fail(QS_EUNSUPPORTED, "qs_batch_finalize: matrix pool too large");
-    // longest first: HBM passes and in-LDS arithmetic, both proportional to the state size
-    std::vector<double> cost(Bt->circs.size());
-    for (size_t i = 0; i < Bt->circs.size(); ++i) {
+    // Level k holds pass k of every circuit kept in HBM; level 0 also holds the circuits that live in LDS, costliest
+    // first, ahead of all blocks so that they start at once.
+    std::vector<int> small, large;
+    int nlev = 0;
+    for (int i = 0; i < (int)Bt->circs.size(); ++i) {
         const BatchCirc &c = Bt->circs[i];
-        cost[i] = std::ldexp(1.0, c.n) * ((c.n > Bt->b ? 4.0 * c.npass : 0.0) + 0.25 * Bt->nops[i]);
+        if (c.n <= Bt->b) {
+            small.push_back(i);
+            nlev = std::max(nlev, 1);
+        } else {
+            large.push_back(i);
+            nlev = std::max(nlev, c.npass);
+        }
     }
-    Bt->order.resize(Bt->circs.size());
-    for (size_t i = 0; i < Bt->order.size(); ++i)
-        Bt->order[i] = (int)i;
-    std::stable_sort(Bt->order.begin(), Bt->order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::stable_sort(small.begin(), small.end(), [&](int a, int b) {
+        return std::ldexp(1.0 + Bt->nops[a], Bt->circs[a].n) > std::ldexp(1.0 + Bt->nops[b], Bt->circs[b].n);
+    });
+    std::stable_sort(large.begin(), large.end(), [&](int a, int b) { return Bt->circs[a].n > Bt->circs[b].n; });
+    Bt->items.clear();
+    Bt->level_begin.clear();
+    Bt->level_blocks.clear();
+    for (int lev = 0; lev < nlev; ++lev) {
+        Bt->level_begin.push_back((int)Bt->items.size());
+        uint64_t blk = 0;
+        if (lev == 0)
+            for (int i : small) {
+                const BatchCirc &c = Bt->circs[i];
+                Bt->items.push_back(BatchItem{0, c.prob_off, (uint32_t)blk, c.pass_begin, c.npass, c.n, kBatchSmall});
+                blk += 1;
+            }
+        for (int i : large) {
+            const BatchCirc &c = Bt->circs[i];
+            if (c.npass <= lev)
+                continue;
+            const int flags = (lev == 0 ? kBatchFirst : 0) | (lev == c.npass - 1 ? kBatchLast : 0);
+            Bt->items.push_back(BatchItem{c.state_off, c.prob_off, (uint32_t)blk, c.pass_begin + lev, 1, c.n, flags});
+            blk += (uint64_t)1 << (c.n - Bt->b);
+        }
+        if (blk >= ((uint64_t)1 << 31))
+            return qs_fail(QS_EUNSUPPORTED, "qs_batch_finalize: %llu blocks in one level exceed 2^31",
+                           (unsigned long long)blk);
+        Bt->level_blocks.push_back((uint32_t)blk);
+    }
+    Bt->level_begin.push_back((int)Bt->items.size());
     const size_t esz = Bt->dtype == QS_C128 ? 16 : 8;
     QS_HIP(hipMalloc(&Bt->psi, std::max<uint64_t>(Bt->state_amps, 1) * esz));
     QS_HIP(hipMalloc((void **)&Bt->probs, std::max<uint64_t>(Bt->prob_count, 1) * sizeof(double)));
-    QS_HIP(hipMalloc((void **)&Bt->counter, sizeof(int)));
-    if (int rc = upload_vec(&Bt->dcircs, Bt->circs))
-        return rc;
-    if (int rc = upload_vec(&Bt->dorder, Bt->order))
+    if (int rc = upload_vec(&Bt->ditems, Bt->items))
         return rc;
     if (int rc = upload_vec(&Bt->dpasses, Bt->passes))
         return rc;
@@ -1100,8 +1143,15 @@ QS_API int qs_batch_run(qs_batch *Bt, int use_graph)
         if (int rc = qs_batch_finalize(Bt))
             return rc;
     auto enqueue = [&]() {
-        return launch_batch(Bt->dtype, Bt->b, Bt->psi, Bt->probs, Bt->dcircs, Bt->dorder, (int)Bt->circs.size(),
-                            Bt->counter, Bt->dpasses, Bt->dstages, Bt->dsops, Bt->dmats, Bt->wg_per_cu, Bt->stream);
+        for (size_t lev = 0; lev + 1 < Bt->level_begin.size(); ++lev) {
+            const int i0 = Bt->level_begin[lev], i1 = Bt->level_begin[lev + 1];
+            hipError_t e = launch_batch_level(Bt->dtype, Bt->b, Bt->psi, Bt->probs, Bt->ditems + i0, i1 - i0,
+                                              Bt->level_blocks[lev], Bt->dpasses, Bt->dstages, Bt->dsops, Bt->dmats,
+                                              Bt->wg_per_cu, Bt->stream);
+            if (e != hipSuccess)
+                return e;
+        }
+        return hipSuccess;
     };
     if (!use_graph) {
         QS_HIP(enqueue());
@@ -1122,7 +1172,8 @@ QS_API int qs_batch_run(qs_batch *Bt, int use_graph)
     return QS_OK;
 }
 
-QS_API int qs_batch_info(const qs_batch *Bt, int *ncirc, int64_t *state_bytes, int64_t *prob_count, int *npasses)
+QS_API int qs_batch_info(const qs_batch *Bt, int *ncirc, int64_t *state_bytes, int64_t *prob_count, int *npasses,
+                         int *nlevels)
 {
     qs_clear_error();
     if (!Bt)
@@ -1135,6 +1186,8 @@ QS_API int qs_batch_info(const qs_batch *Bt, int *ncirc, int64_t *state_bytes, i
         *prob_count = (int64_t)Bt->prob_count;
     if (npasses)
         *npasses = (int)Bt->passes.size();
+    if (nlevels)
+        *nlevels = Bt->finalized ? (int)Bt->level_blocks.size() : 0;
     return QS_OK;
 }
 

@@ -83,3 +83,48 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+class SegmentedPlan:
+    """A circuit planned in segments that end at given layers, with the state renormalised (FP64 norm, FP64
+    factor) after each of those layers -- the complex64 cadence. Segments are planned independently."""
+
+    def __init__(self, n: int, ops, renorm_after, mode: str = "block", block_bits: int = 12, low_bits: int = 4,
+                 dtype: str = "c64"):
+        marks = sorted(set(renorm_after))
+        self.n = n
+        self.parts = []
+        ops = list(ops)
+        # split after the last op of each renormalisation layer (ops are in layer order)
+        segs, start = [], 0
+        for L in marks:
+            idx = [i for i, o in enumerate(ops) if o.layer <= L]
+            end = (max(idx) + 1) if idx else start
+            if end > start:
+                segs.append((ops[start:end], True))
+                start = end
+        if start < len(ops):
+            segs.append((ops[start:], False))
+        for seg, renorm in segs:
+            c = Circuit.from_ops(n, seg)
+            self.parts.append((c, Plan(c, mode, block_bits, low_bits, dtype), renorm))
+
+    def info(self) -> dict:
+        tot = {}
+        for _, p, _ in self.parts:
+            for k, v in p.info().items():
+                tot[k] = tot.get(k, 0) + v
+        tot["renormalisations"] = sum(1 for _, _, r in self.parts if r)
+        return tot
+
+    def run(self, state) -> None:
+        for _, p, renorm in self.parts:
+            p.run(state)
+            if renorm:
+                B.qs_renormalize(state.h, False)
+
+    def close(self) -> None:
+        for c, p, _ in self.parts:
+            p.close()
+            c.close()
+        self.parts = []
