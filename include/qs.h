@@ -232,6 +232,9 @@ QS_API int qs_mlp_train_step(qs_mlp *m, const float *X, const float *T, int B, f
  *   workgroups per compute unit (tile and schedule parameters chosen by the autotuner). */
 typedef struct qs_batch qs_batch;
 QS_API int qs_batch_create(qs_batch **out, int dtype, int block_bits, int low_bits, int wg_per_cu, void *hip_stream);
+/* Change the persistent workgroups per CU (1..8) of later runs; a captured graph is dropped (the call waits for the
+ * batch's stream first) and captured again by the next graph run. Host-side only otherwise. */
+QS_API int qs_batch_set_launch(qs_batch *b, int wg_per_cu);
 /* Plan and append a circuit (host only). QS_EUNSUPPORTED for circuits outside the batch's scope. */
 QS_API int qs_batch_add(qs_batch *b, const qs_circuit *c);
 /* Build the pass levels, allocate state and probability slices, upload the tables (synchronous). QS_EUNSUPPORTED if

@@ -51,6 +51,10 @@ class Batch:
                 c.close()
         B.qs_batch_finalize(self.h)
 
+    def set_launch(self, wg_per_cu: int) -> None:
+        B.qs_batch_set_launch(self.h, wg_per_cu)
+        self.params["wg_per_cu"] = int(wg_per_cu)
+
     def run(self, graph: bool = False) -> None:
         B.qs_batch_run(self.h, graph)
 
@@ -112,13 +116,20 @@ def autotune(circuits, dtype: str = "c128", cache: Optional[str] = CACHE, space:
         return data[sig]["best"], data[sig]["times"]
     times = {}
     recorded = record(circuits)
+    # one planned batch per (block bits, low bits); the workgroup count only changes the launch
+    groups: Dict[Tuple[int, int], List[int]] = {}
     for cand in (space or SPACE):
-        b = Batch(recorded, dtype, **cand)
-        t = time_batch(b, reps=2)
+        groups.setdefault((cand["block_bits"], cand["low_bits"]), []).append(cand["wg_per_cu"])
+    for (bb, lb), wgs in groups.items():
+        b = Batch(recorded, dtype, bb, lb, wgs[0])
+        for wg in wgs:
+            b.set_launch(wg)
+            t = time_batch(b, reps=2)
+            cand = {"block_bits": bb, "low_bits": lb, "wg_per_cu": wg}
+            times[json.dumps(cand, sort_keys=True)] = t
+            if log:
+                log(f"autotune {cand}: {t * 1e3:.2f} ms")
         b.close()
-        times[json.dumps(cand, sort_keys=True)] = t
-        if log:
-            log(f"autotune {cand}: {t * 1e3:.2f} ms")
     best = json.loads(min(times, key=times.get))
     if cache:
         data[sig] = {"best": best, "times": times}

@@ -83,6 +83,7 @@ SIGNATURES = {
     "qs_batch_info": [_P, _IP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), _IP, _IP],
     "qs_batch_probs": [_P, _I, ctypes.POINTER(_P), _DP],
     "qs_batch_free": [_P],
+    "qs_batch_set_launch": [_P, _I],
     "qs_mlp_create": [ctypes.POINTER(_P), _I, _I, _P],
     "qs_mlp_free": [_P],
     "qs_mlp_num_params": [_P, _IP],
@@ -387,6 +388,10 @@ def qs_batch_create(dtype: int = QS_C128, block_bits: int = 12, low_bits: int = 
     _check(lib().qs_batch_create(ctypes.byref(h), int(dtype), int(block_bits), int(low_bits), int(wg_per_cu),
                                  hip_stream), "qs_batch_create")
     return h.value
+
+
+def qs_batch_set_launch(b: int, wg_per_cu: int) -> None:
+    _check(lib().qs_batch_set_launch(b, int(wg_per_cu)), "qs_batch_set_launch")
 
 
 def qs_batch_add(b: int, c: int) -> None:

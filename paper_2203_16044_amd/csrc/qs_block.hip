@@ -114,6 +114,26 @@ __device__ __forceinline__ void reg_op_dispatch(typename BT<R>::C2 *x, int mask,
     }
 }
 
+// Byte offset in LDS of local index m. swz is linear over XOR and a group's base index m and a register offset
+// off[a] have disjoint bits, so slot(m | off[a]) = slot(m) ^ slot(off[a]): the 16 register offsets of a stage are
+// computed once per stage (uniform) and every LDS access costs one XOR.
+template <class C2>
+__device__ __forceinline__ uint32_t slot_bytes(uint32_t m) { return swz(m) * (uint32_t)sizeof(C2); }
+template <class C2>
+__device__ __forceinline__ C2 &lds_at(C2 *s, uint32_t bytes)
+{
+    return *reinterpret_cast<C2 *>(reinterpret_cast<unsigned char *>(s) + bytes);
+}
+
+template <class C2>
+__device__ __forceinline__ void stage_offsets(const BlkStage &stg, uint32_t *soff)
+{
+#pragma unroll
+    for (int a = 0; a < 16; ++a)
+        soff[a] = slot_bytes<C2>(((a & 1) << stg.pos[0]) | (((a >> 1) & 1) << stg.pos[1]) |
+                                 (((a >> 2) & 1) << stg.pos[2]) | (((a >> 3) & 1) << stg.pos[3]));
+}
+
 // One stage: every thread takes groups of 16 amplitudes (the 4 stage positions varying), applies the stage's ops
 // in registers and writes the group back.
 template <class R, int B>
@@ -122,27 +142,25 @@ __device__ __forceinline__ void run_stage(typename BT<R>::C2 *s, const BlkStage 
 {
     using C2 = typename BT<R>::C2;
     constexpr int NG = (1 << B) >> 4;
-    uint32_t off[16];
-#pragma unroll
-    for (int a = 0; a < 16; ++a)
-        off[a] = ((a & 1) << stg.pos[0]) | (((a >> 1) & 1) << stg.pos[1]) | (((a >> 2) & 1) << stg.pos[2]) |
-                 (((a >> 3) & 1) << stg.pos[3]);
+    uint32_t soff[16];
+    stage_offsets<C2>(stg, soff);
     for (int g = threadIdx.x; g < NG; g += blockDim.x) {
         uint32_t m = 0;
 #pragma unroll
         for (int j = 0; j < B - 4; ++j)
             m |= (((uint32_t)g >> j) & 1u) << stg.order[j];
+        const uint32_t sm = slot_bytes<C2>(m);
         C2 x[16];
 #pragma unroll
         for (int a = 0; a < 16; ++a)
-            x[a] = s[swz(m + off[a])];
+            x[a] = lds_at(s, sm ^ soff[a]);
         for (int o = 0; o < stg.nops; ++o) {
             const BlkStageOp op = sops[stg.op_begin + o];
             reg_op_dispatch<R>(x, op.mask, mats + op.mat_off);
         }
 #pragma unroll
         for (int a = 0; a < 16; ++a)
-            s[swz(m + off[a])] = x[a];
+            lds_at(s, sm ^ soff[a]) = x[a];
     }
 }
 
@@ -153,26 +171,24 @@ __device__ __forceinline__ void run_stage_n(typename BT<R>::C2 *s, const BlkStag
 {
     using C2 = typename BT<R>::C2;
     const int ng = (1 << nb) >> 4;
-    uint32_t off[16];
-#pragma unroll
-    for (int a = 0; a < 16; ++a)
-        off[a] = ((a & 1) << stg.pos[0]) | (((a >> 1) & 1) << stg.pos[1]) | (((a >> 2) & 1) << stg.pos[2]) |
-                 (((a >> 3) & 1) << stg.pos[3]);
+    uint32_t soff[16];
+    stage_offsets<C2>(stg, soff);
     for (int g = threadIdx.x; g < ng; g += blockDim.x) {
         uint32_t m = 0;
         for (int j = 0; j < nb - 4; ++j)
             m |= (((uint32_t)g >> j) & 1u) << stg.order[j];
+        const uint32_t sm = slot_bytes<C2>(m);
         C2 x[16];
 #pragma unroll
         for (int a = 0; a < 16; ++a)
-            x[a] = s[swz(m + off[a])];
+            x[a] = lds_at(s, sm ^ soff[a]);
         for (int o = 0; o < stg.nops; ++o) {
             const BlkStageOp op = sops[stg.op_begin + o];
             reg_op_dispatch<R>(x, op.mask, mats + op.mat_off);
         }
 #pragma unroll
         for (int a = 0; a < 16; ++a)
-            s[swz(m + off[a])] = x[a];
+            lds_at(s, sm ^ soff[a]) = x[a];
     }
 }
 
@@ -193,35 +209,33 @@ __global__ __launch_bounds__(256) void k_block(typename BT<R>::C2 *__restrict__ 
     for (int it = 0; it < PER; ++it)
         hi[it] = spread((uint32_t)(256 * it), bm);
     // Software pipeline over this workgroup's blocks: the next block's global loads are issued into registers before
-    // the current block's stages run, so HBM traffic overlaps the FP arithmetic.
+    // the current block's stages run, so HBM traffic overlaps the FP arithmetic. The loop is rotated so that wherever
+    // the prefetched registers are consumed, exactly the prefetch loads and then the previous block's stores are in
+    // flight: the wait needs only the loads (vmcnt(PER)) and the stores keep draining behind the next block's stages.
+    // The last prefetch of a workgroup re-reads its own block (one redundant block read per workgroup).
     using NV = typename NT2<R>::type;
     NV pre[PER];
     uint64_t blk = blockIdx.x;
     if (blk >= nblocks)
         return;
-    {
-        const uint64_t base = ins0b(blk, outer) | own;
+    uint64_t base = ins0b(blk, outer) | own;
+#pragma unroll
+    for (int it = 0; it < PER; ++it)
+        pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(psi + base + hi[it]));
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+        C2 v;
+        v.x = pre[it].x;
+        v.y = pre[it].y;
+        s[swz(threadIdx.x + 256 * it)] = v;
+    }
+    lds_barrier();
+    for (;;) {
+        const uint64_t nxt = blk + gridDim.x;
+        const uint64_t nbase = ins0b(nxt < nblocks ? nxt : blk, outer) | own;
 #pragma unroll
         for (int it = 0; it < PER; ++it)
-            pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(psi + base + hi[it]));
-    }
-    for (; blk < nblocks; blk += gridDim.x) {
-        const uint64_t base = ins0b(blk, outer) | own;
-#pragma unroll
-        for (int it = 0; it < PER; ++it) {
-            C2 v;
-            v.x = pre[it].x;
-            v.y = pre[it].y;
-            s[swz(threadIdx.x + 256 * it)] = v;
-        }
-        lds_barrier();
-        const uint64_t nxt = blk + gridDim.x;
-        if (nxt < nblocks) {
-            const uint64_t nbase = ins0b(nxt, outer) | own;
-#pragma unroll
-            for (int it = 0; it < PER; ++it)
-                pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(psi + nbase + hi[it]));
-        }
+            pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(psi + nbase + hi[it]));
         for (int t = 0; t < nstages; ++t) {
             run_stage<R, B>(s, stages[t], sops, mats);
             lds_barrier();
@@ -233,6 +247,18 @@ __global__ __launch_bounds__(256) void k_block(typename BT<R>::C2 *__restrict__ 
             w.x = v.x;
             w.y = v.y;
             __builtin_nontemporal_store(w, reinterpret_cast<NV *>(psi + base + hi[it]));
+        }
+        if (nxt >= nblocks)
+            break;
+        blk = nxt;
+        base = nbase;
+        lds_barrier();  // every thread has read its stored values out of LDS
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            C2 v;
+            v.x = pre[it].x;
+            v.y = pre[it].y;
+            s[swz(threadIdx.x + 256 * it)] = v;
         }
         lds_barrier();
     }
@@ -247,7 +273,7 @@ __global__ __launch_bounds__(256) void k_block(typename BT<R>::C2 *__restrict__ 
 //   * any other item is one pass over a circuit of more than B qubits held in HBM: its FIRST pass generates the
 //     basis state |0..0> in registers instead of reading it, its LAST pass writes |amp|^2 in FP64 instead of the
 //     amplitudes. Passes of one circuit are ordered by the launch boundaries between levels.
-// As in k_block, the next block's loads are issued before the current block's stages run.
+// As in k_block, the next block's loads are issued before the current block's stages run (rotated loop).
 __device__ __forceinline__ int find_item(const BatchItem *__restrict__ items, int nitems, uint32_t g)
 {
     int lo = 0, hi = nitems - 1;
@@ -291,23 +317,36 @@ __device__ __forceinline__ void batch_small(typename BT<R>::C2 *s, const BatchIt
     lds_barrier();
 }
 
+// Loads of one block into registers. The loads are issued even for a FIRST pass (whose values are then replaced by
+// the basis state) so that the wait before their use is the same on every path and can leave stores in flight.
 template <class R, int B>
 __device__ __forceinline__ void batch_fetch(typename NT2<R>::type *pre, const typename BT<R>::C2 *__restrict__ psi,
-                                            uint64_t base, const BlockMap &bm, bool first)
+                                            uint64_t base, const BlockMap &bm)
 {
     using NV = typename NT2<R>::type;
     constexpr int PER = (1 << B) / 256;
 #pragma unroll
-    for (int it = 0; it < PER; ++it) {
-        const uint64_t idx = base + spread((uint32_t)(256 * it), bm);
+    for (int it = 0; it < PER; ++it)
+        pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(psi + base + spread((uint32_t)(256 * it), bm)));
+}
+
+template <class R, int B>
+__device__ __forceinline__ void batch_to_lds(typename BT<R>::C2 *s, const typename NT2<R>::type *pre, uint64_t base,
+                                             const BlockMap &bm, bool first)
+{
+    using C2 = typename BT<R>::C2;
+    constexpr int PER = (1 << B) / 256;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        C2 v;
         if (first) {
-            NV v;
-            v.x = idx == 0 ? (R)1 : (R)0;
+            v.x = (base + spread((uint32_t)(256 * k), bm)) == 0 ? (R)1 : (R)0;
             v.y = 0;
-            pre[it] = v;
         } else {
-            pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(psi + idx));
+            v.x = pre[k].x;
+            v.y = pre[k].y;
         }
+        s[swz(threadIdx.x + 256 * k)] = v;
     }
 }
 
@@ -324,60 +363,63 @@ __global__ __launch_bounds__(256) void k_batch_level(typename BT<R>::C2 *__restr
     extern __shared__ __align__(16) unsigned char smem_blk[];
     C2 *s = reinterpret_cast<C2 *>(smem_blk);
     constexpr int PER = (1 << B) / 256;
+    // small items come first in the flat order: a workgroup runs its small circuits, then its HBM blocks
+    uint32_t g = blockIdx.x;
+    BatchItem cur{};
+    for (; g < nblocks; g += gridDim.x) {
+        cur = items[find_item(items, nitems, g)];
+        if (!(cur.flags & kBatchSmall))
+            break;
+        batch_small<R, B>(s, cur, prob_base, passes, stages, sops, mats);
+    }
+    if (g >= nblocks)
+        return;
+    // HBM blocks: the rotated pipeline of k_block (prefetch of the next block before the stages; waits only on the
+    // prefetch loads, the previous block's stores keep draining); the last prefetch re-reads the current block.
     NV pre[PER];
-    bool have = false;  // pre[] holds the loads of block g
-    for (uint32_t g = blockIdx.x; g < nblocks; g += gridDim.x) {
-        const BatchItem it = items[find_item(items, nitems, g)];
-        if (it.flags & kBatchSmall) {
-            batch_small<R, B>(s, it, prob_base, passes, stages, sops, mats);
-            continue;
-        }
-        const BatchPass &bp = passes[it.pass];
-        C2 *psi = psi_base + it.state_off;
-        const uint64_t own = spread(threadIdx.x, bp.bm);
-        const uint64_t base = ins0b(g - it.blk_begin, bp.outer) | own;
-        if (!have)
-            batch_fetch<R, B>(pre, psi, base, bp.bm, (it.flags & kBatchFirst) != 0);
-#pragma unroll
-        for (int k = 0; k < PER; ++k) {
-            C2 v;
-            v.x = pre[k].x;
-            v.y = pre[k].y;
-            s[swz(threadIdx.x + 256 * k)] = v;
-        }
-        lds_barrier();
-        // items after a non-small item are non-small: prefetch the next block of this workgroup
-        have = false;
+    const BatchPass *bp = &passes[cur.pass];
+    uint64_t base = ins0b(g - cur.blk_begin, bp->outer) | spread(threadIdx.x, bp->bm);
+    batch_fetch<R, B>(pre, psi_base + cur.state_off, base, bp->bm);
+    batch_to_lds<R, B>(s, pre, base, bp->bm, (cur.flags & kBatchFirst) != 0);
+    lds_barrier();
+    for (;;) {
         const uint32_t nx = g + gridDim.x;
-        if (nx < nblocks) {
-            const BatchItem nt = items[find_item(items, nitems, nx)];
-            const BatchPass &np = passes[nt.pass];
-            const uint64_t nbase = ins0b(nx - nt.blk_begin, np.outer) | spread(threadIdx.x, np.bm);
-            batch_fetch<R, B>(pre, psi_base + nt.state_off, nbase, np.bm, (nt.flags & kBatchFirst) != 0);
-            have = true;
-        }
-        for (int t = 0; t < bp.nstages; ++t) {
-            run_stage<R, B>(s, stages[bp.stage_begin + t], sops, mats);
+        const uint32_t ng = nx < nblocks ? nx : g;
+        const BatchItem nt = items[find_item(items, nitems, ng)];
+        const BatchPass *np = &passes[nt.pass];
+        const uint64_t nbase = ins0b(ng - nt.blk_begin, np->outer) | spread(threadIdx.x, np->bm);
+        batch_fetch<R, B>(pre, psi_base + nt.state_off, nbase, np->bm);
+        for (int t = 0; t < bp->nstages; ++t) {
+            run_stage<R, B>(s, stages[bp->stage_begin + t], sops, mats);
             lds_barrier();
         }
-        if (it.flags & kBatchLast) {
-            double *out = prob_base + it.prob_off;
+        if (cur.flags & kBatchLast) {
+            double *out = prob_base + cur.prob_off;
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
                 const C2 v = s[swz(threadIdx.x + 256 * k)];
                 const double re = (double)v.x, im = (double)v.y;
-                out[base + spread((uint32_t)(256 * k), bp.bm)] = re * re + im * im;
+                out[base + spread((uint32_t)(256 * k), bp->bm)] = re * re + im * im;
             }
         } else {
+            C2 *psi = psi_base + cur.state_off;
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
                 const C2 v = s[swz(threadIdx.x + 256 * k)];
                 NV w;
                 w.x = v.x;
                 w.y = v.y;
-                __builtin_nontemporal_store(w, reinterpret_cast<NV *>(psi + base + spread((uint32_t)(256 * k), bp.bm)));
+                __builtin_nontemporal_store(w, reinterpret_cast<NV *>(psi + base + spread((uint32_t)(256 * k), bp->bm)));
             }
         }
+        if (nx >= nblocks)
+            break;
+        g = nx;
+        cur = nt;
+        bp = np;
+        base = nbase;
+        lds_barrier();  // every thread has read its stored values out of LDS
+        batch_to_lds<R, B>(s, pre, base, bp->bm, (cur.flags & kBatchFirst) != 0);
         lds_barrier();
     }
 }

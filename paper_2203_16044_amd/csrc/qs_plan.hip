@@ -984,6 +984,29 @@ QS_API int qs_batch_create(qs_batch **out, int dtype, int block_bits, int low_bi
     return QS_OK;
 }
 
+QS_API int qs_batch_set_launch(qs_batch *Bt, int wg_per_cu)
+{
+    qs_clear_error();
+    if (!Bt)
+        return qs_fail(QS_EINVAL, "qs_batch_set_launch: NULL batch");
+    if (wg_per_cu < 1 || wg_per_cu > 8)
+        return qs_fail(QS_EINVAL, "qs_batch_set_launch: wg_per_cu = %d outside [1, 8]", wg_per_cu);
+    if (wg_per_cu == Bt->wg_per_cu)
+        return QS_OK;
+    // a captured graph holds the old grid: drop it (after the stream has finished with it)
+    if (Bt->exec || Bt->graph) {
+        QS_HIP(hipStreamSynchronize(Bt->stream));
+        if (Bt->exec)
+            QS_HIP(hipGraphExecDestroy(Bt->exec));
+        if (Bt->graph)
+            QS_HIP(hipGraphDestroy(Bt->graph));
+        Bt->exec = nullptr;
+        Bt->graph = nullptr;
+    }
+    Bt->wg_per_cu = wg_per_cu;
+    return QS_OK;
+}
+
 QS_API int qs_batch_add(qs_batch *Bt, const qs_circuit *c)
 {
     qs_clear_error();

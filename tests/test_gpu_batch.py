@@ -54,6 +54,12 @@ def test_graph_replays_match_eager(gpu):
         torch.cuda.synchronize()
         for i in range(len(circs)):
             assert b.probs(i).tobytes() == ref[i].tobytes(), (rep, i)
+    # a new launch shape drops the captured graph; the next graph run captures the new one
+    b.set_launch(1)
+    b.run(graph=True)
+    b.sync()
+    for i in range(len(circs)):
+        assert b.probs(i).tobytes() == ref[i].tobytes(), i
     b.close()
 
 

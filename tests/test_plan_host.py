@@ -93,6 +93,10 @@ def test_batch_host_validation():
     keep = [Circuit.from_ops(circ.n, circ.ops) for circ in C.config4(count=6, nmax=15)]
     for c in keep:
         B.qs_batch_add(b, c.h)
+    with pytest.raises(B.QSError):
+        B.qs_batch_set_launch(b, 0)
+    B.qs_batch_set_launch(b, 3)  # no graph captured yet: host-side only
     info = B.qs_batch_info(b)
+    assert info["levels"] == 0  # not finalized
     assert info["circuits"] == 6 and info["prob_count"] == sum(1 << c.n for c in C.config4(count=6, nmax=15))
     B.qs_batch_free(b)
