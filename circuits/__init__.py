@@ -33,7 +33,7 @@ import numpy as np
 __all__ = [
     "Op", "Circuit", "u3", "rx", "rz", "h", "x_gate", "haar_su4", "dagger",
     "config0", "config1", "config2", "config3", "config3_error_run", "config4",
-    "hadamard_x11", "qsb", "ghz", "rx_sweep", "random_state", "random_circuit",
+    "hadamard_x11", "qsb", "quantum_volume", "ghz", "rx_sweep", "random_state", "random_circuit",
     "basis_state", "inverse_circuit",
 ]
 
@@ -309,6 +309,19 @@ def ghz(n: int) -> Circuit:
     c.ops.append(_dense((0,), h(), "H"))
     for qb in range(n - 1):
         c.ops.append(_ctrl((qb,), (qb + 1,), x_gate(), "CNOT"))
+    return c
+
+
+def quantum_volume(n: int, seed: int = 0, depth: int = 10) -> Circuit:
+    """Quantum Volume model circuit (Sec. IV-E): ``depth`` layers, each a random permutation of the qubit labels
+    followed by a Haar SU(4) on every consecutive pair of the permuted labels (an odd n leaves one qubit idle).
+    The reference generator the paper used is not available; this follows its prose."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    c = Circuit(n, name=f"qv_n{n}_d{depth}", seed=seed)
+    for L in range(1, depth + 1):
+        perm = rng.permutation(n)
+        for j in range(n // 2):
+            c.ops.append(_dense((perm[2 * j], perm[2 * j + 1]), haar_su4(rng), "SU4", L))
     return c
 
 
