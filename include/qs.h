@@ -143,6 +143,25 @@ QS_API int qs_get_info(qs_state *st, int *n, int *dtype, void **dev_ptr, void **
 /* Message of the last failing call on this thread ("" if none). */
 QS_API const char *qs_last_error(void);
 
+/* ---- measurement, sampling and reset ----
+ * A circuit is a sequence of gates, measurements and resets (Sec. II-A); the probability of observing basis state
+ * i is |a_i|^2 relative to the total mass (Eq. 1 generalised to n qubits). Random numbers are the caller's: each
+ * call takes uniforms in [0, 1), so runs are reproducible and can be checked one by one. */
+/* Measure `qubit`: P0, P1 = FP64 masses with the qubit's bit 0 / 1 (fixed-order reduction), outcome = 1 iff
+ * u (P0 + P1) < P1, then the state collapses: amplitudes of the observed outcome are scaled by 1/sqrt(P_outcome)
+ * (factor in FP64), the others set to 0. prob_one (nullable) receives P1 / (P0 + P1). Synchronises (the outcome
+ * is decided on the host). QS_EINVAL for a qubit out of range, u outside [0, 1) or a state with no finite
+ * nonzero mass (then the state is unchanged). */
+QS_API int qs_measure(qs_state *st, int qubit, double u, int *outcome, double *prob_one);
+/* Measure `qubit` as qs_measure does, then flip it to |0> if the outcome was 1 (an exact permutation). */
+QS_API int qs_reset(qs_state *st, int qubit, double u, int *outcome);
+/* Draw nshots basis indices (no collapse): shot k returns the smallest i whose cumulative FP64 mass exceeds
+ * u[k] x total mass (chunked deterministic prefix sums; every index returned lies in [0, 2^n)). u and out are
+ * host arrays of nshots doubles / int64 (0 <= nshots <= 2^30); uses temporary device memory of about
+ * 2^(n-11) doubles + 16 bytes per shot. Synchronises. QS_EINVAL for u outside [0, 1) or a state with no finite
+ * nonzero mass. */
+QS_API int qs_sample(qs_state *st, int64_t nshots, const double *u, int64_t *out);
+
 /* ---- circuits and execution plans ----
  * A circuit is an ordered list of operations (Sec. II-A: a circuit applies its gates in sequence); the add
  * calls take the same arguments, with the same validation, as the qs_apply_* calls, and copy them. */

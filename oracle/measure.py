@@ -49,22 +49,35 @@ def reset(psi: np.ndarray, q: int, u: float):
     return out, res
 
 
-def sample_valid(psi: np.ndarray, u: float, idx: int, rtol: float = 1e-12) -> bool:
-    """idx is the smallest i with cum[i] > u * total, up to rtol * total at the boundaries, and has mass."""
+def _dist(psi: np.ndarray):
     p = _p(psi)
-    if not 0 <= idx < p.size or p[idx] <= 0.0:
-        return False
-    cum = np.cumsum(p)
-    total = math.fsum(p.tolist())
-    target = u * total
-    excl = cum[idx] - p[idx]
+    return p, np.cumsum(p), math.fsum(p.tolist())
+
+
+def samples_valid(psi: np.ndarray, us, idxs, rtol: float = 1e-12) -> np.ndarray:
+    """For each (u, idx): idx is the smallest i with cum[i] > u * total, up to rtol * total at the boundaries, and
+    has mass. The distribution is built once for all shots."""
+    p, cum, total = _dist(psi)
+    us = np.asarray(us, dtype=np.float64)
+    idxs = np.asarray(idxs, dtype=np.int64)
+    ok = (idxs >= 0) & (idxs < p.size)
+    j = np.where(ok, idxs, 0)
+    target = us * total
     tol = rtol * total
-    return excl <= target + tol and cum[idx] > target - tol
+    excl = cum[j] - p[j]
+    return ok & (p[j] > 0.0) & (excl <= target + tol) & (cum[j] > target - tol)
+
+
+def sample_valid(psi: np.ndarray, u: float, idx: int, rtol: float = 1e-12) -> bool:
+    return bool(samples_valid(psi, [u], [idx], rtol)[0])
+
+
+def samples(psi: np.ndarray, us) -> np.ndarray:
+    """The inverse-CDF indices of the uniforms `us` (FP64 cumulative sums)."""
+    p, cum, _ = _dist(psi)
+    i = np.searchsorted(cum, np.asarray(us, dtype=np.float64) * cum[-1], side="right")
+    return np.minimum(i, p.size - 1).astype(np.int64)
 
 
 def sample(psi: np.ndarray, u: float) -> int:
-    """The inverse-CDF index of u (FP64 cumulative sums)."""
-    p = _p(psi)
-    cum = np.cumsum(p)
-    i = int(np.searchsorted(cum, u * cum[-1], side="right"))
-    return min(i, p.size - 1)
+    return int(samples(psi, [u])[0])

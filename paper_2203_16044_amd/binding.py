@@ -83,6 +83,9 @@ SIGNATURES = {
     "qs_batch_info": [_P, _IP, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), _IP, _IP],
     "qs_batch_probs": [_P, _I, ctypes.POINTER(_P), _DP],
     "qs_batch_free": [_P],
+    "qs_measure": [_P, _I, ctypes.c_double, _IP, _DP],
+    "qs_reset": [_P, _I, ctypes.c_double, _IP],
+    "qs_sample": [_P, ctypes.c_int64, _DP, ctypes.POINTER(ctypes.c_int64)],
     "qs_batch_set_launch": [_P, _I],
     "qs_mlp_create": [ctypes.POINTER(_P), _I, _I, _P],
     "qs_mlp_free": [_P],
@@ -169,6 +172,27 @@ def qs_apply_controlled(h: int, controls: Sequence[int], targets: Sequence[int],
 
 def qs_fused_swap(h: int, p: int, q: int, s: int) -> None:
     _check(lib().qs_fused_swap(h, int(p), int(q), int(s)), "qs_fused_swap")
+
+
+def qs_measure(h: int, qubit: int, u: float):
+    """Returns (outcome, P(outcome 1) before the collapse)."""
+    o, p1 = ctypes.c_int(), ctypes.c_double()
+    _check(lib().qs_measure(h, int(qubit), float(u), ctypes.byref(o), ctypes.byref(p1)), "qs_measure")
+    return o.value, p1.value
+
+
+def qs_reset(h: int, qubit: int, u: float) -> int:
+    o = ctypes.c_int()
+    _check(lib().qs_reset(h, int(qubit), float(u), ctypes.byref(o)), "qs_reset")
+    return o.value
+
+
+def qs_sample(h: int, u) -> np.ndarray:
+    u = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(-1))
+    out = np.empty(u.size, dtype=np.int64)
+    _check(lib().qs_sample(h, ctypes.c_int64(u.size), _dptr(u),
+                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), "qs_sample")
+    return out
 
 
 def qs_probs(h: int, out_dev: Optional[int] = None, want_norm: bool = False) -> Optional[float]:

@@ -88,6 +88,17 @@ class State:
                 B.qs_renormalize(self.h)
 
     # -------------------------------------------------------------------------------------------- I/O
+    def measure(self, qubit: int, u: float):
+        """Measure `qubit` with the uniform u in [0, 1): returns (outcome, P(1)); the state collapses."""
+        return B.qs_measure(self.h, qubit, u)
+
+    def reset(self, qubit: int, u: float) -> int:
+        return B.qs_reset(self.h, qubit, u)
+
+    def sample(self, u) -> np.ndarray:
+        """One basis index per uniform in `u` (the state is unchanged)."""
+        return B.qs_sample(self.h, u)
+
     def init_zero(self):
         B.qs_init_zero(self.h)
 
