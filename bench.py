@@ -29,6 +29,38 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_TBS = 8.0  # MI355X HBM3E, published
 
+# HBM traffic per dispatch of the dominant kernels, from two rocprofv3 PMC runs of this script (FETCH_SIZE, then
+# WRITE_SIZE; KiB per dispatch, mean over the 32-qubit dispatches), each scaled by what the same counter reads for
+# a device copy of known size (paper_2203_16044_amd.probe copy of 4 GiB: FETCH_SIZE reports 2097194 KiB, half of
+# the bytes read, WRITE_SIZE 4194304 KiB, all bytes written). Commands and figures: profiles/*_pmc_traffic.md. The readings hold for the kernel sources they were taken on: `sha1` fingerprints
+# those files and the traffic is reported as null once they differ.
+PMC_TRAFFIC = {
+    "block_b12": {"fetch_kib": 33585331.24, "write_kib": 67115266.55, "fetch_scale": 2.0, "write_scale": 1.0,
+                  "sources": ["paper_2203_16044_amd/csrc/qs_block.hip", "paper_2203_16044_amd/csrc/qs_internal.h"],
+                  "sha1": "859da6ca17405dc1d1c735c22e692bc1bd0f56f8"},
+    "dense_k1": {"fetch_kib": 33554446.77, "write_kib": 67110649.03, "fetch_scale": 2.0, "write_scale": 1.0,
+                 "sources": ["paper_2203_16044_amd/csrc/qs_kernels.hip", "paper_2203_16044_amd/csrc/qs_internal.h"],
+                 "sha1": "16409c133a9994ea26340f0b7c7444d6c10f31c2"},
+}
+
+
+def sources_sha1(paths):
+    import hashlib
+    h = hashlib.sha1()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def pmc_traffic(kernel):
+    """HBM bytes per dispatch of `kernel` from the recorded PMC readings, or None if there are none or the kernel's
+    sources changed since."""
+    t = PMC_TRAFFIC.get(kernel)
+    if not t or t["fetch_kib"] is None or t["write_kib"] is None or t["sha1"] != sources_sha1(t["sources"]):
+        return None
+    return int(round(t["fetch_kib"] * 1024 * t["fetch_scale"] + t["write_kib"] * 1024 * t["write_scale"]))
+
 
 def _alg_bytes(op, n, amp):
     """Algorithmic bytes one op moves (read + write of every amplitude it changes)."""
@@ -343,7 +375,7 @@ def main():
                              else "one pass per gate")),
                    "parallelism": "none"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_TBS, "unit": "TB/s",
-                     "frac": achieved / HBM_PEAK_TBS, "traffic": None, "kernel": dom,
+                     "frac": achieved / HBM_PEAK_TBS, "traffic": pmc_traffic(dom), "kernel": dom,
                      "avg_launch_ms": avg * 1e3, "launches_per_step": cnt // len(step_times),
                      "alg_bytes_per_launch": bsum // cnt},
         "plain": {"gates_per_s": plain_rate, "gates_timed": len(plain_ops),

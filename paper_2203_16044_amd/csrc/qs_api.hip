@@ -631,6 +631,10 @@ QS_API int qs_set_tunable(const char *name, int64_t value)
         if (value < 1 || value > 16)
             return qs_fail(QS_EINVAL, "block_wg_per_cu must be in [1, 16]");
         t.block_wg_per_cu = (int)value;
+    } else if (!std::strcmp(name, "block_stage_width")) {
+        if (value != 3 && value != 4)
+            return qs_fail(QS_EINVAL, "block_stage_width must be 3 or 4");
+        t.block_stage_width = (int)value;
     } else {
         return qs_fail(QS_EINVAL, "qs_set_tunable: unknown tunable '%s'", name);
     }

@@ -44,9 +44,9 @@ __device__ __forceinline__ uint64_t spread(uint32_t m, const BlockMap &bm)
 // with their lowest counter bits, so 16 consecutive lanes always touch 16 different bank groups.
 __device__ __forceinline__ uint32_t swz(uint32_t m) { return m ^ (((m >> 4) ^ (m >> 8) ^ (m >> 12)) & 15u); }
 
-// Apply a k-qubit op (k = popcount(MASK) <= 3) to the 16 register amplitudes x[a], a = the 4 stage bits. Matrix bit
-// j <-> the j-th set bit of MASK (ascending); U is 2^k x 2^k, interleaved, in the compute precision.
-template <class R, int MASK>
+// Apply a k-qubit op (k = popcount(MASK) <= 3) to the 2^W register amplitudes x[a], a = the W stage bits. Matrix
+// bit j <-> the j-th set bit of MASK (ascending); U is 2^k x 2^k, interleaved, in the compute precision.
+template <class R, int W, int MASK>
 __device__ __forceinline__ void reg_op(typename BT<R>::C2 *x, const R *__restrict__ U)
 {
     using C2 = typename BT<R>::C2;
@@ -55,12 +55,12 @@ __device__ __forceinline__ void reg_op(typename BT<R>::C2 *x, const R *__restric
     int bitpos[3] = {0, 0, 0};
     {
         int j = 0;
-        for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < W; ++b)
             if ((MASK >> b) & 1)
                 bitpos[j++] = b;
     }
 #pragma unroll
-    for (int rest = 0; rest < 16; ++rest) {
+    for (int rest = 0; rest < (1 << W); ++rest) {
         if (rest & MASK)
             continue;  // enumerate the combinations of the other stage bits once
         C2 v[D];
@@ -93,29 +93,41 @@ __device__ __forceinline__ void reg_op(typename BT<R>::C2 *x, const R *__restric
     }
 }
 
-template <class R>
+template <class R, int W>
 __device__ __forceinline__ void reg_op_dispatch(typename BT<R>::C2 *x, int mask, const R *__restrict__ U)
 {
-    switch (mask) {
-    case 1: reg_op<R, 1>(x, U); break;
-    case 2: reg_op<R, 2>(x, U); break;
-    case 3: reg_op<R, 3>(x, U); break;
-    case 4: reg_op<R, 4>(x, U); break;
-    case 5: reg_op<R, 5>(x, U); break;
-    case 6: reg_op<R, 6>(x, U); break;
-    case 7: reg_op<R, 7>(x, U); break;
-    case 8: reg_op<R, 8>(x, U); break;
-    case 9: reg_op<R, 9>(x, U); break;
-    case 10: reg_op<R, 10>(x, U); break;
-    case 11: reg_op<R, 11>(x, U); break;
-    case 12: reg_op<R, 12>(x, U); break;
-    case 13: reg_op<R, 13>(x, U); break;
-    default: reg_op<R, 14>(x, U); break;
+    if constexpr (W == 3) {
+        switch (mask) {
+        case 1: reg_op<R, 3, 1>(x, U); break;
+        case 2: reg_op<R, 3, 2>(x, U); break;
+        case 3: reg_op<R, 3, 3>(x, U); break;
+        case 4: reg_op<R, 3, 4>(x, U); break;
+        case 5: reg_op<R, 3, 5>(x, U); break;
+        case 6: reg_op<R, 3, 6>(x, U); break;
+        default: reg_op<R, 3, 7>(x, U); break;
+        }
+    } else {
+        switch (mask) {
+        case 1: reg_op<R, 4, 1>(x, U); break;
+        case 2: reg_op<R, 4, 2>(x, U); break;
+        case 3: reg_op<R, 4, 3>(x, U); break;
+        case 4: reg_op<R, 4, 4>(x, U); break;
+        case 5: reg_op<R, 4, 5>(x, U); break;
+        case 6: reg_op<R, 4, 6>(x, U); break;
+        case 7: reg_op<R, 4, 7>(x, U); break;
+        case 8: reg_op<R, 4, 8>(x, U); break;
+        case 9: reg_op<R, 4, 9>(x, U); break;
+        case 10: reg_op<R, 4, 10>(x, U); break;
+        case 11: reg_op<R, 4, 11>(x, U); break;
+        case 12: reg_op<R, 4, 12>(x, U); break;
+        case 13: reg_op<R, 4, 13>(x, U); break;
+        default: reg_op<R, 4, 14>(x, U); break;
+        }
     }
 }
 
 // Byte offset in LDS of local index m. swz is linear over XOR and a group's base index m and a register offset
-// off[a] have disjoint bits, so slot(m | off[a]) = slot(m) ^ slot(off[a]): the 16 register offsets of a stage are
+// off[a] have disjoint bits, so slot(m | off[a]) = slot(m) ^ slot(off[a]): the register offsets of a stage are
 // computed once per stage (uniform) and every LDS access costs one XOR.
 template <class C2>
 __device__ __forceinline__ uint32_t slot_bytes(uint32_t m) { return swz(m) * (uint32_t)sizeof(C2); }
@@ -125,46 +137,50 @@ __device__ __forceinline__ C2 &lds_at(C2 *s, uint32_t bytes)
     return *reinterpret_cast<C2 *>(reinterpret_cast<unsigned char *>(s) + bytes);
 }
 
-template <class C2>
+template <class C2, int W>
 __device__ __forceinline__ void stage_offsets(const BlkStage &stg, uint32_t *soff)
 {
 #pragma unroll
-    for (int a = 0; a < 16; ++a)
-        soff[a] = slot_bytes<C2>(((a & 1) << stg.pos[0]) | (((a >> 1) & 1) << stg.pos[1]) |
-                                 (((a >> 2) & 1) << stg.pos[2]) | (((a >> 3) & 1) << stg.pos[3]));
+    for (int a = 0; a < (1 << W); ++a) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int j = 0; j < W; ++j)
+            o |= ((uint32_t)(a >> j) & 1u) << stg.pos[j];
+        soff[a] = slot_bytes<C2>(o);
+    }
 }
 
-// One stage: every thread takes groups of 16 amplitudes (the 4 stage positions varying), applies the stage's ops
-// in registers and writes the group back.
-template <class R, int B>
+// One stage: every thread takes groups of 2^W amplitudes (the W stage positions varying), applies the stage's ops
+// in registers and writes the group back. NT threads share the 2^(B-W) groups.
+template <class R, int B, int W, int NT>
 __device__ __forceinline__ void run_stage(typename BT<R>::C2 *s, const BlkStage &stg, const BlkStageOp *__restrict__ sops,
                                           const R *__restrict__ mats)
 {
     using C2 = typename BT<R>::C2;
-    constexpr int NG = (1 << B) >> 4;
-    uint32_t soff[16];
-    stage_offsets<C2>(stg, soff);
-    for (int g = threadIdx.x; g < NG; g += blockDim.x) {
+    constexpr int NG = 1 << (B - W);
+    uint32_t soff[1 << W];
+    stage_offsets<C2, W>(stg, soff);
+    for (int g = threadIdx.x; g < NG; g += NT) {
         uint32_t m = 0;
 #pragma unroll
-        for (int j = 0; j < B - 4; ++j)
+        for (int j = 0; j < B - W; ++j)
             m |= (((uint32_t)g >> j) & 1u) << stg.order[j];
         const uint32_t sm = slot_bytes<C2>(m);
-        C2 x[16];
+        C2 x[1 << W];
 #pragma unroll
-        for (int a = 0; a < 16; ++a)
+        for (int a = 0; a < (1 << W); ++a)
             x[a] = lds_at(s, sm ^ soff[a]);
         for (int o = 0; o < stg.nops; ++o) {
             const BlkStageOp op = sops[stg.op_begin + o];
-            reg_op_dispatch<R>(x, op.mask, mats + op.mat_off);
+            reg_op_dispatch<R, W>(x, op.mask, mats + op.mat_off);
         }
 #pragma unroll
-        for (int a = 0; a < 16; ++a)
+        for (int a = 0; a < (1 << W); ++a)
             lds_at(s, sm ^ soff[a]) = x[a];
     }
 }
 
-// The same stage for a block of 2^nb amplitudes, nb <= B chosen at run time (whole small circuits held in LDS).
+// A 4-position stage for a block of 2^nb amplitudes, nb <= B chosen at run time (whole small circuits in LDS).
 template <class R>
 __device__ __forceinline__ void run_stage_n(typename BT<R>::C2 *s, const BlkStage &stg,
                                             const BlkStageOp *__restrict__ sops, const R *__restrict__ mats, int nb)
@@ -172,7 +188,7 @@ __device__ __forceinline__ void run_stage_n(typename BT<R>::C2 *s, const BlkStag
     using C2 = typename BT<R>::C2;
     const int ng = (1 << nb) >> 4;
     uint32_t soff[16];
-    stage_offsets<C2>(stg, soff);
+    stage_offsets<C2, 4>(stg, soff);
     for (int g = threadIdx.x; g < ng; g += blockDim.x) {
         uint32_t m = 0;
         for (int j = 0; j < nb - 4; ++j)
@@ -184,7 +200,7 @@ __device__ __forceinline__ void run_stage_n(typename BT<R>::C2 *s, const BlkStag
             x[a] = lds_at(s, sm ^ soff[a]);
         for (int o = 0; o < stg.nops; ++o) {
             const BlkStageOp op = sops[stg.op_begin + o];
-            reg_op_dispatch<R>(x, op.mask, mats + op.mat_off);
+            reg_op_dispatch<R, 4>(x, op.mask, mats + op.mat_off);
         }
 #pragma unroll
         for (int a = 0; a < 16; ++a)
@@ -192,22 +208,28 @@ __device__ __forceinline__ void run_stage_n(typename BT<R>::C2 *s, const BlkStag
     }
 }
 
-template <class R, int B>
-__global__ __launch_bounds__(256) void k_block(typename BT<R>::C2 *__restrict__ psi, uint64_t nblocks, InsBits outer,
-                                               BlockMap bm, const BlkStage *__restrict__ stages, int nstages,
-                                               const BlkStageOp *__restrict__ sops, const R *__restrict__ mats)
+// NT threads per workgroup: 256 with 4-position stages; 512 with 3-position stages (8 register amplitudes per
+// thread, so that two 64 KB complex128 blocks per CU run 16 waves when the kernel stays within 128 VGPRs).
+template <int NT> struct BlockBounds;
+template <> struct BlockBounds<256> { static constexpr int waves_per_eu = 1; };
+template <> struct BlockBounds<512> { static constexpr int waves_per_eu = 4; };
+
+template <class R, int B, int W, int NT>
+__global__ __launch_bounds__(NT, BlockBounds<NT>::waves_per_eu) void k_block(
+    typename BT<R>::C2 *__restrict__ psi, uint64_t nblocks, InsBits outer, BlockMap bm,
+    const BlkStage *__restrict__ stages, int nstages, const BlkStageOp *__restrict__ sops, const R *__restrict__ mats)
 {
     using C2 = typename BT<R>::C2;
     extern __shared__ __align__(16) unsigned char smem_blk[];
     C2 *s = reinterpret_cast<C2 *>(smem_blk);
     constexpr int N = 1 << B;
-    constexpr int PER = N / 256;  // amplitudes per thread for load / store
-    // local index m = tid + 256 * it: spread(tid) per thread, spread(256 * it) uniform
+    constexpr int PER = N / NT;  // amplitudes per thread for load / store
+    // local index m = tid + NT * it: spread(tid) per thread, spread(NT * it) uniform
     const uint64_t own = spread(threadIdx.x, bm);
     uint64_t hi[PER];
 #pragma unroll
     for (int it = 0; it < PER; ++it)
-        hi[it] = spread((uint32_t)(256 * it), bm);
+        hi[it] = spread((uint32_t)(NT * it), bm);
     // Software pipeline over this workgroup's blocks: the next block's global loads are issued into registers before
     // the current block's stages run, so HBM traffic overlaps the FP arithmetic. The loop is rotated so that wherever
     // the prefetched registers are consumed, exactly the prefetch loads and then the previous block's stores are in
@@ -227,7 +249,7 @@ __global__ __launch_bounds__(256) void k_block(typename BT<R>::C2 *__restrict__ 
         C2 v;
         v.x = pre[it].x;
         v.y = pre[it].y;
-        s[swz(threadIdx.x + 256 * it)] = v;
+        s[swz(threadIdx.x + NT * it)] = v;
     }
     lds_barrier();
     for (;;) {
@@ -237,12 +259,12 @@ __global__ __launch_bounds__(256) void k_block(typename BT<R>::C2 *__restrict__ 
         for (int it = 0; it < PER; ++it)
             pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(psi + nbase + hi[it]));
         for (int t = 0; t < nstages; ++t) {
-            run_stage<R, B>(s, stages[t], sops, mats);
+            run_stage<R, B, W, NT>(s, stages[t], sops, mats);
             lds_barrier();
         }
 #pragma unroll
         for (int it = 0; it < PER; ++it) {
-            const C2 v = s[swz(threadIdx.x + 256 * it)];
+            const C2 v = s[swz(threadIdx.x + NT * it)];
             NV w;
             w.x = v.x;
             w.y = v.y;
@@ -258,7 +280,7 @@ __global__ __launch_bounds__(256) void k_block(typename BT<R>::C2 *__restrict__ 
             C2 v;
             v.x = pre[it].x;
             v.y = pre[it].y;
-            s[swz(threadIdx.x + 256 * it)] = v;
+            s[swz(threadIdx.x + NT * it)] = v;
         }
         lds_barrier();
     }
@@ -390,7 +412,7 @@ __global__ __launch_bounds__(256) void k_batch_level(typename BT<R>::C2 *__restr
         const uint64_t nbase = ins0b(ng - nt.blk_begin, np->outer) | spread(threadIdx.x, np->bm);
         batch_fetch<R, B>(pre, psi_base + nt.state_off, nbase, np->bm);
         for (int t = 0; t < bp->nstages; ++t) {
-            run_stage<R, B>(s, stages[bp->stage_begin + t], sops, mats);
+            run_stage<R, B, 4, 256>(s, stages[bp->stage_begin + t], sops, mats);
             lds_barrier();
         }
         if (cur.flags & kBatchLast) {
@@ -465,16 +487,18 @@ hipError_t batch_r(int b, void *psi, double *probs, const BatchItem *items, int 
     }
 }
 
-template <class R, int B>
+template <class R, int B, int W>
 hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm, const BlkStage *stages,
                    int nstages, const BlkStageOp *sops, const void *mats, hipStream_t s)
 {
     using C2 = typename BT<R>::C2;
+    constexpr int NT = W == 3 ? 512 : 256;
+    static_assert((1 << B) >= NT, "block smaller than the workgroup");
     const size_t shm = sizeof(C2) << B;
     static bool attr_set = false;
     if (!attr_set && shm > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_block<R, B>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)shm);
+        hipError_t e = hipFuncSetAttribute((const void *)k_block<R, B, W, NT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
         if (e != hipSuccess)
             return e;
         attr_set = true;
@@ -486,22 +510,31 @@ hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const Bloc
     uint64_t grid = (uint64_t)cus * qs_tunables().block_wg_per_cu;
     if (grid > nblocks)
         grid = nblocks;
-    hipLaunchKernelGGL((k_block<R, B>), dim3((unsigned)grid), dim3(256), shm, s, (C2 *)psi, nblocks, outer, bm,
+    hipLaunchKernelGGL((k_block<R, B, W, NT>), dim3((unsigned)grid), dim3(NT), shm, s, (C2 *)psi, nblocks, outer, bm,
                        stages, nstages, sops, (const R *)mats);
     return hipGetLastError();
 }
 
 template <class R>
-hipError_t block_r(int b, void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm,
+hipError_t block_r(int b, int w, void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm,
                    const BlkStage *stages, int nstages, const BlkStageOp *sops, const void *mats, hipStream_t s)
 {
+    if (w == 3) {
+        switch (b) {
+        case 12: return block_b<R, 12, 3>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
+        case 13: return block_b<R, 13, 3>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (w != 4)
+        return hipErrorInvalidValue;
     switch (b) {
-    case 8: return block_b<R, 8>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
-    case 9: return block_b<R, 9>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
-    case 10: return block_b<R, 10>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
-    case 11: return block_b<R, 11>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
-    case 12: return block_b<R, 12>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
-    case 13: return block_b<R, 13>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
+    case 8: return block_b<R, 8, 4>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
+    case 9: return block_b<R, 9, 4>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
+    case 10: return block_b<R, 10, 4>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
+    case 11: return block_b<R, 11, 4>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
+    case 12: return block_b<R, 12, 4>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
+    case 13: return block_b<R, 13, 4>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -518,10 +551,11 @@ hipError_t launch_batch_level(int dtype, int b, void *psi, double *probs, const 
                                              wg_per_cu, s);
 }
 
-hipError_t launch_block(int dtype, int b, void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm,
-                        const BlkStage *stages_dev, int nstages, const BlkStageOp *sops_dev, const void *mats_dev,
-                        hipStream_t s)
+hipError_t launch_block(int dtype, int b, int w, void *psi, uint64_t nblocks, const InsBits &outer,
+                        const BlockMap &bm, const BlkStage *stages_dev, int nstages, const BlkStageOp *sops_dev,
+                        const void *mats_dev, hipStream_t s)
 {
-    return dtype == QS_C128 ? block_r<double>(b, psi, nblocks, outer, bm, stages_dev, nstages, sops_dev, mats_dev, s)
-                            : block_r<float>(b, psi, nblocks, outer, bm, stages_dev, nstages, sops_dev, mats_dev, s);
+    return dtype == QS_C128
+               ? block_r<double>(b, w, psi, nblocks, outer, bm, stages_dev, nstages, sops_dev, mats_dev, s)
+               : block_r<float>(b, w, psi, nblocks, outer, bm, stages_dev, nstages, sops_dev, mats_dev, s);
 }

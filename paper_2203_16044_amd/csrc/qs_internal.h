@@ -125,20 +125,21 @@ struct BlockMap {
     int lpos[kMaxBlockBits];  // global bit of local bit t (ascending)
 };
 struct BlkStage {
-    int pos[4];    // local positions held in registers during the stage, ascending
+    int pos[4];    // local positions held in registers during the stage (the first W, ascending; W = 3 or 4)
     int op_begin;  // first op of the stage in the op table
     int nops;
     // the other local positions in the order the bits of a thread's group counter fill them: the first four cover
     // the four residue classes (mod 4) of the LDS swizzle so that 16 consecutive lanes hit 16 distinct bank groups
-    int order[kMaxBlockBits - 4];
+    int order[kMaxBlockBits - 3];
 };
 struct BlkStageOp {
-    int mask;          // stage positions the op acts on (bit j of the mask <-> pos[j]); 1..3 bits set
+    int mask;          // stage positions the op acts on (bit j of the mask <-> pos[j], j < W); 1..3 bits set
     uint32_t mat_off;  // offset of its 2^k x 2^k matrix (bit order of the mask's positions) in real elements
 };
-hipError_t launch_block(int dtype, int b, void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm,
-                        const BlkStage *stages_dev, int nstages, const BlkStageOp *sops_dev, const void *mats_dev,
-                        hipStream_t s);
+// w = register stage width: 4 (256 threads, any b in 8..13) or 3 (512 threads, b = 12, 13)
+hipError_t launch_block(int dtype, int b, int w, void *psi, uint64_t nblocks, const InsBits &outer,
+                        const BlockMap &bm, const BlkStage *stages_dev, int nstages, const BlkStageOp *sops_dev,
+                        const void *mats_dev, hipStream_t s);
 
 // batched circuits: one persistent launch per pass level (see qs_block.hip)
 struct BatchCirc {
@@ -193,5 +194,6 @@ struct Tunables {
     int nontemporal = 1;     // use non-temporal loads/stores in the plain gate kernels
     int mfma_wg_per_cu = 2;  // persistent workgroups per CU for the MFMA block kernel
     int block_wg_per_cu = 4; // persistent workgroups per CU for the LDS block kernel
+    int block_stage_width = 4; // register stage width of new block plans: 4, or 3 (512-thread kernel, b = 12, 13)
 };
 Tunables &qs_tunables();

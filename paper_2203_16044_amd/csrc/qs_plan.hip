@@ -119,6 +119,7 @@ struct PlanPass {
     BlockMap bm{};
     int op_begin = 0, nops = 0;  // block: fused ops carried
     int stage_begin = 0, nstages = 0;  // block: range in stages
+    int sw = 4;                        // block: register stage width (3 or 4)
     // dense
     int k = 0;
     TPos tp{};
@@ -544,9 +545,21 @@ QS_API int qs_circuit_run(qs_state *st, const qs_circuit *c)
     return QS_OK;
 }
 
-QS_API int qs_plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts)
+}  // extern "C"
+
+namespace {
+int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, int stage_width);
+}
+
+extern "C" QS_API int qs_plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts)
 {
     qs_clear_error();
+    return plan_create(out, c, opts, qs_tunables().block_stage_width);
+}
+
+namespace {
+int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, int stage_width)
+{
     if (!out || !c || !opts)
         return qs_fail(QS_EINVAL, "qs_plan_create: NULL argument");
     *out = nullptr;
@@ -648,8 +661,10 @@ QS_API int qs_plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts
                 pm |= 1u << (int)(std::find(LL.begin(), LL.end(), q) - LL.begin());
             posmask.push_back(pm);
         }
-        // stages of at most 4 positions: repeatedly take ready ops (every earlier op sharing a position placed)
-        // that keep the stage within 4 positions, fewest new positions first
+        // stages of at most W positions (W = 3 only where a 512-thread kernel exists): repeatedly take ready ops
+        // (every earlier op sharing a position placed) that keep the stage within W positions, fewest new first
+        const int W = (stage_width == 3 && (b == 12 || b == 13)) ? 3 : 4;
+        pp.sw = W;
         const int nf = (int)fused.size();
         std::vector<char> placed(nf, 0);
         int left = nf;
@@ -669,7 +684,7 @@ QS_API int qs_plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts
                     if (!rdy)
                         continue;
                     const int nw = __builtin_popcount(posmask[i] & ~S);
-                    if (__builtin_popcount(S | posmask[i]) <= 4 && nw < bestnew) {
+                    if (__builtin_popcount(S | posmask[i]) <= W && nw < bestnew) {
                         best = i;
                         bestnew = nw;
                     }
@@ -681,7 +696,7 @@ QS_API int qs_plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts
                 S |= posmask[best];
                 members.push_back(best);
             }
-            for (int p = 0; __builtin_popcount(S) < 4 && p < b; ++p)
+            for (int p = 0; __builtin_popcount(S) < W && p < b; ++p)
                 S |= 1u << p;  // pad with unused positions
             BlkStage stg{};
             int j = 0;
@@ -703,14 +718,14 @@ QS_API int qs_plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts
                             break;
                         }
                 ord.insert(ord.end(), rest.begin(), rest.end());
-                for (int t = 0; t < b - 4; ++t)
+                for (int t = 0; t < b - W; ++t)
                     stg.order[t] = ord[t];
             }
             stg.op_begin = (int)P->sops.size();
             stg.nops = (int)members.size();
             for (int i : members) {
                 BlkStageOp so{};
-                for (int t = 0; t < 4; ++t)
+                for (int t = 0; t < W; ++t)
                     if ((posmask[i] >> stg.pos[t]) & 1)
                         so.mask |= 1 << t;
                 so.mat_off = (uint32_t)P->pool.size();
@@ -726,6 +741,9 @@ QS_API int qs_plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts
     *out = P;
     return QS_OK;
 }
+}  // namespace
+
+extern "C" {
 
 QS_API int qs_plan_run_range(qs_state *st, qs_plan *P, int begin, int end)
 {
@@ -746,7 +764,7 @@ QS_API int qs_plan_run_range(qs_state *st, qs_plan *P, int begin, int end)
         switch (pp.type) {
         case 0: {
             const InsBits outer = qs_make_ins(pp.lmask, 0);
-            QS_HIP(launch_block(st->dtype, pp.b, st->psi, (uint64_t)1 << (P->n - pp.b), outer, pp.bm,
+            QS_HIP(launch_block(st->dtype, pp.b, pp.sw, st->psi, (uint64_t)1 << (P->n - pp.b), outer, pp.bm,
                                 P->dstages + pp.stage_begin, pp.nstages, P->dsops, P->dpool, st->stream));
             break;
         }
@@ -1019,7 +1037,7 @@ QS_API int qs_batch_add(qs_batch *Bt, const qs_circuit *c)
     const int bb = std::min(c->n, Bt->b);
     qs_plan_opts o{QS_PLAN_BLOCK, bb, std::min(Bt->low, bb), Bt->dtype};
     qs_plan *P = nullptr;
-    if (int rc = qs_plan_create(&P, c, &o))
+    if (int rc = plan_create(&P, c, &o, 4))  // the batch kernel runs 4-position stages
         return rc;
     for (const PlanPass &pp : P->passes)
         if (pp.type != 0) {

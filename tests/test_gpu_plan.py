@@ -94,3 +94,21 @@ def test_plan_rejects_mismatched_state(gpu):
     with pytest.raises(gpu.QSError):
         p.run(st)
     st.close()
+
+
+@pytest.fixture
+def stage_width_3():
+    from paper_2203_16044_amd import binding as B
+    B.qs_set_tunable("block_stage_width", 3)
+    yield
+    B.qs_set_tunable("block_stage_width", 4)
+
+
+@pytest.mark.parametrize("bits,low", [(12, 4), (12, 3), (13, 3), (11, 3)])
+@pytest.mark.parametrize("dtype,tol", [("c128", TOL128), ("c64", 2e-5)])
+def test_plan_three_position_stages(gpu, stage_width_3, bits, low, dtype, tol):
+    """3-position register stages (512-thread kernel for 12- and 13-qubit blocks; other sizes keep 4 positions)."""
+    for circ in (C.random_circuit(15, seed=431, num_ops=150, kmax=3), C.config2(n=17, seed=33, layers=8)):
+        psi0 = C.random_state(circ.n, 7)
+        got, _ = _run_plan(gpu, circ, "block", bits, low, psi0, dtype)
+        assert _maxerr(got, oracle.run(circ, psi0)) <= tol, circ.name
