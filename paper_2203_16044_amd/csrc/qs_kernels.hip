@@ -415,6 +415,42 @@ __global__ __launch_bounds__(256) void k_fswap_lds(C2 *__restrict__ psi, uint64_
     }
 }
 
+// Wide-row form for runs shorter than 256 bytes whose 2^s x 2^s tile fits 32 KiB. With x low "mid" bits carried along, the segment
+// (mid_low, B, e) for fixed A is contiguous: 2^(x+s+lo) amplitudes (kilobytes). A workgroup loads the 2^s rows
+// A = a of one work item with coalesced 16-byte lanes into LDS and writes every row b back with the element at
+// (mid_low, B = a, e) taken from row a at (mid_low, B = b, e): 2^x independent 2^s x 2^s transposes at once.
+// Fixed points (a == b) share cache lines with moved amplitudes at these sizes and are rewritten unchanged.
+template <class C2>
+__global__ __launch_bounds__(256) void k_fswap_wide(C2 *__restrict__ psi, uint64_t nwork, int lo, int hi, int s,
+                                                    int x)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    C2 *X = reinterpret_cast<C2 *>(smem_raw);
+    const int R = 1 << (x + s + lo);  // amplitudes per row
+    const int RP = R + 1;             // padded LDS row
+    const int S = 1 << s;
+    const int nel = S * R;
+    const int nmid_hi = hi - lo - s - x;  // mid bits above the carried ones
+    const int bshift = lo, bmask = S - 1;
+    for (uint64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+        const uint64_t midh = w & (((uint64_t)1 << nmid_hi) - 1);
+        const uint64_t top = w >> nmid_hi;
+        const uint64_t base = (top << (hi + s)) | (midh << (lo + s + x));
+        for (int u = threadIdx.x; u < nel; u += blockDim.x) {
+            const int a = u / R, c = u - a * R;
+            X[a * RP + c] = psi[base | ((uint64_t)a << hi) | (uint64_t)c];
+        }
+        lds_barrier();
+        for (int u = threadIdx.x; u < nel; u += blockDim.x) {
+            const int b = u / R, c = u - b * R;
+            const int a = (c >> bshift) & bmask;                       // B field of the destination = source row
+            const int cs = (c & ~(bmask << bshift)) | (b << bshift);  // source column: B field = b
+            psi[base | ((uint64_t)b << hi) | (uint64_t)c] = X[a * RP + cs];
+        }
+        lds_barrier();
+    }
+}
+
 // ---------------------------------------------------------------------------------------------------------
 // probabilities, norm, scale, init
 // ---------------------------------------------------------------------------------------------------------
@@ -733,6 +769,23 @@ hipError_t fswap_t(void *psi_, int n, int lo, int hi, int s_, hipStream_t s)
         const uint64_t total = outer * npairs * ((uint64_t)1 << lo);
         hipLaunchKernelGGL(k_fswap_runs<C2>, dim3(grid_for(total, 256)), dim3(256), 0, s, psi, total, lo, hi, s_,
                            npairs);
+        return hipGetLastError();
+    }
+    if (((size_t)1 << (2 * s_ + lo)) * sz <= 32768) {
+        // wide rows whenever the 2^s x 2^s tile of runs fits 32 KiB (larger tiles with short rows measured slower
+        // than the sub-tile form below): carry x low mid bits so that a tile holds about 32 KiB (or all mid bits
+        // if fewer)
+        const int nmid = hi - lo - s_;
+        const int tile_log = (sz == 16 ? 11 : 12);
+        int x = tile_log - 2 * s_ - lo;
+        if (x > nmid)
+            x = nmid;
+        if (x < 0)
+            x = 0;
+        const uint64_t nwork = (uint64_t)1 << (n - 2 * s_ - lo - x);
+        const size_t shm = (size_t)(1 << s_) * ((1 << (x + s_ + lo)) + 1) * sz;
+        const unsigned g = (unsigned)(nwork < (1u << 20) ? nwork : (1u << 20));
+        hipLaunchKernelGGL(k_fswap_wide<C2>, dim3(g), dim3(256), shm, s, psi, nwork, lo, hi, s_, x);
         return hipGetLastError();
     }
     // LDS sub-tiles: largest T = 2^ts <= 2^s with T*T*2^lo amplitudes <= 16 KiB per tile

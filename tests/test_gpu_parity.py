@@ -165,7 +165,24 @@ FSWAP_CASES = [
     (18, 1, 12, 5), (18, 2, 9, 6), (18, 3, 11, 7), (20, 0, 14, 6),  # LDS path, various run lengths
     (18, 4, 12, 6), (18, 6, 12, 6), (20, 5, 15, 5), (19, 4, 8, 3),  # run path (>= 256-byte runs)
     (16, 12, 0, 4),  # reversed argument order
+    # wide-row path (s <= 3, runs < 256 B): carried mid bits x = 9/7/5, capped by few mid bits, none at all
+    (18, 0, 12, 1), (18, 0, 14, 2), (18, 0, 15, 3), (18, 1, 10, 2), (18, 2, 9, 3), (18, 3, 11, 2),
+    (14, 0, 3, 1), (12, 0, 2, 2), (12, 1, 4, 3), (9, 0, 3, 3), (20, 0, 17, 3),
+    (20, 0, 13, 6), (13, 0, 6, 6), (16, 0, 10, 5), (17, 1, 9, 5),  # wide rows with 32-64 KiB tiles
 ]
+
+
+@pytest.mark.parametrize("n,p,q,s", [(18, 0, 12, 1), (18, 0, 14, 2), (18, 0, 15, 3), (18, 4, 9, 3), (12, 0, 2, 2),
+                                     (18, 1, 12, 5), (18, 5, 12, 6), (20, 0, 13, 6), (16, 1, 8, 6)])
+def test_fused_swap_complex64_bit_exact(gpu, n, p, q, s):
+    psi = C.random_state(n, n + 3 * s).astype(np.complex64)
+    st = gpu.State(n, "c64")
+    st.set(psi)
+    st.fused_swap(p, q, s)
+    ref = psi.astype(np.complex128)
+    oracle.fused_swap(ref, p, q, s)
+    assert st.get().tobytes() == ref.astype(np.complex64).tobytes()
+    st.close()
 
 
 @pytest.mark.parametrize("n,p,q,s", FSWAP_CASES)
