@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_TBS = 8.0  # MI355X HBM3E, published
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (= FP64 MFMA): 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
 
 # HBM traffic per dispatch of the dominant kernels, from two rocprofv3 PMC runs of this script (FETCH_SIZE, then
 # WRITE_SIZE; KiB per dispatch, mean over the 32-qubit dispatches), each scaled by what the same counter reads for
@@ -35,12 +36,12 @@ HBM_PEAK_TBS = 8.0  # MI355X HBM3E, published
 # the bytes read, WRITE_SIZE 4194304 KiB, all bytes written). Commands and figures: profiles/*_pmc_traffic.md. The readings hold for the kernel sources they were taken on: `sha1` fingerprints
 # those files and the traffic is reported as null once they differ.
 PMC_TRAFFIC = {
-    "block_b12": {"fetch_kib": 33585331.24, "write_kib": 67115266.55, "fetch_scale": 2.0, "write_scale": 1.0,
+    "block_b12": {"fetch_kib": 33585373.34, "write_kib": 67111340.19, "fetch_scale": 2.0, "write_scale": 1.0,
                   "sources": ["paper_2203_16044_amd/csrc/qs_block.hip", "paper_2203_16044_amd/csrc/qs_internal.h"],
-                  "sha1": "859da6ca17405dc1d1c735c22e692bc1bd0f56f8"},
-    "dense_k1": {"fetch_kib": 33554446.77, "write_kib": 67110649.03, "fetch_scale": 2.0, "write_scale": 1.0,
+                  "sha1": "6ae18a5bc0eb9388bddf3ec1c2a805a40228ac38"},
+    "dense_k1": {"fetch_kib": 33554442.22, "write_kib": 67110636.53, "fetch_scale": 2.0, "write_scale": 1.0,
                  "sources": ["paper_2203_16044_amd/csrc/qs_kernels.hip", "paper_2203_16044_amd/csrc/qs_internal.h"],
-                 "sha1": "16409c133a9994ea26340f0b7c7444d6c10f31c2"},
+                 "sha1": "09f3c1c23a085b0c65ebc778517dc6d44a092b80"},
 }
 
 
@@ -76,6 +77,17 @@ def _alg_bytes(op, n, amp):
     raise ValueError(op.kind)
 
 
+def _alg_flops(op, n):
+    """Flops one op performs (complex arithmetic counted in real flops: 8 per complex multiply-add)."""
+    if op.kind == "dense":
+        return 8 * (1 << len(op.targets)) * (1 << n)
+    if op.kind == "diag":
+        return 6 * (1 << n)
+    if op.kind == "ctrl":
+        return 8 * (1 << len(op.targets)) * (1 << (n - len(op.controls)))
+    return 0
+
+
 def _kernel_class(op):
     if op.kind == "dense":
         return f"dense_k{len(op.targets)}"
@@ -103,8 +115,9 @@ def run_plan(st, plan, npass, events):
 
 def time_steps(st, steps, warmup, body, units, torch):
     """Warm up, then time `steps` steps of reset + body + FP64 probability reduction. body(record) enqueues the
-    work; with record=True it records a (start, end) event pair around every launch unit. Returns
-    (per-step seconds, {class: [seconds, launches, alg_bytes]})."""
+    work; with record=True it records a (start, end) event pair around every launch unit. units holds
+    (class, algorithmic bytes, flops) per launch unit. Returns (per-step seconds,
+    {class: [seconds, launches, alg_bytes, flops]})."""
     import paper_2203_16044_amd as qs
     mk = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     events = [(mk(), mk()) for _ in units]
@@ -123,11 +136,12 @@ def time_steps(st, steps, warmup, body, units, torch):
         e1.record(st.stream)
         e1.synchronize()
         times.append(e0.elapsed_time(e1) / 1e3)
-        for (cls, nbytes), (a, b) in zip(units, events):
-            c = per.setdefault(cls, [0.0, 0, 0])
+        for (cls, nbytes, flops), (a, b) in zip(units, events):
+            c = per.setdefault(cls, [0.0, 0, 0, 0])
             c[0] += a.elapsed_time(b) / 1e3
             c[1] += 1
             c[2] += nbytes
+            c[3] += flops
     torch.cuda.synchronize()
     return times, per
 
@@ -301,7 +315,7 @@ def main():
     log0("bench: plain leg")
     # plain: one pass per gate (on a prefix of the circuit in tuned mode: the per-gate rate is layer-invariant)
     plain_ops = ops if args.mode == "plain" else [o for o in ops if o.layer <= args.plain_layers]
-    units = [(_kernel_class(o), _alg_bytes(o, n, 16)) for o in plain_ops]
+    units = [(_kernel_class(o), _alg_bytes(o, n, 16), _alg_flops(o, n)) for o in plain_ops]
     p_times, p_per = time_steps(st, args.steps if args.mode == "plain" else 1,
                                 args.warmup if args.mode == "plain" else 0,
                                 lambda ev: run_plain(st, plain_ops, ev) if ev else [st.apply_op(o) for o in plain_ops],
@@ -328,8 +342,11 @@ def main():
             info = plan.info()
             passes = plan.passes()
             kinds = {0: f"block_b{bits}", 1: "dense_k{}", 2: "fswap", 3: "other"}
+            # flops of a pass from the planner's features (flops per amplitude, / 256) x amplitudes
+            fl = [float(qs.binding.qs_plan_features(plan.h, i)[14]) * 256 * (1 << n) for i in range(len(passes))]
             units = [(kinds[ps["type"]].format(ps["nqubits"]),
-                      int(full * (1 - 2.0 ** -(ps["nqubits"] // 2))) if ps["type"] == 2 else full) for ps in passes]
+                      int(full * (1 - 2.0 ** -(ps["nqubits"] // 2))) if ps["type"] == 2 else full, int(fl[i]))
+                     for i, ps in enumerate(passes)]
             main = vi == 0
             times, per = time_steps(st, args.steps if main else 1, args.warmup if main else 1,
                                     lambda ev, plan=plan, npass=len(passes): run_plan(st, plan, npass, ev) if ev
@@ -352,9 +369,19 @@ def main():
 
     t_step = sum(step_times) / len(step_times)
     dom = max(per_class, key=lambda c: per_class[c][0])
-    tsum, cnt, bsum = per_class[dom]
+    tsum, cnt, bsum, fsum = per_class[dom]
     avg = tsum / cnt
     achieved = (bsum / cnt) / avg / 1e12
+    tflops = (fsum / cnt) / avg / 1e12
+    # the binding roof of the dominant kernel: the larger of its HBM time and its FP64 time at peak
+    t_hbm = (bsum / cnt) / (HBM_PEAK_TBS * 1e12)
+    t_alu = (fsum / cnt) / (FP64_PEAK_TFLOPS * 1e12)
+    if t_alu > t_hbm:
+        roof = {"bound": "alu", "achieved": tflops, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tflops / FP64_PEAK_TFLOPS}
+    else:
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_TBS, "unit": "TB/s",
+                "frac": achieved / HBM_PEAK_TBS}
     out = {
         "metric": "gates/s, 32-qubit complex128 random circuit (SU(4) pairings + U3, 40 layers); tuned vs plain",
         "value": gates / t_step,
@@ -374,10 +401,11 @@ def main():
                             (f"{head_v[0]} b={head_v[1]} low={head_v[2]}" if args.mode == "tuned"
                              else "one pass per gate")),
                    "parallelism": "none"},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_TBS, "unit": "TB/s",
-                     "frac": achieved / HBM_PEAK_TBS, "traffic": pmc_traffic(dom), "kernel": dom,
-                     "avg_launch_ms": avg * 1e3, "launches_per_step": cnt // len(step_times),
-                     "alg_bytes_per_launch": bsum // cnt},
+        "roofline": dict(roof, traffic=pmc_traffic(dom), kernel=dom, avg_launch_ms=avg * 1e3,
+                         launches_per_step=cnt // len(step_times), alg_bytes_per_launch=bsum // cnt,
+                         flops_per_launch=fsum // cnt, hbm_tbs=achieved, hbm_frac=achieved / HBM_PEAK_TBS,
+                         fp64_tflops=tflops, fp64_frac=tflops / FP64_PEAK_TFLOPS,
+                         frac_of_roofline=max(t_hbm, t_alu) / avg),
         "plain": {"gates_per_s": plain_rate, "gates_timed": len(plain_ops),
                   "per_kernel": summarize(p_per, len(p_times))},
         "speedup_vs_plain": (gates / t_step) / plain_rate,

@@ -282,8 +282,14 @@ QS_API int qs_probe_rmw(void *buf, size_t bytes, void *hip_stream);
  * "dense_gpt"   groups per thread of the 1- and 2-qubit dense kernels: 1, 2 or 4 (default 1);
  * "nontemporal" 0/1: non-temporal loads and stores in the dense kernels (default 1);
  * "mfma_wg_per_cu" persistent workgroups per compute unit of the k = 5, 6 MFMA block kernel (1..16, default 2);
- * "block_wg_per_cu" persistent workgroups per compute unit of the LDS block kernel (1..16, default 4).
- * Process-wide; affects launches enqueued after the call. QS_EINVAL for an unknown name or value. */
+ * "block_wg_per_cu" persistent workgroups per compute unit of the LDS block kernel (1..16, default 4);
+ * "block_stage_width" register stage width of block plans created afterwards: 4 (256-thread kernel, default) or
+ *                     3 (512-thread kernel with 8 register amplitudes per thread, for 12- and 13-qubit blocks);
+ * "plan_beam"   beam width of pass formation for plans created afterwards (0..64, default 16): the local set of a
+ *               pass grows one ready gate at a time, keeping the candidates that take the most gates; 0 selects
+ *               the fewest-new-qubits greedy. Batches always plan with 4-position stages.
+ * Process-wide; affects launches enqueued and plans created after the call. QS_EINVAL for an unknown name or
+ * value. */
 QS_API int qs_set_tunable(const char *name, int64_t value);
 
 #ifdef __cplusplus

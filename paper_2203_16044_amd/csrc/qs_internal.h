@@ -195,5 +195,6 @@ struct Tunables {
     int mfma_wg_per_cu = 2;  // persistent workgroups per CU for the MFMA block kernel
     int block_wg_per_cu = 4; // persistent workgroups per CU for the LDS block kernel
     int block_stage_width = 4; // register stage width of new block plans: 4, or 3 (512-thread kernel, b = 12, 13)
+    int plan_beam = 16;        // pass formation: beam width over local-set growth (0: fewest-new-qubits greedy)
 };
 Tunables &qs_tunables();

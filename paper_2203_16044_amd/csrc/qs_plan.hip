@@ -172,46 +172,139 @@ int check_list(int n, const int *q, int cnt, uint64_t *mask, const char *what)
 // ---- pass formation ----------------------------------------------------------------------------------------
 struct Former {
     const qs_circuit &c;
-    int b, w, max_block_q;
+    int b, w, max_block_q, beam;
     std::vector<std::vector<int>> qlist;
     std::vector<size_t> head;
-    std::vector<char> done;
 
-    Former(const qs_circuit &c_, int b_, int w_, int maxq) : c(c_), b(b_), w(w_), max_block_q(maxq)
+    Former(const qs_circuit &c_, int b_, int w_, int maxq, int beam_)
+        : c(c_), b(b_), w(w_), max_block_q(maxq), beam(beam_)
     {
         qlist.assign(c.n, {});
         head.assign(c.n, 0);
-        done.assign(c.gates.size(), 0);
         for (size_t g = 0; g < c.gates.size(); ++g)
             for (int q : c.gates[g].q)
                 qlist[q].push_back((int)g);
     }
-    bool ready(int g) const
+    bool ready(int g, const std::vector<size_t> &h) const
     {
         for (int q : c.gates[g].q)
-            if (head[q] >= qlist[q].size() || qlist[q][head[q]] != g)
+            if (h[q] >= qlist[q].size() || qlist[q][h[q]] != g)
                 return false;
         return true;
     }
-    void take(int g)
-    {
-        done[g] = 1;
-        for (int q : c.gates[g].q)
-            ++head[q];
-    }
     bool blockable(int g) const { return c.gates[g].kind == 0 && (int)c.gates[g].q.size() <= max_block_q; }
     // ready gates, ascending circuit index
-    std::vector<int> front() const
+    std::vector<int> front(const std::vector<size_t> &h) const
     {
         std::vector<int> f;
         for (int q = 0; q < c.n; ++q)
-            if (head[q] < qlist[q].size()) {
-                const int g = qlist[q][head[q]];
-                if (ready(g) && std::find(f.begin(), f.end(), g) == f.end())
+            if (h[q] < qlist[q].size()) {
+                const int g = qlist[q][h[q]];
+                if (ready(g, h) && std::find(f.begin(), f.end(), g) == f.end())
                     f.push_back(g);
             }
         std::sort(f.begin(), f.end());
         return f;
+    }
+
+    // A candidate pass: its local set L, the gates it takes (in a dependency-respecting order) and the DAG position
+    // after them.
+    struct Cand {
+        std::vector<int> L;
+        std::vector<size_t> h;
+        std::vector<int> gates;
+    };
+    // take every ready blockable gate inside L, repeatedly (the result depends only on L and the start position)
+    void closure(Cand &s) const
+    {
+        bool changed = true;
+        while (changed) {
+            changed = false;
+            for (int g : front(s.h))
+                if (blockable(g) && subset(c.gates[g].q, s.L)) {
+                    for (int q : c.gates[g].q)
+                        ++s.h[q];
+                    s.gates.push_back(g);
+                    changed = true;
+                }
+        }
+    }
+    // Grow L from the always-local low qubits. beam == 0: add the ready gate needing the fewest new qubits while
+    // L has room. beam >= 1: a beam search over growth steps, keeping the `beam` candidates that take the most
+    // gates (fewest qubits on ties); the pass is the candidate taking the most gates once none can grow.
+    Cand form_pass() const
+    {
+        Cand s0;
+        for (int q = 0; q < w && q < c.n; ++q)
+            s0.L.push_back(q);
+        s0.h = head;
+        closure(s0);
+        if (beam == 0) {
+            for (;;) {
+                int best = -1, bestnew = 1 << 30;
+                for (int g : front(s0.h)) {
+                    if (!blockable(g))
+                        continue;
+                    int nw = 0;
+                    for (int q : c.gates[g].q)
+                        nw += std::find(s0.L.begin(), s0.L.end(), q) == s0.L.end();
+                    if ((int)s0.L.size() + nw <= b && nw < bestnew) {
+                        best = g;
+                        bestnew = nw;
+                    }
+                }
+                if (best < 0)
+                    return s0;
+                for (int q : c.gates[best].q)
+                    if (std::find(s0.L.begin(), s0.L.end(), q) == s0.L.end())
+                        s0.L.push_back(q);
+                closure(s0);
+            }
+        }
+        std::vector<Cand> cur{s0};
+        Cand best = s0;
+        while (!cur.empty()) {
+            std::vector<Cand> nxt;
+            for (const Cand &st : cur) {
+                bool grown = false;
+                for (int g : front(st.h)) {
+                    if (!blockable(g))
+                        continue;
+                    int nw = 0;
+                    for (int q : c.gates[g].q)
+                        nw += std::find(st.L.begin(), st.L.end(), q) == st.L.end();
+                    if (nw == 0 || (int)st.L.size() + nw > b)
+                        continue;
+                    Cand t = st;
+                    for (int q : c.gates[g].q)
+                        if (std::find(t.L.begin(), t.L.end(), q) == t.L.end())
+                            t.L.push_back(q);
+                    std::sort(t.L.begin(), t.L.end());
+                    closure(t);
+                    nxt.push_back(std::move(t));
+                    grown = true;
+                }
+                if (!grown && st.gates.size() > best.gates.size())
+                    best = st;
+            }
+            std::stable_sort(nxt.begin(), nxt.end(), [](const Cand &x, const Cand &y) {
+                return x.gates.size() != y.gates.size() ? x.gates.size() > y.gates.size() : x.L.size() < y.L.size();
+            });
+            cur.clear();
+            for (Cand &t : nxt) {
+                bool dup = false;
+                for (const Cand &u : cur)
+                    if (u.L == t.L) {
+                        dup = true;
+                        break;
+                    }
+                if (!dup)
+                    cur.push_back(std::move(t));
+                if ((int)cur.size() >= beam)
+                    break;
+            }
+        }
+        return best;
     }
 
     void run(std::vector<std::pair<std::vector<int>, std::vector<int>>> &out_passes, std::vector<int> &singles_order)
@@ -219,52 +312,21 @@ struct Former {
         // out_passes: (L sorted, gates) for blockable passes; singles are encoded as L empty + one gate
         size_t remaining = c.gates.size();
         while (remaining) {
-            std::vector<int> L;
-            for (int q = 0; q < w && q < c.n; ++q)
-                L.push_back(q);
-            std::vector<int> pass;
-            for (;;) {
-                bool changed = true;
-                while (changed) {
-                    changed = false;
-                    for (int g : front())
-                        if (blockable(g) && subset(c.gates[g].q, L)) {
-                            take(g);
-                            pass.push_back(g);
-                            changed = true;
-                        }
-                }
-                int best = -1, bestnew = 1 << 30;
-                for (int g : front()) {
-                    if (!blockable(g))
-                        continue;
-                    int nw = 0;
-                    for (int q : c.gates[g].q)
-                        nw += std::find(L.begin(), L.end(), q) == L.end();
-                    if ((int)L.size() + nw <= b && nw < bestnew) {
-                        best = g;
-                        bestnew = nw;
-                    }
-                }
-                if (best < 0)
-                    break;
-                for (int q : c.gates[best].q)
-                    if (std::find(L.begin(), L.end(), q) == L.end())
-                        L.push_back(q);
-            }
-            if (!pass.empty()) {
-                // fill L up to b with the next qubits the front needs (they cost nothing) -- keep it sorted
-                std::sort(L.begin(), L.end());
-                remaining -= pass.size();
-                out_passes.emplace_back(L, pass);
+            Cand p = form_pass();
+            if (!p.gates.empty()) {
+                std::sort(p.L.begin(), p.L.end());
+                head = p.h;
+                remaining -= p.gates.size();
+                out_passes.emplace_back(p.L, p.gates);
                 continue;
             }
             // nothing blockable is ready: emit the earliest ready non-blockable gate on its own
-            std::vector<int> f = front();
+            std::vector<int> f = front(head);
             if (f.empty())
                 break;  // cannot happen for a well-formed circuit
             const int g = f[0];
-            take(g);
+            for (int q : c.gates[g].q)
+                ++head[q];
             --remaining;
             out_passes.emplace_back(std::vector<int>(), std::vector<int>{g});
             singles_order.push_back(g);
@@ -594,7 +656,7 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
     P->mode = mode;
     P->raw = c->raw;
     const int maxq = mode == QS_PLAN_BLOCK ? kMaxBlockOpK : b;
-    Former F(*c, b, w, maxq);
+    Former F(*c, b, w, maxq, qs_tunables().plan_beam);
     std::vector<std::pair<std::vector<int>, std::vector<int>>> passes;
     std::vector<int> singles;
     F.run(passes, singles);
