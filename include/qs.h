@@ -247,11 +247,11 @@ QS_API int qs_mlp_train_step(qs_mlp *m, const float *X, const float *T, int B, f
  * compute unit). Circuits of at most block_bits qubits run start to finish inside one workgroup's LDS during the
  * first launch. Every circuit starts in |0..0>, generated in the first pass, and its last pass writes its FP64
  * output probabilities instead of amplitudes.
- *   block_bits 10..12 (the LDS block), low_bits the always-local low qubits, wg_per_cu 1..8 persistent
+ *   block_bits 10..12 (the LDS block), low_bits the always-local low qubits, wg_per_cu 1..64 persistent
  *   workgroups per compute unit (tile and schedule parameters chosen by the autotuner). */
 typedef struct qs_batch qs_batch;
 QS_API int qs_batch_create(qs_batch **out, int dtype, int block_bits, int low_bits, int wg_per_cu, void *hip_stream);
-/* Change the persistent workgroups per CU (1..8) of later runs; a captured graph is dropped (the call waits for the
+/* Change the persistent workgroups per CU (1..64) of later runs; a captured graph is dropped (the call waits for the
  * batch's stream first) and captured again by the next graph run. Host-side only otherwise. */
 QS_API int qs_batch_set_launch(qs_batch *b, int wg_per_cu);
 /* Plan and append a circuit (host only). QS_EUNSUPPORTED for circuits outside the batch's scope. */
@@ -282,7 +282,9 @@ QS_API int qs_probe_rmw(void *buf, size_t bytes, void *hip_stream);
  * "dense_gpt"   groups per thread of the 1- and 2-qubit dense kernels: 1, 2 or 4 (default 1);
  * "nontemporal" 0/1: non-temporal loads and stores in the dense kernels (default 1);
  * "mfma_wg_per_cu" persistent workgroups per compute unit of the k = 5, 6 MFMA block kernel (1..16, default 2);
- * "block_wg_per_cu" persistent workgroups per compute unit of the LDS block kernel (1..16, default 4);
+ * "block_wg_per_cu" persistent 256-thread workgroups per compute unit of the LDS block kernel (1..4096, default
+ *               32: a grid far larger than the resident workgroups measured fastest; smaller workgroups are
+ *               scaled up proportionally);
  * "block_stage_width" register stage width of block plans created afterwards: 4 (256-thread kernel, default) or
  *                     3 (512-thread kernel with 8 register amplitudes per thread, for 12- and 13-qubit blocks);
  * "plan_beam"   beam width of pass formation for plans created afterwards (0..64, default 16): the local set of a

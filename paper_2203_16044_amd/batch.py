@@ -21,7 +21,7 @@ from .plan import Circuit
 CACHE = os.environ.get("QS_AUTOTUNE_CACHE",
                        os.path.join(os.path.dirname(os.path.abspath(__file__)), ".autotune_cache.json"))
 DEFAULT = {"block_bits": 12, "low_bits": 4, "wg_per_cu": 2}
-SPACE = [{"block_bits": b, "low_bits": w, "wg_per_cu": g} for b in (10, 11, 12) for w in (3, 4) for g in (1, 2, 4)]
+SPACE = [{"block_bits": b, "low_bits": w, "wg_per_cu": g} for b in (10, 11, 12) for w in (3, 4) for g in (2, 8, 32)]
 
 
 def record(circuits) -> List[Circuit]:

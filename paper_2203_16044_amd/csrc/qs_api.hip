@@ -628,8 +628,8 @@ QS_API int qs_set_tunable(const char *name, int64_t value)
             return qs_fail(QS_EINVAL, "mfma_wg_per_cu must be in [1, 16]");
         t.mfma_wg_per_cu = (int)value;
     } else if (!std::strcmp(name, "block_wg_per_cu")) {
-        if (value < 1 || value > 16)
-            return qs_fail(QS_EINVAL, "block_wg_per_cu must be in [1, 16]");
+        if (value < 1 || value > 4096)
+            return qs_fail(QS_EINVAL, "block_wg_per_cu must be in [1, 4096]");
         t.block_wg_per_cu = (int)value;
     } else if (!std::strcmp(name, "plan_beam")) {
         if (value < 0 || value > 64)

@@ -208,11 +208,18 @@ __device__ __forceinline__ void run_stage_n(typename BT<R>::C2 *s, const BlkStag
     }
 }
 
-// NT threads per workgroup: 256 with 4-position stages; 512 with 3-position stages (8 register amplitudes per
-// thread, so that two 64 KB complex128 blocks per CU run 16 waves when the kernel stays within 128 VGPRs).
-template <int NT> struct BlockBounds;
-template <> struct BlockBounds<256> { static constexpr int waves_per_eu = 1; };
+// NT threads per workgroup: one register group per thread with 4-position stages (64 threads for 10-qubit blocks,
+// 128 for 11, 256 for 12 and 13); 512 with 3-position stages (8 register amplitudes per thread, so that two 64 KB
+// complex128 blocks per CU run 16 waves when the kernel stays within 128 VGPRs).
+template <int NT> struct BlockBounds { static constexpr int waves_per_eu = 1; };
 template <> struct BlockBounds<512> { static constexpr int waves_per_eu = 4; };
+
+// Threads of a block workgroup: one 2^W-amplitude group per thread (at least one wave; 4-position stages of
+// 13-qubit blocks take two groups per thread).
+template <int B, int W> struct BlockThreads {
+    static constexpr int groups = 1 << (B - W);
+    static constexpr int value = W == 3 ? 512 : (groups < 64 ? 64 : (groups > 256 ? 256 : groups));
+};
 
 template <class R, int B, int W, int NT>
 __global__ __launch_bounds__(NT, BlockBounds<NT>::waves_per_eu) void k_block(
@@ -492,7 +499,7 @@ hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const Bloc
                    int nstages, const BlkStageOp *sops, const void *mats, hipStream_t s)
 {
     using C2 = typename BT<R>::C2;
-    constexpr int NT = W == 3 ? 512 : 256;
+    constexpr int NT = BlockThreads<B, W>::value;
     static_assert((1 << B) >= NT, "block smaller than the workgroup");
     const size_t shm = sizeof(C2) << B;
     static bool attr_set = false;
@@ -507,7 +514,10 @@ hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const Bloc
     int cus = 0, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
         cus = 256;
-    uint64_t grid = (uint64_t)cus * qs_tunables().block_wg_per_cu;
+    // block_wg_per_cu counts 256-thread workgroups: smaller workgroups get proportionally more
+    uint64_t grid = (uint64_t)cus * qs_tunables().block_wg_per_cu * 256 / NT;
+    if (grid < (uint64_t)cus)
+        grid = cus;
     if (grid > nblocks)
         grid = nblocks;
     hipLaunchKernelGGL((k_block<R, B, W, NT>), dim3((unsigned)grid), dim3(NT), shm, s, (C2 *)psi, nblocks, outer, bm,

@@ -193,7 +193,7 @@ struct Tunables {
     int dense_gpt = 1;       // groups per thread for k = 1, 2
     int nontemporal = 1;     // use non-temporal loads/stores in the plain gate kernels
     int mfma_wg_per_cu = 2;  // persistent workgroups per CU for the MFMA block kernel
-    int block_wg_per_cu = 4; // persistent workgroups per CU for the LDS block kernel
+    int block_wg_per_cu = 32; // persistent workgroups per CU for the LDS block kernel (in 256-thread units)
     int block_stage_width = 4; // register stage width of new block plans: 4, or 3 (512-thread kernel, b = 12, 13)
     int plan_beam = 16;        // pass formation: beam width over local-set growth (0: fewest-new-qubits greedy)
 };

@@ -1050,7 +1050,7 @@ QS_API int qs_batch_create(qs_batch **out, int dtype, int block_bits, int low_bi
         return qs_fail(QS_EINVAL, "qs_batch_create: bad dtype %d", dtype);
     if (block_bits < 10 || block_bits > 12)
         return qs_fail(QS_EINVAL, "qs_batch_create: block_bits = %d outside [10, 12]", block_bits);
-    if (low_bits < 0 || low_bits > block_bits || wg_per_cu < 1 || wg_per_cu > 8)
+    if (low_bits < 0 || low_bits > block_bits || wg_per_cu < 1 || wg_per_cu > 64)
         return qs_fail(QS_EINVAL, "qs_batch_create: low_bits or wg_per_cu out of range");
     qs_batch *Bt = new (std::nothrow) qs_batch();
     if (!Bt)
@@ -1069,8 +1069,8 @@ QS_API int qs_batch_set_launch(qs_batch *Bt, int wg_per_cu)
     qs_clear_error();
     if (!Bt)
         return qs_fail(QS_EINVAL, "qs_batch_set_launch: NULL batch");
-    if (wg_per_cu < 1 || wg_per_cu > 8)
-        return qs_fail(QS_EINVAL, "qs_batch_set_launch: wg_per_cu = %d outside [1, 8]", wg_per_cu);
+    if (wg_per_cu < 1 || wg_per_cu > 64)
+        return qs_fail(QS_EINVAL, "qs_batch_set_launch: wg_per_cu = %d outside [1, 64]", wg_per_cu);
     if (wg_per_cu == Bt->wg_per_cu)
         return QS_OK;
     // a captured graph holds the old grid: drop it (after the stream has finished with it)

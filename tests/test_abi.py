@@ -68,6 +68,11 @@ def test_tunables_validate():
     with pytest.raises(qs.QSError):
         B.qs_set_tunable("dense_gpt", 3)
     B.qs_set_tunable("dense_gpt", 1)
+    for name, bad, good in (("block_wg_per_cu", 0, 32), ("block_wg_per_cu", 4097, 32), ("block_stage_width", 5, 4),
+                            ("plan_beam", 65, 16), ("plan_beam", -1, 16)):
+        with pytest.raises(qs.QSError):
+            B.qs_set_tunable(name, bad)
+        B.qs_set_tunable(name, good)  # the defaults
 
 
 def test_binding_rejects_matrix_shape_mismatch():

@@ -80,7 +80,7 @@ def test_batch_host_validation():
     with pytest.raises(B.QSError):
         B.qs_batch_create(B.QS_C128, 13, 4, 2)
     with pytest.raises(B.QSError):
-        B.qs_batch_create(B.QS_C128, 12, 4, 9)
+        B.qs_batch_create(B.QS_C128, 12, 4, 65)
     b = B.qs_batch_create(B.QS_C128, 12, 4, 2)
     small = Circuit.from_ops(6, C.random_circuit(6, 1, num_ops=10, kmax=2, kinds=("dense",)).ops)
     with pytest.raises(B.QSError) as ei:
