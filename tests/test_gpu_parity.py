@@ -317,3 +317,23 @@ def test_complex64_moves_bit_exact(gpu):
     psi = _with_signed_zeros(C.random_state(n, 3).astype(np.complex64).astype(np.complex128), 3)
     got, ref = _run_both(gpu, n, ops, psi, dtype="c64")
     assert got.tobytes() == ref.astype(np.complex64).tobytes()
+
+
+@pytest.mark.parametrize("n", [6, 7, 9, 12])
+def test_complex64_one_qubit_every_target_and_diagonals(gpu, n):
+    """complex64: every target of a 1-qubit gate (lane-exchange form below 4, shared-vector form at 0) and 1- and
+    2-qubit diagonals (two amplitudes per 16-byte lane), against the FP64 oracle from the FP32-rounded input."""
+    rng = _rng(900 + n)
+    ops = [C.Op("dense", (q,), mat=_rand_u(rng, 2)) for q in range(n)]
+    ops += [C.Op("diag", (q,), mat=C.rz(float(rng.uniform(0, 6.28)))) for q in range(n)]
+    ops += [C.Op("diag", (0, n - 1), mat=C.CZ_DIAG), C.Op("diag", (1, 2), mat=np.exp(1j * rng.uniform(0, 6, 4)))]
+    psi = C.random_state(n, 901).astype(np.complex64)
+    st = gpu.State(n, "c64")
+    st.set(psi)
+    for op in ops:
+        st.apply_op(op)
+    ref = psi.astype(np.complex128)
+    for op in ops:
+        oracle.apply_op(ref, op)
+    assert _maxerr(st.get(), ref) <= 1e-5
+    st.close()
