@@ -211,8 +211,10 @@ __device__ __forceinline__ void run_stage_n(typename BT<R>::C2 *s, const BlkStag
 // NT threads per workgroup: one register group per thread with 4-position stages (64 threads for 10-qubit blocks,
 // 128 for 11, 256 for 12 and 13); 512 with 3-position stages (8 register amplitudes per thread, so that two 64 KB
 // complex128 blocks per CU run 16 waves when the kernel stays within 128 VGPRs).
-template <int NT> struct BlockBounds { static constexpr int waves_per_eu = 1; };
-template <> struct BlockBounds<512> { static constexpr int waves_per_eu = 4; };
+template <class R, int NT> struct BlockBounds { static constexpr int waves_per_eu = 1; };
+template <class R> struct BlockBounds<R, 512> { static constexpr int waves_per_eu = 4; };
+// (asking the complex64 256-thread instance for 4 waves per SIMD forces <= 128 VGPRs and spills: measured 22 %
+// slower than the compiler's own choice of ~150 VGPRs and 3 waves)
 
 // Threads of a block workgroup: one 2^W-amplitude group per thread (at least one wave; 4-position stages of
 // 13-qubit blocks take two groups per thread).
@@ -222,7 +224,7 @@ template <int B, int W> struct BlockThreads {
 };
 
 template <class R, int B, int W, int NT>
-__global__ __launch_bounds__(NT, BlockBounds<NT>::waves_per_eu) void k_block(
+__global__ __launch_bounds__(NT, (BlockBounds<R, NT>::waves_per_eu)) void k_block(
     typename BT<R>::C2 *__restrict__ psi, uint64_t nblocks, InsBits outer, BlockMap bm,
     const BlkStage *__restrict__ stages, int nstages, const BlkStageOp *__restrict__ sops, const R *__restrict__ mats)
 {
@@ -241,7 +243,6 @@ __global__ __launch_bounds__(NT, BlockBounds<NT>::waves_per_eu) void k_block(
     // the current block's stages run, so HBM traffic overlaps the FP arithmetic. The loop is rotated so that wherever
     // the prefetched registers are consumed, exactly the prefetch loads and then the previous block's stores are in
     // flight: the wait needs only the loads (vmcnt(PER)) and the stores keep draining behind the next block's stages.
-    // The last prefetch of a workgroup re-reads its own block (one redundant block read per workgroup).
     using NV = typename NT2<R>::type;
     NV pre[PER];
     uint64_t blk = blockIdx.x;
@@ -261,10 +262,13 @@ __global__ __launch_bounds__(NT, BlockBounds<NT>::waves_per_eu) void k_block(
     lds_barrier();
     for (;;) {
         const uint64_t nxt = blk + gridDim.x;
-        const uint64_t nbase = ins0b(nxt < nblocks ? nxt : blk, outer) | own;
+        const bool more = nxt < nblocks;  // uniform
+        const uint64_t nbase = ins0b(more ? nxt : blk, outer) | own;
+        if (more) {
 #pragma unroll
-        for (int it = 0; it < PER; ++it)
-            pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(psi + nbase + hi[it]));
+            for (int it = 0; it < PER; ++it)
+                pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(psi + nbase + hi[it]));
+        }
         for (int t = 0; t < nstages; ++t) {
             run_stage<R, B, W, NT>(s, stages[t], sops, mats);
             lds_barrier();
@@ -404,7 +408,7 @@ __global__ __launch_bounds__(256) void k_batch_level(typename BT<R>::C2 *__restr
     if (g >= nblocks)
         return;
     // HBM blocks: the rotated pipeline of k_block (prefetch of the next block before the stages; waits only on the
-    // prefetch loads, the previous block's stores keep draining); the last prefetch re-reads the current block.
+    // prefetch loads, the previous block's stores keep draining).
     NV pre[PER];
     const BatchPass *bp = &passes[cur.pass];
     uint64_t base = ins0b(g - cur.blk_begin, bp->outer) | spread(threadIdx.x, bp->bm);
@@ -413,11 +417,13 @@ __global__ __launch_bounds__(256) void k_batch_level(typename BT<R>::C2 *__restr
     lds_barrier();
     for (;;) {
         const uint32_t nx = g + gridDim.x;
-        const uint32_t ng = nx < nblocks ? nx : g;
+        const bool more = nx < nblocks;  // uniform
+        const uint32_t ng = more ? nx : g;
         const BatchItem nt = items[find_item(items, nitems, ng)];
         const BatchPass *np = &passes[nt.pass];
         const uint64_t nbase = ins0b(ng - nt.blk_begin, np->outer) | spread(threadIdx.x, np->bm);
-        batch_fetch<R, B>(pre, psi_base + nt.state_off, nbase, np->bm);
+        if (more)
+            batch_fetch<R, B>(pre, psi_base + nt.state_off, nbase, np->bm);
         for (int t = 0; t < bp->nstages; ++t) {
             run_stage<R, B, 4, 256>(s, stages[bp->stage_begin + t], sops, mats);
             lds_barrier();
