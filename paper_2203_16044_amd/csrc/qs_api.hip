@@ -631,6 +631,10 @@ QS_API int qs_set_tunable(const char *name, int64_t value)
         if (value < 1 || value > 4096)
             return qs_fail(QS_EINVAL, "block_wg_per_cu must be in [1, 4096]");
         t.block_wg_per_cu = (int)value;
+    } else if (!std::strcmp(name, "block_async")) {
+        if (value != 0 && value != 1)
+            return qs_fail(QS_EINVAL, "block_async must be 0 or 1");
+        t.block_async = (int)value;
     } else if (!std::strcmp(name, "plan_beam")) {
         if (value < 0 || value > 64)
             return qs_fail(QS_EINVAL, "plan_beam must be in [0, 64]");

@@ -297,6 +297,102 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, NT>::waves_per_eu)) void k_bloc
     }
 }
 
+// Double-buffered block pass: the next block streams from HBM straight into the other LDS buffer (direct-to-LDS
+// 16-byte loads, no registers involved) while the current block's stages run, so HBM traffic and arithmetic
+// overlap inside one workgroup. Load instruction `it` of wave w fills slots [256 it + 64 w, +64), one 16-byte slot
+// per lane in lane order; lane l fetches the element whose local index is swz(slot) (swz is an involution), so
+// slot swz(m) holds local index m exactly as in k_block. Waits are explicit: before the stages a wave needs its
+// loads of the current block, which precede at most the previous block's stores and the next block's loads.
+// gfx9 s_waitcnt immediate waiting for vmcnt <= n only (expcnt and lgkmcnt left at their maxima)
+template <int n> struct VmWait { static constexpr int imm = (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); };
+
+// Workgroup barrier for the double-buffered pass: waits for this wave's LDS operations (lgkmcnt) only. A fence
+// would also wait for the direct-to-LDS loads of the next block in flight, which count as LDS writes; the asm
+// barrier with a memory clobber keeps the compiler from moving memory accesses across it, and the loads the
+// stages read were waited for explicitly (vmcnt) before the first barrier of the block.
+__device__ __forceinline__ void lds_sync_nofence()
+{
+    __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4) | (0 << 8));  // lgkmcnt(0); vmcnt, expcnt unconstrained
+    asm volatile("s_barrier" ::: "memory");
+}
+
+template <class R, int B>
+__global__ __launch_bounds__(256) void k_block_async(typename BT<R>::C2 *__restrict__ psi, uint64_t nblocks,
+                                                     InsBits outer, BlockMap bm, const BlkStage *__restrict__ stages,
+                                                     int nstages, const BlkStageOp *__restrict__ sops,
+                                                     const R *__restrict__ mats)
+{
+    using C2 = typename BT<R>::C2;
+    using NV = typename NT2<R>::type;
+    constexpr int NT = 256;
+    constexpr int N = 1 << B;
+    constexpr int PER = N / NT;
+    static_assert(PER == 16, "one 16-load fill per thread");
+    extern __shared__ __align__(16) unsigned char smem_blk[];
+    C2 *buf0 = reinterpret_cast<C2 *>(smem_blk);
+    C2 *buf1 = buf0 + N;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint64_t off[PER];  // load side: global offset (from the block base) of this lane's element for fill `it`
+    uint64_t hi[PER];   // store side: as in k_block
+#pragma unroll
+    for (int it = 0; it < PER; ++it) {
+        off[it] = spread(swz((uint32_t)(NT * it + 64 * wave + lane)), bm);
+        hi[it] = spread((uint32_t)(NT * it), bm);
+    }
+    const uint64_t own = spread(threadIdx.x, bm);
+    auto fill = [&](C2 *dst, uint64_t b) {
+        const uint64_t base = ins0b(b, outer);
+#pragma unroll
+        for (int it = 0; it < PER; ++it)
+            __builtin_amdgcn_global_load_lds((const void *)(psi + base + off[it]), (void *)(dst + NT * it + 64 * wave),
+                                             16, 0, 0);
+    };
+    uint64_t blk = blockIdx.x;
+    if (blk >= nblocks)
+        return;
+    fill(buf0, blk);
+    bool first = true;
+    int cur = 0;
+    for (;;) {
+        const uint64_t nxt = blk + gridDim.x;
+        const bool more = nxt < nblocks;  // uniform
+        C2 *sc = cur ? buf1 : buf0;
+        C2 *sn = cur ? buf0 : buf1;
+        if (more)
+            fill(sn, nxt);  // sn was read out (previous block's stores) before the barrier that ended that block
+        // this wave's loads of the current block are done once at most the loads and stores issued after them are
+        // outstanding: first block: the next fill (PER); later: the previous stores (PER) and the next fill (PER)
+        if (first || !more) {
+            if (first && !more)
+                __builtin_amdgcn_s_waitcnt(VmWait<0>::imm);
+            else
+                __builtin_amdgcn_s_waitcnt(VmWait<PER>::imm);
+        } else {
+            __builtin_amdgcn_s_waitcnt(VmWait<2 * PER>::imm);
+        }
+        lds_sync_nofence();  // every wave's part of the current block has landed in LDS
+        for (int t = 0; t < nstages; ++t) {
+            run_stage<R, B, 4, NT>(sc, stages[t], sops, mats);
+            lds_sync_nofence();
+        }
+        const uint64_t base = ins0b(blk, outer) | own;
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            const C2 v = sc[swz(threadIdx.x + NT * it)];
+            NV w;
+            w.x = v.x;
+            w.y = v.y;
+            __builtin_nontemporal_store(w, reinterpret_cast<NV *>(psi + base + hi[it]));
+        }
+        if (!more)
+            break;
+        lds_sync_nofence();  // every thread has read its stored values out of sc before sc is refilled
+        blk = nxt;
+        cur ^= 1;
+        first = false;
+    }
+}
+
 // Batched circuits, level by level. A batch runs as a short sequence of persistent launches; launch k ("level k")
 // executes pass k of every circuit that has more than k passes, all of those passes' blocks forming one flat index
 // space that the whole grid walks, so a large circuit is spread over every CU instead of one workgroup. The items of
@@ -526,6 +622,24 @@ hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const Bloc
         grid = cus;
     if (grid > nblocks)
         grid = nblocks;
+    // complex128 only: a 16-byte direct-to-LDS load is one complex128 amplitude; for complex64 it would carry two
+    // amplitudes into two adjacent slots, which the swizzle may need in the opposite order
+    if constexpr (B == 12 && W == 4 && sizeof(R) == 8) {
+        if (qs_tunables().block_async) {
+            static bool attr_async = false;
+            const size_t shm2 = 2 * shm;
+            if (!attr_async && shm2 > 65536) {
+                hipError_t e = hipFuncSetAttribute((const void *)k_block_async<R, B>,
+                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm2);
+                if (e != hipSuccess)
+                    return e;
+                attr_async = true;
+            }
+            hipLaunchKernelGGL((k_block_async<R, B>), dim3((unsigned)grid), dim3(256), shm2, s, (C2 *)psi, nblocks,
+                               outer, bm, stages, nstages, sops, (const R *)mats);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((k_block<R, B, W, NT>), dim3((unsigned)grid), dim3(NT), shm, s, (C2 *)psi, nblocks, outer, bm,
                        stages, nstages, sops, (const R *)mats);
     return hipGetLastError();

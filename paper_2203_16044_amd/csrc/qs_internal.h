@@ -196,5 +196,6 @@ struct Tunables {
     int block_wg_per_cu = 32; // persistent workgroups per CU for the LDS block kernel (in 256-thread units)
     int block_stage_width = 4; // register stage width of new block plans: 4, or 3 (512-thread kernel, b = 12, 13)
     int plan_beam = 16;        // pass formation: beam width over local-set growth (0: fewest-new-qubits greedy)
+    int block_async = 0;       // 12-qubit block passes: double-buffered LDS with direct-to-LDS loads
 };
 Tunables &qs_tunables();

@@ -112,3 +112,23 @@ def test_plan_three_position_stages(gpu, stage_width_3, bits, low, dtype, tol):
         psi0 = C.random_state(circ.n, 7)
         got, _ = _run_plan(gpu, circ, "block", bits, low, psi0, dtype)
         assert _maxerr(got, oracle.run(circ, psi0)) <= tol, circ.name
+
+
+@pytest.fixture
+def block_async():
+    from paper_2203_16044_amd import binding as B
+    B.qs_set_tunable("block_async", 1)
+    yield
+    B.qs_set_tunable("block_async", 0)
+
+
+@pytest.mark.parametrize("low", [4, 3])
+@pytest.mark.parametrize("dtype,tol", [("c128", TOL128), ("c64", 2e-5)])
+def test_plan_double_buffered_block_pass(gpu, block_async, low, dtype, tol):
+    """12-qubit block passes with double-buffered LDS filled by direct-to-LDS loads (complex128; complex64 keeps the
+    register-prefetch kernel under the same setting): same results as the oracle, on circuits whose passes span one
+    block per workgroup (15 qubits) and many (20 qubits)."""
+    for circ in (C.random_circuit(15, seed=441, num_ops=150, kmax=3), C.config2(n=20, seed=34, layers=12)):
+        psi0 = C.random_state(circ.n, 8)
+        got, _ = _run_plan(gpu, circ, "block", 12, low, psi0, dtype)
+        assert _maxerr(got, oracle.run(circ, psi0)) <= tol, circ.name
