@@ -48,7 +48,7 @@ enum {
     QS_EINVAL = -1,       /* argument out of range, null pointer, overlapping qubits */
     QS_ENOMEM = -2,       /* device or pinned-host allocation failed */
     QS_EDEVICE = -3,      /* a HIP runtime call failed (no device, launch failure, fault) */
-    QS_EUNSUPPORTED = -4  /* a valid request this build does not implement */
+    QS_EUNSUPPORTED = -4  /* a valid request the library does not implement */
 };
 
 enum { QS_C128 = 0, QS_C64 = 1 };

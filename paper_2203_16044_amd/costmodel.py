@@ -4,7 +4,7 @@ plan pass from its features; the planner scores candidate plans with it and keep
 
 Data: the simulator times every pass of candidate plans of 20-30-qubit circuits with HIP events on the state's
 stream (the target is log(pass milliseconds)). Features come from ``qs_plan_features`` (QS_PLAN_NFEAT floats).
-Usage on a GPU machine:  python -m paper_2203_16044_amd.costmodel --out <weights.npz>
+Usage (on a machine with the GPU):  python -m paper_2203_16044_amd.costmodel --out <weights.npz>
 """
 from __future__ import annotations
 

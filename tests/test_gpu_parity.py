@@ -161,7 +161,7 @@ def test_permutation_gates_bit_exact(gpu, n):
 
 FSWAP_CASES = [
     (4, 0, 2, 2), (8, 0, 4, 4), (8, 5, 1, 3), (10, 0, 7, 3), (7, 0, 1, 1),  # small / generic
-    (16, 0, 12, 4),  # configs[0]'s swap: LDS path (runs of 1 amplitude)
+    (16, 0, 12, 4),  # the 16-qubit circuit's swap: runs of 1 amplitude
     (18, 1, 12, 5), (18, 2, 9, 6), (18, 3, 11, 7), (20, 0, 14, 6),  # LDS path, various run lengths
     (18, 4, 12, 6), (18, 6, 12, 6), (20, 5, 15, 5), (19, 4, 8, 3),  # run path (>= 256-byte runs)
     (16, 12, 0, 4),  # reversed argument order
