@@ -36,12 +36,12 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (= FP64 MFMA): 256 CUs x 4 SIMDs x
 # the bytes read, WRITE_SIZE 4194304 KiB, all bytes written). Commands and figures: profiles/*_pmc_traffic.md. The readings hold for the kernel sources they were taken on: `sha1` fingerprints
 # those files and the traffic is reported as null once they differ.
 PMC_TRAFFIC = {
-    "block_b12": {"fetch_kib": 33554649.0, "write_kib": 67110845.0, "fetch_scale": 2.0, "write_scale": 1.0,
+    "block_b12": {"fetch_kib": 33554698.1, "write_kib": 67111892.6, "fetch_scale": 2.0, "write_scale": 1.0,
                   "sources": ["paper_2203_16044_amd/csrc/qs_block.hip", "paper_2203_16044_amd/csrc/qs_internal.h"],
-                  "sha1": "0093a0b419d7c5752ab4b40e957a338d60db6d62"},
-    "dense_k1": {"fetch_kib": 33554444.0, "write_kib": 67110460.0, "fetch_scale": 2.0, "write_scale": 1.0,
+                  "sha1": "f2871ca5d8ba5c15639a1ad7414784580e3add94"},
+    "dense_k1": {"fetch_kib": 33554444.3, "write_kib": 67110482.2, "fetch_scale": 2.0, "write_scale": 1.0,
                  "sources": ["paper_2203_16044_amd/csrc/qs_kernels.hip", "paper_2203_16044_amd/csrc/qs_internal.h"],
-                 "sha1": "71a8345daad8c9732bec6cd0a75d285e2c0a48ee"},
+                 "sha1": "6ce6e028e1e04f12e0b18f5fe1c0d2d873e5e0dc"},
 }
 
 
@@ -284,6 +284,8 @@ def main():
     ap.add_argument("--low-bits", type=int, default=4)
     ap.add_argument("--plain-layers", type=int, default=4, help="layers of the circuit timed on the plain path")
     ap.add_argument("--greedy", action="store_true", help="headline the greedy plan instead of the learned one")
+    ap.add_argument("--no-compare-greedy", action="store_true",
+                    help="do not also time the greedy plan (profiling runs: only the headline plan's kernels)")
     ap.add_argument("--compare-fuse", type=int, nargs="*", default=[4, 6], help="fused-dense plans also timed")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -333,9 +335,8 @@ def main():
             lp.close()
             model.close()
         head_v = learned or ("block", args.block_bits, args.low_bits)
-        variants = [head_v] + [v for v in [("block", args.block_bits, args.low_bits)] + [("fuse", k, 0) for k in
-                                                                                          args.compare_fuse]
-                               if v != head_v]
+        greedy_v = [] if args.no_compare_greedy else [("block", args.block_bits, args.low_bits)]
+        variants = [head_v] + [v for v in greedy_v + [("fuse", k, 0) for k in args.compare_fuse] if v != head_v]
         for vi, (mode, bits, low) in enumerate(variants):
             log0(f"bench: plan {mode} {bits} {low}")
             plan = Plan(cc, mode, bits, low, "c128")
@@ -410,7 +411,7 @@ def main():
                   "per_kernel": summarize(p_per, len(p_times))},
         "speedup_vs_plain": (gates / t_step) / plain_rate,
         "speedup_vs_greedy_plan": ((gates / t_step) / results[greedy_key]["gates_per_s"]
-                                   if args.mode == "tuned" else None),
+                                   if args.mode == "tuned" and greedy_key in results else None),
         "hbm_tbs_whole_step": (sum(v[2] for v in per_class.values()) / len(step_times)) / t_step / 1e12,
         "paper_nominal_tbs": (1 << (n + 5)) * gates / t_step / 1e12,
         "alternatives": {k: {kk: vv for kk, vv in v.items() if not kk.startswith("_")} for k, v in results.items()},
