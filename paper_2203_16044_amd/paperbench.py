@@ -3,8 +3,9 @@
 Workloads (generated from the paper's descriptions; see circuits): the Hadamard benchmark, eleven H gates on
 every qubit (Sec. IV-D); the QSB circuit, ten sets of an RZ.RX.RZ rotation layer and a CNOT layer (target i,
 control i+1 mod n) plus a final rotation layer (Sec. IV-F); the Quantum Volume model circuit of depth 10
-(Sec. IV-E); one RX gate on every target qubit in turn for the per-target gate time (Sec. IV-C); and the swap
-ablation of Sec. III-D (s single swaps against one fused-swap).
+(Sec. IV-E); one RX gate on every target qubit in turn for the per-target gate time (Sec. IV-C); the swap
+ablation of Sec. III-D (s single swaps against one fused-swap); and `mixed28`, the 28-qubit circuit of U3, CZ,
+RZ, Toffoli and fused-swap operations, with per-kernel-class algorithmic bandwidth on the plain path.
 
 Each circuit runs on the plain path (one HBM pass per gate, as the paper's simulator applies them) and through
 the block plan. Timing follows the paper's protocol (Sec. IV-B): six runs, the mean of the last five, each run
@@ -22,6 +23,8 @@ import argparse
 import json
 import sys
 import time
+
+import numpy as np
 
 HBM_PEAK = 8.0e12
 FP64_PEAK = 78.6e12
@@ -95,6 +98,52 @@ def run_rx_sweep(n, torch, seed=0):
             "min_tbs": min(r["effective_tbs"] for r in rows), "max_tbs": max(r["effective_tbs"] for r in rows)}
 
 
+def _op_bytes_class(op, n, S):
+    """(kernel class, algorithmic bytes) of one op on the plain path: every amplitude the op changes is read and
+    written once (a diagonal's unit entries and a controlled gate's inactive half are not touched; a fused-swap
+    leaves its 2^(n-s) fixed points alone)."""
+    full = 2 * S * (1 << n)
+    if op.kind == "dense":
+        return f"dense_k{len(op.targets)}", full
+    if op.kind == "diag":
+        d = np.asarray(op.mat).reshape(-1)
+        frac = float(np.mean(d != 1.0))
+        return f"diag_k{len(op.targets)}", int(full * frac)
+    if op.kind == "ctrl":
+        return f"ctrl_c{len(op.controls)}_k{len(op.targets)}", full >> len(op.controls)
+    return f"fswap_s{op.s}", int(full * (1 - 2.0 ** -op.s))
+
+
+def run_per_class(circ, torch):
+    """The plain path op by op with HIP events around each op: per kernel class, launches, mean ms and algorithmic
+    TB/s (and the fraction of the 8 TB/s peak)."""
+    import paper_2203_16044_amd as qs
+    n = circ.n
+    st = qs.State(n, "c128")
+    st.init_zero()
+    s = st.stream
+    per = {}
+    for rep in range(2):  # the first sweep warms up
+        for op in circ.ops:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            st.apply_op(op)
+            e1.record(s)
+            e1.synchronize()
+            if rep == 1:
+                cls, nbytes = _op_bytes_class(op, n, 16)
+                c = per.setdefault(cls, [0, 0.0, 0])
+                c[0] += 1
+                c[1] += e0.elapsed_time(e1) / 1e3
+                c[2] += nbytes
+    st.close()
+    rows = {cls: {"launches": v[0], "avg_ms": v[1] / v[0] * 1e3, "tbs": v[2] / v[1] / 1e12,
+                  "frac_of_hbm_peak": v[2] / v[1] / HBM_PEAK} for cls, v in sorted(per.items())}
+    tot_t = sum(v[1] for v in per.values())
+    return {"workload": f"{circ.name}_per_class", "n": n, "gates": len(circ.ops), "seconds": tot_t,
+            "gates_per_s": len(circ.ops) / tot_t, "per_class": rows}
+
+
 def run_swap_ablation(n, torch, p=0, s_max=6):
     """Swap insertion against fused-swap in HBM (Sec. III-D, Fig. 2): for s = 1..s_max, s single swaps
     swap(p+j, q+j) against one fused_swap(p, q, s) with q = n - s_max. Both give the same permutation; the bytes
@@ -154,13 +203,16 @@ def main(argv=None):
     res = {"n": args.n, "protocol": "6 runs, mean of the last 5, reset outside the timed region",
            "hbm_peak_tbs": HBM_PEAK / 1e12, "fp64_peak_tflops": FP64_PEAK / 1e12, "results": []}
     gen = {"hadamard": lambda: C.hadamard_x11(args.n), "qsb": lambda: C.qsb(args.n, args.seed),
-           "qv": lambda: C.quantum_volume(args.n, args.seed)}
+           "qv": lambda: C.quantum_volume(args.n, args.seed), "mixed28": lambda: C.config1()}
     for w in args.workloads:
         t0 = time.perf_counter()
         if w == "rx":
             r = run_rx_sweep(args.n, torch, args.seed)
         elif w == "swap":
             r = run_swap_ablation(args.n, torch)
+        elif w == "mixed28":
+            r = run_circuit(gen[w](), torch)
+            r["plain_per_class"] = run_per_class(gen[w](), torch)["per_class"]
         else:
             r = run_circuit(gen[w](), torch)
         r["wall_s"] = time.perf_counter() - t0

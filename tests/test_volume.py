@@ -58,3 +58,46 @@ def test_paper_metrics_definitions():
     assert m["effective_tbs"] == 2.0 ** 35 * 1290 / 2.0 / 1e12
     assert m["qbf"] == 2.0 ** 35 * 1290 / (2.0 * 78.6e12)
     assert m["frac_of_hbm_peak"] == m["effective_tbs"] / 8.0
+
+
+def test_plain_path_algorithmic_bytes_per_class():
+    """Bytes an op moves on the plain path: a CZ changes a quarter of the amplitudes, a Toffoli a quarter, an RZ
+    all of them, a fused-swap all but its 2^(n-s) fixed points."""
+    from paper_2203_16044_amd.paperbench import _op_bytes_class
+    n, S = 10, 16
+    full = 2 * S * (1 << n)
+    assert _op_bytes_class(C.Op("dense", (3,), mat=C.h()), n, S) == ("dense_k1", full)
+    assert _op_bytes_class(C.Op("diag", (2, 5), mat=C.CZ_DIAG), n, S) == ("diag_k2", full // 4)
+    assert _op_bytes_class(C.Op("diag", (4,), mat=C.rz(0.3)), n, S) == ("diag_k1", full)
+    assert _op_bytes_class(C.Op("ctrl", (1,), (2, 3), mat=np.array([[0, 1], [1, 0]])), n, S) == ("ctrl_c2_k1", full // 4)
+    assert _op_bytes_class(C.Op("fswap", p=0, q=6, s=4), n, S) == ("fswap_s4", full * 15 // 16)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_bench_traffic_is_null_once_the_kernel_sources_change(tmp_path):
+    import importlib.util
+    import shutil
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_under_test", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    for name, t in bench.PMC_TRAFFIC.items():
+        assert t["sha1"] == bench.sources_sha1(t["sources"]), name  # the readings match the committed sources
+        assert bench.pmc_traffic(name) > 2 * 16 * (1 << 32)
+    # a copy of the sources with one byte changed no longer matches
+    fake = tmp_path / "k.hip"
+    shutil.copy(os.path.join(root, bench.PMC_TRAFFIC["block_b12"]["sources"][0]), fake)
+    with open(fake, "ab") as f:
+        f.write(b" ")
+    bench.ROOT = str(tmp_path)
+    t = dict(bench.PMC_TRAFFIC["block_b12"], sources=["k.hip"])
+    bench.PMC_TRAFFIC["block_b12"] = t
+    assert bench.pmc_traffic("block_b12") is None
