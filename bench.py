@@ -180,8 +180,17 @@ def cpu_baseline(circ, budget_s, torch):
     if n_run < n:
         sample += f", gates/s scaled by 2^({n_run}-{n}) to {n} qubits"
     del psi
+    host = {}
+    try:
+        with open("/proc/cpuinfo") as f:
+            host["cpu"] = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+        import psutil
+        host["mem_gib"] = round(psutil.virtual_memory().total / 2 ** 30, 1)
+        host["nproc"] = os.cpu_count()
+    except Exception:
+        pass
     return {"value": rate, "unit": "gates/s", "cores": oracle.oracle_threads(), "kind": "oracle", "sample": sample,
-            "seconds": round(dt, 2)}
+            "seconds": round(dt, 2), "host": host}
 
 
 def bench_c64(head_rate, steps, torch):
