@@ -203,7 +203,7 @@ def bench_c64(head_rate, steps, torch):
     import paper_2203_16044_amd as qs
     from paper_2203_16044_amd.plan import Circuit, Plan, SegmentedPlan
 
-    circ = C.config3()
+    circ = C.su4_u3_renorm()
     st = qs.State(circ.n, "c64")
     sp = SegmentedPlan(circ.n, circ.ops, circ.renorm_after, "block", 12, 4, "c64")
     mk = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
@@ -228,7 +228,7 @@ def bench_c64(head_rate, steps, torch):
     torch.cuda.empty_cache()
     t = sum(times) / len(times)
     # error of the complex64 engine on the 24-qubit run, against the complex128 path
-    e = C.config3_error_run()
+    e = C.su4_u3_error_run()
     a = qs.State(e.n, "c64")
     sp = SegmentedPlan(e.n, e.ops, e.renorm_after, "block", 12, 4, "c64")
     sp.run(a)
@@ -256,7 +256,7 @@ def bench_batch(torch, log):
     import circuits as C
     from paper_2203_16044_amd import batch as BT
 
-    circs = C.config4()
+    circs = C.serving_batch()
     rec = BT.record(circs)
     out = {"workload": "512 circuits, n ~ U{10..22}, depth ~ U{10..40} (U3 / CNOT-or-CZ / RZ layers, seed 512), "
                        "FP64 probabilities of every circuit", "circuits": len(circs),
@@ -314,7 +314,7 @@ def main():
     torch.cuda.set_device(0)
     from paper_2203_16044_amd.plan import Circuit, Plan
 
-    circ = C.config2(n=args.n, seed=32, layers=args.layers)
+    circ = C.su4_u3_random(n=args.n, seed=32, layers=args.layers)
     ops = circ.ops
     n = circ.n
     gates = len(ops)

@@ -32,7 +32,7 @@ import numpy as np
 
 __all__ = [
     "Op", "Circuit", "u3", "rx", "rz", "h", "x_gate", "haar_su4", "dagger",
-    "config0", "config1", "config2", "config3", "config3_error_run", "config4",
+    "u3_cnot_layers", "mixed_layers", "su4_u3_random", "su4_u3_renorm", "su4_u3_error_run", "serving_batch",
     "hadamard_x11", "qsb", "quantum_volume", "ghz", "rx_sweep", "random_state", "random_circuit",
     "basis_state", "inverse_circuit",
 ]
@@ -170,12 +170,12 @@ def _u3_layer(rng, n, layer):
 # workload families
 # ----------------------------------------------------------------------------------------------------------
 
-def config0(n: int = 16, seed: int = 16, layers: int = 10) -> Circuit:
+def u3_cnot_layers(n: int = 16, seed: int = 16, layers: int = 10) -> Circuit:
     """Plain method, 16 qubits: per layer random U3 on every qubit, then CNOT on even neighbour pairs
     (0,1),(2,3).. on even layers and odd pairs (1,2),(3,4).. on odd layers (control = lower qubit);
     finally fused_swap(0, n-4, 4), i.e. qubits {12..15} <-> {0..3} at n=16."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    c = Circuit(n, name=f"config0_n{n}", seed=seed)
+    c = Circuit(n, name=f"u3_cnot_n{n}", seed=seed)
     for L in range(layers):
         c.ops += _u3_layer(rng, n, L + 1)
         start = 0 if L % 2 == 0 else 1
@@ -185,12 +185,12 @@ def config0(n: int = 16, seed: int = 16, layers: int = 10) -> Circuit:
     return c
 
 
-def config1(n: int = 28, seed: int = 28, layers: int = 20, toffolis: int = 32, swap_s: int = 6) -> Circuit:
+def mixed_layers(n: int = 28, seed: int = 28, layers: int = 20, toffolis: int = 32, swap_s: int = 6) -> Circuit:
     """Plain method, 28 qubits, unfused: per layer U3 on all, CZ on alternating neighbour pairs, RZ on all.
     Toffolis on ``toffolis`` random distinct triples (c1, c2, t), a quarter after layers 5/10/15/20;
     fused_swap(0, n-s, s) after layers 7/14/20."""
     rng = np.random.Generator(np.random.PCG64(seed))
-    c = Circuit(n, name=f"config1_n{n}", seed=seed)
+    c = Circuit(n, name=f"mixed_n{n}", seed=seed)
     triples = []
     seen = set()
     while len(triples) < toffolis:
@@ -224,22 +224,22 @@ def _su4_u3_layers(n: int, seed: int, layers: int, name: str) -> Circuit:
     return c
 
 
-def config2(n: int = 32, seed: int = 32, layers: int = 40) -> Circuit:
+def su4_u3_random(n: int = 32, seed: int = 32, layers: int = 40) -> Circuit:
     """32-qubit random circuit: per layer a random qubit pairing (pi = permutation, pairs (pi[2j], pi[2j+1]))
     with a Haar SU(4) on each pair, then U3 on every qubit."""
-    return _su4_u3_layers(n, seed, layers, f"config2_n{n}")
+    return _su4_u3_layers(n, seed, layers, f"su4_u3_n{n}")
 
 
-def config3(n: int = 33, seed: int = 33, layers: int = 40) -> Circuit:
-    """Same family as config2 at 33 qubits (one qubit unpaired per layer); a complex64 state is
+def su4_u3_renorm(n: int = 33, seed: int = 33, layers: int = 40) -> Circuit:
+    """Same family as su4_u3_random at 33 qubits (one qubit unpaired per layer); a complex64 state is
     renormalised after layers 10/20/30/40."""
-    c = _su4_u3_layers(n, seed, layers, f"config3_n{n}")
+    c = _su4_u3_layers(n, seed, layers, f"su4_u3_renorm_n{n}")
     c.renorm_after = tuple(L for L in range(10, layers + 1, 10))
     return c
 
 
-def config3_error_run(n: int = 24, seed: int = 24, layers: int = 40) -> Circuit:
-    return config3(n=n, seed=seed, layers=layers)
+def su4_u3_error_run(n: int = 24, seed: int = 24, layers: int = 40) -> Circuit:
+    return su4_u3_renorm(n=n, seed=seed, layers=layers)
 
 
 def _batch_circuit(rng: np.random.Generator, n: int, depth: int, idx: int) -> Circuit:
@@ -258,7 +258,7 @@ def _batch_circuit(rng: np.random.Generator, n: int, depth: int, idx: int) -> Ci
     return c
 
 
-def config4(count: int = 512, seed: int = 512, nmin: int = 10, nmax: int = 22, dmin: int = 10,
+def serving_batch(count: int = 512, seed: int = 512, nmin: int = 10, nmax: int = 22, dmin: int = 10,
             dmax: int = 40) -> List[Circuit]:
     """Batched serving form: ``count`` independent circuits, n ~ U{nmin..nmax}, depth ~ U{dmin..dmax};
     per layer U3 on all, CNOT or CZ (coin flip per layer) on alternating pairs, RZ on all.

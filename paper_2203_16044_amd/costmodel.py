@@ -59,8 +59,8 @@ def training_circuits(seed: int = 1000):
     import circuits as C
     out = []
     for n in range(20, 31):
-        out.append(C.config2(n=n, seed=seed + n, layers=3))
-        out.append(C.config1(n=n, seed=seed + 100 + n, layers=3, toffolis=8, swap_s=min(6, n // 4)))
+        out.append(C.su4_u3_random(n=n, seed=seed + n, layers=3))
+        out.append(C.mixed_layers(n=n, seed=seed + 100 + n, layers=3, toffolis=8, swap_s=min(6, n // 4)))
         out.append(C.random_circuit(n, seed=seed + 200 + n, num_ops=60, kmax=3,
                                     kinds=("dense", "diag", "ctrl")))
     return out

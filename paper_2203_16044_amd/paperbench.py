@@ -203,7 +203,7 @@ def main(argv=None):
     res = {"n": args.n, "protocol": "6 runs, mean of the last 5, reset outside the timed region",
            "hbm_peak_tbs": HBM_PEAK / 1e12, "fp64_peak_tflops": FP64_PEAK / 1e12, "results": []}
     gen = {"hadamard": lambda: C.hadamard_x11(args.n), "qsb": lambda: C.qsb(args.n, args.seed),
-           "qv": lambda: C.quantum_volume(args.n, args.seed), "mixed28": lambda: C.config1()}
+           "qv": lambda: C.quantum_volume(args.n, args.seed), "mixed28": lambda: C.mixed_layers()}
     for w in args.workloads:
         t0 = time.perf_counter()
         if w == "rx":

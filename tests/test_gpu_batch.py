@@ -20,7 +20,7 @@ def _oracle_probs(circ):
                                     {"block_bits": 10, "low_bits": 3, "wg_per_cu": 1},
                                     {"block_bits": 11, "low_bits": 4, "wg_per_cu": 4}])
 def test_batch_matches_oracle(gpu, params):
-    circs = C.config4(count=24, seed=77, nmin=10, nmax=16, dmin=4, dmax=12)
+    circs = C.serving_batch(count=24, seed=77, nmin=10, nmax=16, dmin=4, dmax=12)
     b = BT.Batch(circs, "c128", **params)
     b.run()
     for i, circ in enumerate(circs):
@@ -29,7 +29,7 @@ def test_batch_matches_oracle(gpu, params):
 
 
 def test_batch_complex64_error(gpu):
-    circs = C.config4(count=12, seed=78, nmin=10, nmax=15, dmin=4, dmax=10)
+    circs = C.serving_batch(count=12, seed=78, nmin=10, nmax=15, dmin=4, dmax=10)
     b = BT.Batch(circs, "c64")
     b.run()
     worst = 0.0
@@ -42,7 +42,7 @@ def test_batch_complex64_error(gpu):
 
 
 def test_graph_replays_match_eager(gpu):
-    circs = C.config4(count=40, seed=79, nmin=10, nmax=18, dmin=4, dmax=10)
+    circs = C.serving_batch(count=40, seed=79, nmin=10, nmax=18, dmin=4, dmax=10)
     b = BT.Batch(circs, "c128")
     b.run(graph=False)
     ref = [b.probs(i).copy() for i in range(len(circs))]
@@ -66,7 +66,7 @@ def test_graph_replays_match_eager(gpu):
 def test_full_512_circuit_batch_against_plain_loop(gpu):
     """The 512-circuit workload (10..22 qubits, 10..40 layers): every output is a distribution, and sampled circuits
     match the per-circuit plain path (itself checked against the oracle) to 1e-12."""
-    circs = C.config4()
+    circs = C.serving_batch()
     b = BT.Batch(circs, "c128")
     b.run(graph=True)
     b.sync()
@@ -82,7 +82,7 @@ def test_full_512_circuit_batch_against_plain_loop(gpu):
 
 
 def test_autotuner_picks_a_measured_candidate(gpu, tmp_path):
-    circs = C.config4(count=20, seed=80, nmin=10, nmax=16, dmin=4, dmax=8)
+    circs = C.serving_batch(count=20, seed=80, nmin=10, nmax=16, dmin=4, dmax=8)
     space = [{"block_bits": 10, "low_bits": 3, "wg_per_cu": 1}, {"block_bits": 12, "low_bits": 4, "wg_per_cu": 2}]
     best, times = BT.autotune(circs, "c128", cache=str(tmp_path / "cache.json"), space=space)
     assert best in space and len(times) == 2

@@ -117,7 +117,7 @@ def test_ghz_at_32_qubits(gpu, big_state):
 def test_random_circuit_norm_and_echo_block_plan(gpu, big_state):
     """The benchmark's 32-qubit random circuit (40 layers, block plan b=12, 4 low bits) preserves the norm, and
     running its inverse afterwards returns to |0..0>."""
-    circ = C.config2(n=N, seed=32, layers=40)
+    circ = C.su4_u3_random(n=N, seed=32, layers=40)
     st = big_state
     st.init_zero()
     c = Circuit.from_ops(N, circ.ops)
@@ -136,8 +136,8 @@ def test_random_circuit_norm_and_echo_block_plan(gpu, big_state):
         x.close()
 
 
-def test_config1_28_qubits_unfused_norm_and_echo(gpu):
-    circ = C.config1()
+def test_mixed_28_qubits_unfused_norm_and_echo(gpu):
+    circ = C.mixed_layers()
     st = gpu.State(28, "c128")
     st.run(circ.ops)
     assert abs(st.norm() - 1.0) <= 1e-12

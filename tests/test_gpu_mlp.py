@@ -97,12 +97,12 @@ def test_learned_planner_against_greedy(gpu):
     if os.path.exists(CM.WEIGHTS):
         model = CM.CostModel.load()
     else:  # train a small model here from 16-22 qubit timings
-        circs = [C.config2(n=n, seed=5 + n, layers=2) for n in (16, 18, 20, 22)]
+        circs = [C.su4_u3_random(n=n, seed=5 + n, layers=2) for n in (16, 18, 20, 22)]
         X, y = CM.collect(circs, dtypes=("c128",), log=lambda m: None)
         model = CM.CostModel()
         model.fit(X, y, epochs=150)
-    held = [(C.config2(n=25, seed=901, layers=6), "c128"), (C.config2(n=27, seed=902, layers=6), "c128"),
-            (C.config3(n=27, seed=903, layers=6), "c64")]
+    held = [(C.su4_u3_random(n=25, seed=901, layers=6), "c128"), (C.su4_u3_random(n=27, seed=902, layers=6), "c128"),
+            (C.su4_u3_renorm(n=27, seed=903, layers=6), "c64")]
     report = []
     for circ, dt in held:
         st = gpu.State(circ.n, dt)

@@ -65,7 +65,7 @@ def test_paperbench_runs_every_workload(gpu):
 
 def test_per_class_plain_run_on_a_small_mixed_circuit(gpu):
     import torch
-    circ = C.config1(n=14, layers=3, toffolis=4, swap_s=2)
+    circ = C.mixed_layers(n=14, layers=3, toffolis=4, swap_s=2)
     r = PB.run_per_class(circ, torch)
     assert sum(v["launches"] for v in r["per_class"].values()) == len(circ.ops)
     assert {"dense_k1", "diag_k1", "diag_k2"} <= set(r["per_class"])

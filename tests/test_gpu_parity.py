@@ -271,8 +271,8 @@ def test_probs_basis_and_uniform_closed_forms(gpu):
 
 # ------------------------------------------------------------------------------------------------ circuits
 
-def test_config0_all_amplitudes(gpu):
-    circ = C.config0()
+def test_u3_cnot_all_amplitudes(gpu):
+    circ = C.u3_cnot_layers()
     st = gpu.State(circ.n)
     st.run(circ.ops)
     got = st.get()
@@ -289,8 +289,8 @@ def test_random_circuits_every_kind(gpu, n):
         assert _maxerr(got, ref) <= TOL128
 
 
-def test_config1_family_at_20_qubits_all_amplitudes(gpu):
-    circ = C.config1(n=20, seed=28)
+def test_mixed_family_at_20_qubits_all_amplitudes(gpu):
+    circ = C.mixed_layers(n=20, seed=28)
     st = gpu.State(circ.n)
     st.run(circ.ops)
     got = st.get()

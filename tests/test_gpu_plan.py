@@ -46,22 +46,22 @@ def test_plan_random_circuits_every_kind(gpu, mode, bits, low, n):
 
 
 @pytest.mark.parametrize("mode,bits,low", [("block", 12, 4), ("block", 10, 3), ("fuse", 4, 0), ("fuse", 6, 0)])
-def test_plan_config0_all_amplitudes(gpu, mode, bits, low):
-    circ = C.config0()
+def test_plan_u3_cnot_all_amplitudes(gpu, mode, bits, low):
+    circ = C.u3_cnot_layers()
     got, _ = _run_plan(gpu, circ, mode, bits, low)
     assert _maxerr(got, oracle.run(circ)) <= TOL128
 
 
 @pytest.mark.parametrize("mode,bits,low", [("block", 12, 4), ("block", 13, 3), ("fuse", 5, 0), ("fuse", 6, 0)])
 def test_plan_su4_u3_family_18_qubits(gpu, mode, bits, low):
-    circ = C.config2(n=18, seed=32, layers=14)
+    circ = C.su4_u3_random(n=18, seed=32, layers=14)
     got, info = _run_plan(gpu, circ, mode, bits, low)
     assert info["passes"] < len(circ.ops) // 4
     assert _maxerr(got, oracle.run(circ)) <= TOL128
 
 
-def test_plan_config1_family_18_qubits(gpu):
-    circ = C.config1(n=18, seed=28)
+def test_plan_mixed_family_18_qubits(gpu):
+    circ = C.mixed_layers(n=18, seed=28)
     got, info = _run_plan(gpu, circ, "block", 12, 4)
     assert info["other"] == 3  # the circuit's fused-swaps
     assert _maxerr(got, oracle.run(circ)) <= TOL128
@@ -76,14 +76,14 @@ def test_plan_small_state_fallback(gpu):
 
 
 def test_plan_complex64_error_against_fp64_oracle(gpu):
-    circ = C.config3(n=18, seed=33, layers=12)
+    circ = C.su4_u3_renorm(n=18, seed=33, layers=12)
     got, _ = _run_plan(gpu, circ, "block", 12, 4, dtype="c64")
     infid, maxd = oracle.error_metrics(got, oracle.run(circ))
     assert infid <= 1e-8 and maxd <= 1e-5, (infid, maxd)
 
 
 def test_plan_rejects_mismatched_state(gpu):
-    circ = C.config0(n=12)
+    circ = C.u3_cnot_layers(n=12)
     c = Circuit.from_ops(12, circ.ops)
     p = Plan(c, "block", 10, 3, "c128")
     st = gpu.State(13)
@@ -108,7 +108,7 @@ def stage_width_3():
 @pytest.mark.parametrize("dtype,tol", [("c128", TOL128), ("c64", 2e-5)])
 def test_plan_three_position_stages(gpu, stage_width_3, bits, low, dtype, tol):
     """3-position register stages (512-thread kernel for 12- and 13-qubit blocks; other sizes keep 4 positions)."""
-    for circ in (C.random_circuit(15, seed=431, num_ops=150, kmax=3), C.config2(n=17, seed=33, layers=8)):
+    for circ in (C.random_circuit(15, seed=431, num_ops=150, kmax=3), C.su4_u3_random(n=17, seed=33, layers=8)):
         psi0 = C.random_state(circ.n, 7)
         got, _ = _run_plan(gpu, circ, "block", bits, low, psi0, dtype)
         assert _maxerr(got, oracle.run(circ, psi0)) <= tol, circ.name
@@ -128,7 +128,7 @@ def test_plan_double_buffered_block_pass(gpu, block_async, low, dtype, tol):
     """12-qubit block passes with double-buffered LDS filled by direct-to-LDS loads (complex128; complex64 keeps the
     register-prefetch kernel under the same setting): same results as the oracle, on circuits whose passes span one
     block per workgroup (15 qubits) and many (20 qubits)."""
-    for circ in (C.random_circuit(15, seed=441, num_ops=150, kmax=3), C.config2(n=20, seed=34, layers=12)):
+    for circ in (C.random_circuit(15, seed=441, num_ops=150, kmax=3), C.su4_u3_random(n=20, seed=34, layers=12)):
         psi0 = C.random_state(circ.n, 8)
         got, _ = _run_plan(gpu, circ, "block", 12, low, psi0, dtype)
         assert _maxerr(got, oracle.run(circ, psi0)) <= tol, circ.name

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 
 def test_error_run_24_qubits_against_fp64_oracle(gpu):
-    circ = C.config3_error_run()
+    circ = C.su4_u3_error_run()
     assert circ.n == 24 and circ.renorm_after == (10, 20, 30, 40)
     ref = oracle.run(circ)
     st = gpu.State(24, "c64")
@@ -49,7 +49,7 @@ def test_renormalisation_restores_the_norm(gpu):
 def test_33_qubit_complex64_run_keeps_the_norm(gpu):
     """The 33-qubit complex64 workload (64 GiB) for 10 layers through the block plan with its renormalisation:
     the FP64 norm stays 1 within FP32 rounding."""
-    circ = C.config3(layers=10)
+    circ = C.su4_u3_renorm(layers=10)
     st = gpu.State(33, "c64")
     sp = SegmentedPlan(33, circ.ops, circ.renorm_after, "block", 12, 4, "c64")
     sp.run(st)

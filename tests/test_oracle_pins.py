@@ -115,8 +115,8 @@ def test_random_circuits_all_kinds_match_brute(n):
         assert np.max(np.abs(a - b)) < 1e-12
 
 
-def test_config0_small_matches_brute():
-    circ = C.config0(n=10, seed=16, layers=4)
+def test_u3_cnot_small_matches_brute():
+    circ = C.u3_cnot_layers(n=10, seed=16, layers=4)
     assert np.max(np.abs(oracle.run(circ) - brute.run(circ))) < 1e-12
 
 
@@ -222,8 +222,8 @@ def test_echo_returns_to_zero_state():
     assert np.max(np.abs(back[1:])) < 1e-12
 
 
-def test_norm_preserved_config0():
-    psi = oracle.run(C.config0())
+def test_norm_preserved_u3_cnot():
+    psi = oracle.run(C.u3_cnot_layers())
     _, nrm = oracle.probs(psi)
     assert abs(nrm - 1.0) < 1e-12
 
@@ -328,16 +328,16 @@ def test_haar_su4_is_special_unitary():
 
 
 def test_config_shapes():
-    c0 = C.config0()
+    c0 = C.u3_cnot_layers()
     assert c0.n == 16 and c0.count(["dense"]) == 160 and c0.count(["ctrl"]) == 75 and c0.count(["fswap"]) == 1
-    c1 = C.config1()
+    c1 = C.mixed_layers()
     assert c1.count(["dense"]) == 560 and c1.count(["fswap"]) == 3 and c1.count(["ctrl"]) == 32
     assert sum(1 for o in c1.ops if o.label == "RZ") == 560 and sum(1 for o in c1.ops if o.label == "CZ") == 270
-    c2 = C.config2()
+    c2 = C.su4_u3_random()
     assert c2.n == 32 and len(c2) == 1920
-    c3 = C.config3()
+    c3 = C.su4_u3_renorm()
     assert c3.n == 33 and len(c3) == 40 * (16 + 33) and c3.renorm_after == (10, 20, 30, 40)
-    b = C.config4(count=16)
+    b = C.serving_batch(count=16)
     assert all(10 <= c.n <= 22 for c in b)
 
 

@@ -13,7 +13,7 @@ def _gates_placed(plan):
 @pytest.mark.parametrize("mode,bits,low", [("block", 8, 0), ("block", 10, 3), ("block", 12, 4), ("block", 13, 3),
                                            ("fuse", 2, 0), ("fuse", 4, 0), ("fuse", 6, 0)])
 def test_every_gate_placed_once(mode, bits, low):
-    for circ in [C.config2(n=20, layers=6), C.config1(n=14), C.config0(n=12), C.random_circuit(12, 3, num_ops=80, kmax=4)]:
+    for circ in [C.su4_u3_random(n=20, layers=6), C.mixed_layers(n=14), C.u3_cnot_layers(n=12), C.random_circuit(12, 3, num_ops=80, kmax=4)]:
         c = Circuit.from_ops(circ.n, circ.ops)
         p = Plan(c, mode, bits, low)
         assert _gates_placed(p) == len(circ.ops)
@@ -31,7 +31,7 @@ def test_every_gate_placed_once(mode, bits, low):
 
 
 def test_block_plan_cuts_passes_on_the_random_circuit():
-    circ = C.config2(n=32, layers=40)
+    circ = C.su4_u3_random(n=32, layers=40)
     c = Circuit.from_ops(circ.n, circ.ops)
     p = Plan(c, "block", 12, 4)
     info = p.info()
@@ -42,7 +42,7 @@ def test_block_plan_cuts_passes_on_the_random_circuit():
 
 
 def test_fused_swaps_stay_passes_of_their_own():
-    circ = C.config1(n=16)
+    circ = C.mixed_layers(n=16)
     c = Circuit.from_ops(circ.n, circ.ops)
     p = Plan(c, "block", 10, 3)
     swaps = [x for x in p.passes() if x["type"] == 2]
@@ -86,11 +86,11 @@ def test_batch_host_validation():
     with pytest.raises(B.QSError) as ei:
         B.qs_batch_add(b, small.h)
     assert ei.value.code == B.QS_EINVAL
-    swapping = Circuit.from_ops(16, C.config0(n=16).ops)  # holds a fused-swap
+    swapping = Circuit.from_ops(16, C.u3_cnot_layers(n=16).ops)  # holds a fused-swap
     with pytest.raises(B.QSError) as ei:
         B.qs_batch_add(b, swapping.h)
     assert ei.value.code == B.QS_EUNSUPPORTED
-    keep = [Circuit.from_ops(circ.n, circ.ops) for circ in C.config4(count=6, nmax=15)]
+    keep = [Circuit.from_ops(circ.n, circ.ops) for circ in C.serving_batch(count=6, nmax=15)]
     for c in keep:
         B.qs_batch_add(b, c.h)
     with pytest.raises(B.QSError):
@@ -98,5 +98,5 @@ def test_batch_host_validation():
     B.qs_batch_set_launch(b, 3)  # no graph captured yet: host-side only
     info = B.qs_batch_info(b)
     assert info["levels"] == 0  # not finalized
-    assert info["circuits"] == 6 and info["prob_count"] == sum(1 << c.n for c in C.config4(count=6, nmax=15))
+    assert info["circuits"] == 6 and info["prob_count"] == sum(1 << c.n for c in C.serving_batch(count=6, nmax=15))
     B.qs_batch_free(b)
