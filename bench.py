@@ -36,12 +36,12 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (= FP64 MFMA): 256 CUs x 4 SIMDs x
 # the bytes read, WRITE_SIZE 4194304 KiB, all bytes written). Commands and figures: profiles/*_pmc_traffic.md. The readings hold for the kernel sources they were taken on: `sha1` fingerprints
 # those files and the traffic is reported as null once they differ.
 PMC_TRAFFIC = {
-    "block_b12": {"fetch_kib": 33554698.1, "write_kib": 67111892.6, "fetch_scale": 2.0, "write_scale": 1.0,
+    "block_b12": {"fetch_kib": 33554697.2, "write_kib": 67111314.7, "fetch_scale": 2.0, "write_scale": 1.0,
                   "sources": ["paper_2203_16044_amd/csrc/qs_block.hip", "paper_2203_16044_amd/csrc/qs_internal.h"],
-                  "sha1": "f2871ca5d8ba5c15639a1ad7414784580e3add94"},
-    "dense_k1": {"fetch_kib": 33554444.3, "write_kib": 67110482.2, "fetch_scale": 2.0, "write_scale": 1.0,
+                  "sha1": "a0972c86fd6febd75d29fda8052c9055214aa1d0"},
+    "dense_k1": {"fetch_kib": 33554444.3, "write_kib": 67110500.4, "fetch_scale": 2.0, "write_scale": 1.0,
                  "sources": ["paper_2203_16044_amd/csrc/qs_kernels.hip", "paper_2203_16044_amd/csrc/qs_internal.h"],
-                 "sha1": "6ce6e028e1e04f12e0b18f5fe1c0d2d873e5e0dc"},
+                 "sha1": "e07f5debe5cfa45c52f6f720444ab887fd686b4a"},
 }
 
 

@@ -153,7 +153,7 @@ __device__ __forceinline__ void stage_offsets(const BlkStage &stg, uint32_t *sof
 // One stage: every thread takes groups of 2^W amplitudes (the W stage positions varying), applies the stage's ops
 // in registers and writes the group back. NT threads share the 2^(B-W) groups.
 template <class R, int B, int W, int NT>
-__device__ __forceinline__ void run_stage(typename BT<R>::C2 *s, const BlkStage &stg, const BlkStageOp *__restrict__ sops,
+__device__ __forceinline__ void run_stage(typename BT<R>::C2 *s, const BlkStage &stg,
                                           const R *__restrict__ mats)
 {
     using C2 = typename BT<R>::C2;
@@ -170,9 +170,11 @@ __device__ __forceinline__ void run_stage(typename BT<R>::C2 *s, const BlkStage 
 #pragma unroll
         for (int a = 0; a < (1 << W); ++a)
             x[a] = lds_at(s, sm ^ soff[a]);
+        uint32_t moff = stg.mat_base;
         for (int o = 0; o < stg.nops; ++o) {
-            const BlkStageOp op = sops[stg.op_begin + o];
-            reg_op_dispatch<R, W>(x, op.mask, mats + op.mat_off);
+            const int mask = (int)(stg.masks >> (4 * o)) & 15;
+            reg_op_dispatch<R, W>(x, mask, mats + moff);
+            moff += 2u << (2 * __builtin_popcount(mask));
         }
 #pragma unroll
         for (int a = 0; a < (1 << W); ++a)
@@ -183,7 +185,7 @@ __device__ __forceinline__ void run_stage(typename BT<R>::C2 *s, const BlkStage 
 // A 4-position stage for a block of 2^nb amplitudes, nb <= B chosen at run time (whole small circuits in LDS).
 template <class R>
 __device__ __forceinline__ void run_stage_n(typename BT<R>::C2 *s, const BlkStage &stg,
-                                            const BlkStageOp *__restrict__ sops, const R *__restrict__ mats, int nb)
+                                            const R *__restrict__ mats, int nb)
 {
     using C2 = typename BT<R>::C2;
     const int ng = (1 << nb) >> 4;
@@ -198,9 +200,11 @@ __device__ __forceinline__ void run_stage_n(typename BT<R>::C2 *s, const BlkStag
 #pragma unroll
         for (int a = 0; a < 16; ++a)
             x[a] = lds_at(s, sm ^ soff[a]);
+        uint32_t moff = stg.mat_base;
         for (int o = 0; o < stg.nops; ++o) {
-            const BlkStageOp op = sops[stg.op_begin + o];
-            reg_op_dispatch<R, 4>(x, op.mask, mats + op.mat_off);
+            const int mask = (int)(stg.masks >> (4 * o)) & 15;
+            reg_op_dispatch<R, 4>(x, mask, mats + moff);
+            moff += 2u << (2 * __builtin_popcount(mask));
         }
 #pragma unroll
         for (int a = 0; a < 16; ++a)
@@ -211,8 +215,7 @@ __device__ __forceinline__ void run_stage_n(typename BT<R>::C2 *s, const BlkStag
 // NT threads per workgroup: one register group per thread with 4-position stages (64 threads for 10-qubit blocks,
 // 128 for 11, 256 for 12 and 13); 512 with 3-position stages (8 register amplitudes per thread, so that two 64 KB
 // complex128 blocks per CU run 16 waves when the kernel stays within 128 VGPRs).
-template <class R, int NT> struct BlockBounds { static constexpr int waves_per_eu = 1; };
-template <class R> struct BlockBounds<R, 512> { static constexpr int waves_per_eu = 4; };
+template <class R, int NT> struct BlockBounds { static constexpr int waves_per_eu = NT == 512 ? 4 : 1; };
 // (asking the complex64 256-thread instance for 4 waves per SIMD forces <= 128 VGPRs and spills: measured 22 %
 // slower than the compiler's own choice of ~150 VGPRs and 3 waves)
 
@@ -226,19 +229,49 @@ template <int B, int W> struct BlockThreads {
 template <class R, int B, int W, int NT>
 __global__ __launch_bounds__(NT, (BlockBounds<R, NT>::waves_per_eu)) void k_block(
     typename BT<R>::C2 *__restrict__ psi, uint64_t nblocks, InsBits outer, BlockMap bm,
-    const BlkStage *__restrict__ stages, int nstages, const BlkStageOp *__restrict__ sops, const R *__restrict__ mats)
+    const BlkStage *__restrict__ stages, int nstages, const R *__restrict__ mats)
 {
     using C2 = typename BT<R>::C2;
     extern __shared__ __align__(16) unsigned char smem_blk[];
     C2 *s = reinterpret_cast<C2 *>(smem_blk);
     constexpr int N = 1 << B;
     constexpr int PER = N / NT;  // amplitudes per thread for load / store
-    // local index m = tid + NT * it: spread(tid) per thread, spread(NT * it) uniform
+    constexpr int LNT = __builtin_ctz(NT);
+    constexpr int PB = B - LNT;  // bits of the per-thread amplitude counter it
+    static_assert(NT >= 16 && PB >= 1, "block kernel shape");
+    // Local index m = tid + NT * it. Its HBM offset is spread(tid) (per thread) | spread(NT * it), the latter the OR of
+    // hb[j] over the set bits j of it; its LDS slot is (swz(tid) ^ swz(NT * it) mod 16) + NT * it, since swz only
+    // folds bits into the low 4. Both are recomputed at every use from a few registers (the empty asm statements keep
+    // the compiler from hoisting 16-32 loop-invariant addresses into registers the stages need).
     const uint64_t own = spread(threadIdx.x, bm);
-    uint64_t hi[PER];
+    uint64_t hb[PB];
 #pragma unroll
-    for (int it = 0; it < PER; ++it)
-        hi[it] = spread((uint32_t)(NT * it), bm);
+    for (int j = 0; j < PB; ++j)
+        hb[j] = (uint64_t)1 << bm.lpos[LNT + j];
+    const uint32_t sbase = slot_bytes<C2>(threadIdx.x);
+    auto hi_of = [&](const uint64_t *h, int it) {
+        uint64_t o = 0;
+#pragma unroll
+        for (int j = 0; j < PB; ++j)
+            if ((it >> j) & 1)
+                o |= h[j];
+        return o;
+    };
+    auto slot_of = [&](uint32_t sb, int it) {
+        return (sb ^ ((swz((uint32_t)(NT * it)) & 15u) * (uint32_t)sizeof(C2))) + (uint32_t)(NT * it * sizeof(C2));
+    };
+    auto opaque_h = [&](uint64_t *h) {
+#pragma unroll
+        for (int j = 0; j < PB; ++j) {
+            h[j] = hb[j];
+            asm volatile("" : "+s"(h[j]));
+        }
+    };
+    auto opaque_s = [&]() {
+        uint32_t sb = sbase;
+        asm volatile("" : "+v"(sb));
+        return sb;
+    };
     // Software pipeline over this workgroup's blocks: the next block's global loads are issued into registers before
     // the current block's stages run, so HBM traffic overlaps the FP arithmetic. The loop is rotated so that wherever
     // the prefetched registers are consumed, exactly the prefetch loads and then the previous block's stores are in
@@ -249,15 +282,21 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, NT>::waves_per_eu)) void k_bloc
     if (blk >= nblocks)
         return;
     uint64_t base = ins0b(blk, outer) | own;
+    {
+        uint64_t h[PB];
+        opaque_h(h);
+        const C2 *pb = psi + base;
 #pragma unroll
-    for (int it = 0; it < PER; ++it)
-        pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(psi + base + hi[it]));
+        for (int it = 0; it < PER; ++it)
+            pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(pb + hi_of(h, it)));
+        const uint32_t sb = opaque_s();
 #pragma unroll
-    for (int it = 0; it < PER; ++it) {
-        C2 v;
-        v.x = pre[it].x;
-        v.y = pre[it].y;
-        s[swz(threadIdx.x + NT * it)] = v;
+        for (int it = 0; it < PER; ++it) {
+            C2 v;
+            v.x = pre[it].x;
+            v.y = pre[it].y;
+            lds_at(s, slot_of(sb, it)) = v;
+        }
     }
     lds_barrier();
     for (;;) {
@@ -265,33 +304,45 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, NT>::waves_per_eu)) void k_bloc
         const bool more = nxt < nblocks;  // uniform
         const uint64_t nbase = ins0b(more ? nxt : blk, outer) | own;
         if (more) {
+            uint64_t h[PB];
+            opaque_h(h);
+            const C2 *pb = psi + nbase;
 #pragma unroll
             for (int it = 0; it < PER; ++it)
-                pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(psi + nbase + hi[it]));
+                pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(pb + hi_of(h, it)));
         }
         for (int t = 0; t < nstages; ++t) {
-            run_stage<R, B, W, NT>(s, stages[t], sops, mats);
+            run_stage<R, B, W, NT>(s, stages[t], mats);
             lds_barrier();
         }
+        {
+            uint64_t h[PB];
+            opaque_h(h);
+            C2 *pb = psi + base;
+            const uint32_t sb = opaque_s();
 #pragma unroll
-        for (int it = 0; it < PER; ++it) {
-            const C2 v = s[swz(threadIdx.x + NT * it)];
-            NV w;
-            w.x = v.x;
-            w.y = v.y;
-            __builtin_nontemporal_store(w, reinterpret_cast<NV *>(psi + base + hi[it]));
+            for (int it = 0; it < PER; ++it) {
+                const C2 v = lds_at(s, slot_of(sb, it));
+                NV w;
+                w.x = v.x;
+                w.y = v.y;
+                __builtin_nontemporal_store(w, reinterpret_cast<NV *>(pb + hi_of(h, it)));
+            }
         }
         if (nxt >= nblocks)
             break;
         blk = nxt;
         base = nbase;
         lds_barrier();  // every thread has read its stored values out of LDS
+        {
+            const uint32_t sb = opaque_s();
 #pragma unroll
-        for (int it = 0; it < PER; ++it) {
-            C2 v;
-            v.x = pre[it].x;
-            v.y = pre[it].y;
-            s[swz(threadIdx.x + NT * it)] = v;
+            for (int it = 0; it < PER; ++it) {
+                C2 v;
+                v.x = pre[it].x;
+                v.y = pre[it].y;
+                lds_at(s, slot_of(sb, it)) = v;
+            }
         }
         lds_barrier();
     }
@@ -319,8 +370,7 @@ __device__ __forceinline__ void lds_sync_nofence()
 template <class R, int B>
 __global__ __launch_bounds__(256) void k_block_async(typename BT<R>::C2 *__restrict__ psi, uint64_t nblocks,
                                                      InsBits outer, BlockMap bm, const BlkStage *__restrict__ stages,
-                                                     int nstages, const BlkStageOp *__restrict__ sops,
-                                                     const R *__restrict__ mats)
+                                                     int nstages, const R *__restrict__ mats)
 {
     using C2 = typename BT<R>::C2;
     using NV = typename NT2<R>::type;
@@ -372,7 +422,7 @@ __global__ __launch_bounds__(256) void k_block_async(typename BT<R>::C2 *__restr
         }
         lds_sync_nofence();  // every wave's part of the current block has landed in LDS
         for (int t = 0; t < nstages; ++t) {
-            run_stage<R, B, 4, NT>(sc, stages[t], sops, mats);
+            run_stage<R, B, 4, NT>(sc, stages[t], mats);
             lds_sync_nofence();
         }
         const uint64_t base = ins0b(blk, outer) | own;
@@ -419,7 +469,7 @@ __device__ __forceinline__ int find_item(const BatchItem *__restrict__ items, in
 template <class R, int B>
 __device__ __forceinline__ void batch_small(typename BT<R>::C2 *s, const BatchItem &it, double *__restrict__ prob_base,
                                             const BatchPass *__restrict__ passes, const BlkStage *__restrict__ stages,
-                                            const BlkStageOp *__restrict__ sops, const R *__restrict__ mats)
+                                            const R *__restrict__ mats)
 {
     using C2 = typename BT<R>::C2;
     const uint32_t N = 1u << it.n;
@@ -433,7 +483,7 @@ __device__ __forceinline__ void batch_small(typename BT<R>::C2 *s, const BatchIt
     for (int p = 0; p < it.npass; ++p) {
         const BatchPass &bp = passes[it.pass + p];
         for (int t = 0; t < bp.nstages; ++t) {
-            run_stage_n<R>(s, stages[bp.stage_begin + t], sops, mats, it.n);
+            run_stage_n<R>(s, stages[bp.stage_begin + t], mats, it.n);
             lds_barrier();
         }
     }
@@ -485,7 +535,7 @@ __global__ __launch_bounds__(256) void k_batch_level(typename BT<R>::C2 *__restr
                                                      const BatchItem *__restrict__ items, int nitems, uint32_t nblocks,
                                                      const BatchPass *__restrict__ passes,
                                                      const BlkStage *__restrict__ stages,
-                                                     const BlkStageOp *__restrict__ sops, const R *__restrict__ mats)
+                                                     const R *__restrict__ mats)
 {
     using C2 = typename BT<R>::C2;
     using NV = typename NT2<R>::type;
@@ -499,7 +549,7 @@ __global__ __launch_bounds__(256) void k_batch_level(typename BT<R>::C2 *__restr
         cur = items[find_item(items, nitems, g)];
         if (!(cur.flags & kBatchSmall))
             break;
-        batch_small<R, B>(s, cur, prob_base, passes, stages, sops, mats);
+        batch_small<R, B>(s, cur, prob_base, passes, stages, mats);
     }
     if (g >= nblocks)
         return;
@@ -521,7 +571,7 @@ __global__ __launch_bounds__(256) void k_batch_level(typename BT<R>::C2 *__restr
         if (more)
             batch_fetch<R, B>(pre, psi_base + nt.state_off, nbase, np->bm);
         for (int t = 0; t < bp->nstages; ++t) {
-            run_stage<R, B, 4, 256>(s, stages[bp->stage_begin + t], sops, mats);
+            run_stage<R, B, 4, 256>(s, stages[bp->stage_begin + t], mats);
             lds_barrier();
         }
         if (cur.flags & kBatchLast) {
@@ -557,7 +607,7 @@ __global__ __launch_bounds__(256) void k_batch_level(typename BT<R>::C2 *__restr
 
 template <class R, int B>
 hipError_t batch_b(void *psi, double *probs, const BatchItem *items, int nitems, uint32_t nblocks,
-                   const BatchPass *passes, const BlkStage *stages, const BlkStageOp *sops, const void *mats,
+                   const BatchPass *passes, const BlkStage *stages, const void *mats,
                    int wg_per_cu, hipStream_t s)
 {
     using C2 = typename BT<R>::C2;
@@ -579,26 +629,26 @@ hipError_t batch_b(void *psi, double *probs, const BatchItem *items, int nitems,
     if (grid == 0)
         return hipSuccess;
     hipLaunchKernelGGL((k_batch_level<R, B>), dim3((unsigned)grid), dim3(256), shm, s, (C2 *)psi, probs, items, nitems,
-                       nblocks, passes, stages, sops, (const R *)mats);
+                       nblocks, passes, stages, (const R *)mats);
     return hipGetLastError();
 }
 
 template <class R>
 hipError_t batch_r(int b, void *psi, double *probs, const BatchItem *items, int nitems, uint32_t nblocks,
-                   const BatchPass *passes, const BlkStage *stages, const BlkStageOp *sops, const void *mats,
+                   const BatchPass *passes, const BlkStage *stages, const void *mats,
                    int wg_per_cu, hipStream_t s)
 {
     switch (b) {
-    case 10: return batch_b<R, 10>(psi, probs, items, nitems, nblocks, passes, stages, sops, mats, wg_per_cu, s);
-    case 11: return batch_b<R, 11>(psi, probs, items, nitems, nblocks, passes, stages, sops, mats, wg_per_cu, s);
-    case 12: return batch_b<R, 12>(psi, probs, items, nitems, nblocks, passes, stages, sops, mats, wg_per_cu, s);
+    case 10: return batch_b<R, 10>(psi, probs, items, nitems, nblocks, passes, stages, mats, wg_per_cu, s);
+    case 11: return batch_b<R, 11>(psi, probs, items, nitems, nblocks, passes, stages, mats, wg_per_cu, s);
+    case 12: return batch_b<R, 12>(psi, probs, items, nitems, nblocks, passes, stages, mats, wg_per_cu, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <class R, int B, int W>
 hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm, const BlkStage *stages,
-                   int nstages, const BlkStageOp *sops, const void *mats, hipStream_t s)
+                   int nstages, const void *mats, hipStream_t s)
 {
     using C2 = typename BT<R>::C2;
     constexpr int NT = BlockThreads<B, W>::value;
@@ -636,35 +686,35 @@ hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const Bloc
                 attr_async = true;
             }
             hipLaunchKernelGGL((k_block_async<R, B>), dim3((unsigned)grid), dim3(256), shm2, s, (C2 *)psi, nblocks,
-                               outer, bm, stages, nstages, sops, (const R *)mats);
+                               outer, bm, stages, nstages, (const R *)mats);
             return hipGetLastError();
         }
     }
     hipLaunchKernelGGL((k_block<R, B, W, NT>), dim3((unsigned)grid), dim3(NT), shm, s, (C2 *)psi, nblocks, outer, bm,
-                       stages, nstages, sops, (const R *)mats);
+                       stages, nstages, (const R *)mats);
     return hipGetLastError();
 }
 
 template <class R>
 hipError_t block_r(int b, int w, void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm,
-                   const BlkStage *stages, int nstages, const BlkStageOp *sops, const void *mats, hipStream_t s)
+                   const BlkStage *stages, int nstages, const void *mats, hipStream_t s)
 {
     if (w == 3) {
         switch (b) {
-        case 12: return block_b<R, 12, 3>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
-        case 13: return block_b<R, 13, 3>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
+        case 12: return block_b<R, 12, 3>(psi, nblocks, outer, bm, stages, nstages, mats, s);
+        case 13: return block_b<R, 13, 3>(psi, nblocks, outer, bm, stages, nstages, mats, s);
         default: return hipErrorInvalidValue;
         }
     }
     if (w != 4)
         return hipErrorInvalidValue;
     switch (b) {
-    case 8: return block_b<R, 8, 4>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
-    case 9: return block_b<R, 9, 4>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
-    case 10: return block_b<R, 10, 4>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
-    case 11: return block_b<R, 11, 4>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
-    case 12: return block_b<R, 12, 4>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
-    case 13: return block_b<R, 13, 4>(psi, nblocks, outer, bm, stages, nstages, sops, mats, s);
+    case 8: return block_b<R, 8, 4>(psi, nblocks, outer, bm, stages, nstages, mats, s);
+    case 9: return block_b<R, 9, 4>(psi, nblocks, outer, bm, stages, nstages, mats, s);
+    case 10: return block_b<R, 10, 4>(psi, nblocks, outer, bm, stages, nstages, mats, s);
+    case 11: return block_b<R, 11, 4>(psi, nblocks, outer, bm, stages, nstages, mats, s);
+    case 12: return block_b<R, 12, 4>(psi, nblocks, outer, bm, stages, nstages, mats, s);
+    case 13: return block_b<R, 13, 4>(psi, nblocks, outer, bm, stages, nstages, mats, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -672,20 +722,20 @@ hipError_t block_r(int b, int w, void *psi, uint64_t nblocks, const InsBits &out
 }  // namespace
 
 hipError_t launch_batch_level(int dtype, int b, void *psi, double *probs, const BatchItem *items, int nitems,
-                              uint32_t nblocks, const BatchPass *passes, const BlkStage *stages, const BlkStageOp *sops,
+                              uint32_t nblocks, const BatchPass *passes, const BlkStage *stages,
                               const void *mats, int wg_per_cu, hipStream_t s)
 {
-    return dtype == QS_C128 ? batch_r<double>(b, psi, probs, items, nitems, nblocks, passes, stages, sops, mats,
+    return dtype == QS_C128 ? batch_r<double>(b, psi, probs, items, nitems, nblocks, passes, stages, mats,
                                               wg_per_cu, s)
-                            : batch_r<float>(b, psi, probs, items, nitems, nblocks, passes, stages, sops, mats,
+                            : batch_r<float>(b, psi, probs, items, nitems, nblocks, passes, stages, mats,
                                              wg_per_cu, s);
 }
 
 hipError_t launch_block(int dtype, int b, int w, void *psi, uint64_t nblocks, const InsBits &outer,
-                        const BlockMap &bm, const BlkStage *stages_dev, int nstages, const BlkStageOp *sops_dev,
+                        const BlockMap &bm, const BlkStage *stages_dev, int nstages, 
                         const void *mats_dev, hipStream_t s)
 {
     return dtype == QS_C128
-               ? block_r<double>(b, w, psi, nblocks, outer, bm, stages_dev, nstages, sops_dev, mats_dev, s)
-               : block_r<float>(b, w, psi, nblocks, outer, bm, stages_dev, nstages, sops_dev, mats_dev, s);
+               ? block_r<double>(b, w, psi, nblocks, outer, bm, stages_dev, nstages, mats_dev, s)
+               : block_r<float>(b, w, psi, nblocks, outer, bm, stages_dev, nstages, mats_dev, s);
 }

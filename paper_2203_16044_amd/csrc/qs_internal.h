@@ -117,29 +117,35 @@ int probs_blocks(uint64_t dim);
 hipError_t launch_scale(int dtype, void *psi, uint64_t dim, double f, hipStream_t s);
 hipError_t launch_scale_dev(int dtype, void *psi, uint64_t dim, const double *norm_dev, hipStream_t s);
 
-// LDS block passes: local qubit set L (ascending global positions), op table in device memory
+// LDS block passes: local qubit set L (ascending global positions), stage table in device memory
 constexpr int kMaxBlockBits = 13;
 constexpr int kMaxBlockOpK = 3;
+constexpr int kStageMaxOps = 8;  // ops per stage (their masks share one 32-bit word)
 struct BlockMap {
     int b;
     int lpos[kMaxBlockBits];  // global bit of local bit t (ascending)
 };
 struct BlkStage {
     int pos[4];    // local positions held in registers during the stage (the first W, ascending; W = 3 or 4)
-    int op_begin;  // first op of the stage in the op table
-    int nops;
+    int op_begin;  // first op of the stage in the host op table
+    int nops;      // <= kStageMaxOps
+    // op o acts on the stage positions in bits 4o..4o+3 of masks (bit j <-> pos[j]; 1..3 bits set); its 2^k x 2^k
+    // matrix starts at mat_base + the sizes of ops 0..o-1 (2 * 4^k real elements each) in the matrix pool, so a
+    // kernel finds every op of the stage without a dependent load
+    uint32_t masks;
+    uint32_t mat_base;
     // the other local positions in the order the bits of a thread's group counter fill them: the first four cover
     // the four residue classes (mod 4) of the LDS swizzle so that 16 consecutive lanes hit 16 distinct bank groups
     int order[kMaxBlockBits - 3];
 };
-struct BlkStageOp {
+struct BlkStageOp {  // host-side op table (planner statistics and batch relocation)
     int mask;          // stage positions the op acts on (bit j of the mask <-> pos[j], j < W); 1..3 bits set
     uint32_t mat_off;  // offset of its 2^k x 2^k matrix (bit order of the mask's positions) in real elements
 };
 // w = register stage width: 4 (256 threads, any b in 8..13) or 3 (512 threads, b = 12, 13)
 hipError_t launch_block(int dtype, int b, int w, void *psi, uint64_t nblocks, const InsBits &outer,
-                        const BlockMap &bm, const BlkStage *stages_dev, int nstages, const BlkStageOp *sops_dev,
-                        const void *mats_dev, hipStream_t s);
+                        const BlockMap &bm, const BlkStage *stages_dev, int nstages, const void *mats_dev,
+                        hipStream_t s);
 
 // batched circuits: one persistent launch per pass level (see qs_block.hip)
 struct BatchCirc {
@@ -167,8 +173,8 @@ struct BatchItem {
     int flags;
 };
 hipError_t launch_batch_level(int dtype, int b, void *psi, double *probs, const BatchItem *items, int nitems,
-                              uint32_t nblocks, const BatchPass *passes, const BlkStage *stages, const BlkStageOp *sops,
-                              const void *mats, int wg_per_cu, hipStream_t s);
+                              uint32_t nblocks, const BatchPass *passes, const BlkStage *stages, const void *mats,
+                              int wg_per_cu, hipStream_t s);
 
 hipError_t launch_probe_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 hipError_t launch_probe_rmw(void *buf, size_t bytes, hipStream_t s);

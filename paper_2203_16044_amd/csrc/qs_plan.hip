@@ -139,7 +139,6 @@ struct qs_plan {
     std::vector<double> pool;  // matrices, FP64 (rounded to FP32 on upload for complex64)
     std::vector<RawOp> raw;    // copy: the plan stays valid after the circuit is freed
     BlkStage *dstages = nullptr;
-    BlkStageOp *dsops = nullptr;
     void *dpool = nullptr;
     int dev = -1;
     int nfused_ops = 0;
@@ -422,9 +421,6 @@ int upload(qs_plan *P)
     QS_HIP(hipMalloc((void **)&P->dstages, std::max<size_t>(P->stages.size(), 1) * sizeof(BlkStage)));
     if (!P->stages.empty())
         QS_HIP(hipMemcpy(P->dstages, P->stages.data(), P->stages.size() * sizeof(BlkStage), hipMemcpyHostToDevice));
-    QS_HIP(hipMalloc((void **)&P->dsops, std::max<size_t>(P->sops.size(), 1) * sizeof(BlkStageOp)));
-    if (!P->sops.empty())
-        QS_HIP(hipMemcpy(P->dsops, P->sops.data(), P->sops.size() * sizeof(BlkStageOp), hipMemcpyHostToDevice));
     const size_t npool = std::max<size_t>(P->pool.size(), 2);
     if (P->dtype == QS_C128) {
         QS_HIP(hipMalloc(&P->dpool, npool * sizeof(double)));
@@ -734,7 +730,7 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
         while (left) {
             uint32_t S = 0;
             std::vector<int> members;
-            for (;;) {
+            while ((int)members.size() < kStageMaxOps) {
                 int best = -1, bestnew = 99;
                 for (int i = 0; i < nf; ++i) {
                     if (placed[i])
@@ -785,7 +781,9 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
             }
             stg.op_begin = (int)P->sops.size();
             stg.nops = (int)members.size();
-            for (int i : members) {
+            stg.mat_base = (uint32_t)P->pool.size();
+            for (size_t o = 0; o < members.size(); ++o) {
+                const int i = members[o];
                 BlkStageOp so{};
                 for (int t = 0; t < W; ++t)
                     if ((posmask[i] >> stg.pos[t]) & 1)
@@ -793,6 +791,7 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
                 so.mat_off = (uint32_t)P->pool.size();
                 push_matrix(P->pool, sorted_ops[i].m);
                 P->sops.push_back(so);
+                stg.masks |= (uint32_t)so.mask << (4 * o);
             }
             P->stages.push_back(stg);
         }
@@ -827,7 +826,7 @@ QS_API int qs_plan_run_range(qs_state *st, qs_plan *P, int begin, int end)
         case 0: {
             const InsBits outer = qs_make_ins(pp.lmask, 0);
             QS_HIP(launch_block(st->dtype, pp.b, pp.sw, st->psi, (uint64_t)1 << (P->n - pp.b), outer, pp.bm,
-                                P->dstages + pp.stage_begin, pp.nstages, P->dsops, P->dpool, st->stream));
+                                P->dstages + pp.stage_begin, pp.nstages, P->dpool, st->stream));
             break;
         }
         case 1: {
@@ -974,8 +973,6 @@ QS_API int qs_plan_free(qs_plan *P)
         return qs_fail(QS_EINVAL, "qs_plan_free: NULL plan");
     if (P->dstages)
         (void)hipFree(P->dstages);
-    if (P->dsops)
-        (void)hipFree(P->dsops);
     if (P->dpool)
         (void)hipFree(P->dpool);
     delete P;
@@ -1006,7 +1003,6 @@ struct qs_batch {
     BatchItem *ditems = nullptr;
     BatchPass *dpasses = nullptr;
     BlkStage *dstages = nullptr;
-    BlkStageOp *dsops = nullptr;
     void *dmats = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1022,7 +1018,7 @@ void batch_release(qs_batch *Bt)
         (void)hipGraphExecDestroy(Bt->exec);
     if (Bt->graph)
         (void)hipGraphDestroy(Bt->graph);
-    void *bufs[] = {Bt->psi, Bt->probs, Bt->ditems, Bt->dpasses, Bt->dstages, Bt->dsops, Bt->dmats};
+    void *bufs[] = {Bt->psi, Bt->probs, Bt->ditems, Bt->dpasses, Bt->dstages, Bt->dmats};
     for (void *p : bufs)
         if (p)
             (void)hipFree(p);
@@ -1141,6 +1137,7 @@ QS_API int qs_batch_add(qs_batch *Bt, const qs_circuit *c)
     }
     for (BlkStage st : P->stages) {
         st.op_begin += o0;
+        st.mat_base += m0;
         Bt->stages.push_back(st);
     }
     for (BlkStageOp so : P->sops) {
@@ -1219,8 +1216,6 @@ QS_API int qs_batch_finalize(qs_batch *Bt)
         return rc;
     if (int rc = upload_vec(&Bt->dstages, Bt->stages))
         return rc;
-    if (int rc = upload_vec(&Bt->dsops, Bt->sops))
-        return rc;
     if (Bt->dtype == QS_C128) {
         double *d = nullptr;
         if (int rc = upload_vec(&d, Bt->pool))
@@ -1249,7 +1244,7 @@ QS_API int qs_batch_run(qs_batch *Bt, int use_graph)
         for (size_t lev = 0; lev + 1 < Bt->level_begin.size(); ++lev) {
             const int i0 = Bt->level_begin[lev], i1 = Bt->level_begin[lev + 1];
             hipError_t e = launch_batch_level(Bt->dtype, Bt->b, Bt->psi, Bt->probs, Bt->ditems + i0, i1 - i0,
-                                              Bt->level_blocks[lev], Bt->dpasses, Bt->dstages, Bt->dsops, Bt->dmats,
+                                              Bt->level_blocks[lev], Bt->dpasses, Bt->dstages, Bt->dmats,
                                               Bt->wg_per_cu, Bt->stream);
             if (e != hipSuccess)
                 return e;
