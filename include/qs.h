@@ -287,6 +287,8 @@ QS_API int qs_probe_rmw(void *buf, size_t bytes, void *hip_stream);
  *               scaled up proportionally);
  * "block_stage_width" register stage width of block plans created afterwards: 4 (256-thread kernel, default) or
  *                     3 (512-thread kernel with 8 register amplitudes per thread, for 12- and 13-qubit blocks);
+ * "block_async" 0/1: 12-qubit complex128 block passes double-buffer the next block in LDS with direct-to-LDS loads
+ *               (default 0: one workgroup per CU fits, measured slower than two with register prefetch);
  * "plan_beam"   beam width of pass formation for plans created afterwards (0..64, default 16): the local set of a
  *               pass grows one ready gate at a time, keeping the candidates that take the most gates; 0 selects
  *               the fewest-new-qubits greedy. Batches always plan with 4-position stages.

@@ -10,9 +10,9 @@
 //
 // Inside the block the pass's ops are grouped into stages of at most 4 local qubits. In a stage every thread holds
 // the 16 amplitudes of a group (the stage's 4 positions varying) in registers, applies all of the stage's ops there
-// and writes the group back: one LDS round trip and one barrier per stage instead of per op. The stage list (4
-// ascending local positions each) and the op list (a 4-bit mask of the stage positions it acts on, k <= 3, and the
-// offset of its 2^k x 2^k matrix in the compute precision) live in device memory.
+// and writes the group back: one LDS round trip and one barrier per stage instead of per op. The stage records live
+// in device memory: 4 ascending local positions, up to 8 ops as 4-bit masks of the stage positions they act on
+// (k <= 3), and the pool offset of the first op's 2^k x 2^k matrix (compute precision; the others follow in order).
 #include "qs_internal.h"
 
 namespace {
