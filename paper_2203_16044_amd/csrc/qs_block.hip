@@ -496,6 +496,40 @@ __device__ __forceinline__ void batch_small(typename BT<R>::C2 *s, const BatchIt
     lds_barrier();
 }
 
+// HBM offset of local index tid + 256 k of a batch block: spread(tid) | OR of h[j] over the set bits j of k, where
+// h[j] = 1 << lpos[8 + j] (the block's map changes from block to block, so the four basis offsets are rebuilt per
+// block and the sixteen offsets recomputed at every use, as in k_block).
+template <int PB>
+__device__ __forceinline__ void batch_basis(uint64_t *h, const BlockMap &bm)
+{
+#pragma unroll
+    for (int j = 0; j < PB; ++j) {
+        h[j] = (uint64_t)1 << bm.lpos[8 + j];
+        asm volatile("" : "+s"(h[j]));
+    }
+}
+template <int PB>
+__device__ __forceinline__ uint64_t batch_hi(const uint64_t *h, int k)
+{
+    uint64_t o = 0;
+#pragma unroll
+    for (int j = 0; j < PB; ++j)
+        if ((k >> j) & 1)
+            o |= h[j];
+    return o;
+}
+// LDS slot (bytes) of local index tid + 256 k from sb = slot_bytes(tid): swz only folds bits into the low 4
+template <class C2>
+__device__ __forceinline__ uint32_t batch_slot(uint32_t sb, int k)
+{
+    return (sb ^ ((swz((uint32_t)(256 * k)) & 15u) * (uint32_t)sizeof(C2))) + (uint32_t)(256 * k * sizeof(C2));
+}
+__device__ __forceinline__ uint32_t opaque_u32(uint32_t v)
+{
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
 // Loads of one block into registers. The loads are issued even for a FIRST pass (whose values are then replaced by
 // the basis state) so that the wait before their use is the same on every path and can leave stores in flight.
 template <class R, int B>
@@ -504,28 +538,36 @@ __device__ __forceinline__ void batch_fetch(typename NT2<R>::type *pre, const ty
 {
     using NV = typename NT2<R>::type;
     constexpr int PER = (1 << B) / 256;
+    constexpr int PB = B - 8;
+    uint64_t h[PB];
+    batch_basis<PB>(h, bm);
+    const typename BT<R>::C2 *pb = psi + base;
 #pragma unroll
     for (int it = 0; it < PER; ++it)
-        pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(psi + base + spread((uint32_t)(256 * it), bm)));
+        pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(pb + batch_hi<PB>(h, it)));
 }
 
 template <class R, int B>
 __device__ __forceinline__ void batch_to_lds(typename BT<R>::C2 *s, const typename NT2<R>::type *pre, uint64_t base,
-                                             const BlockMap &bm, bool first)
+                                             const BlockMap &bm, bool first, uint32_t sbase)
 {
     using C2 = typename BT<R>::C2;
     constexpr int PER = (1 << B) / 256;
+    constexpr int PB = B - 8;
+    uint64_t h[PB];
+    batch_basis<PB>(h, bm);
+    const uint32_t sb = opaque_u32(sbase);
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
         C2 v;
         if (first) {
-            v.x = (base + spread((uint32_t)(256 * k), bm)) == 0 ? (R)1 : (R)0;
+            v.x = (base | batch_hi<PB>(h, k)) == 0 ? (R)1 : (R)0;
             v.y = 0;
         } else {
             v.x = pre[k].x;
             v.y = pre[k].y;
         }
-        s[swz(threadIdx.x + 256 * k)] = v;
+        lds_at(s, batch_slot<C2>(sb, k)) = v;
     }
 }
 
@@ -542,6 +584,7 @@ __global__ __launch_bounds__(256) void k_batch_level(typename BT<R>::C2 *__restr
     extern __shared__ __align__(16) unsigned char smem_blk[];
     C2 *s = reinterpret_cast<C2 *>(smem_blk);
     constexpr int PER = (1 << B) / 256;
+    constexpr int PB = B - 8;
     // small items come first in the flat order: a workgroup runs its small circuits, then its HBM blocks
     uint32_t g = blockIdx.x;
     BatchItem cur{};
@@ -555,11 +598,12 @@ __global__ __launch_bounds__(256) void k_batch_level(typename BT<R>::C2 *__restr
         return;
     // HBM blocks: the rotated pipeline of k_block (prefetch of the next block before the stages; waits only on the
     // prefetch loads, the previous block's stores keep draining).
+    const uint32_t sbase = slot_bytes<C2>(threadIdx.x);
     NV pre[PER];
     const BatchPass *bp = &passes[cur.pass];
     uint64_t base = ins0b(g - cur.blk_begin, bp->outer) | spread(threadIdx.x, bp->bm);
     batch_fetch<R, B>(pre, psi_base + cur.state_off, base, bp->bm);
-    batch_to_lds<R, B>(s, pre, base, bp->bm, (cur.flags & kBatchFirst) != 0);
+    batch_to_lds<R, B>(s, pre, base, bp->bm, (cur.flags & kBatchFirst) != 0, sbase);
     lds_barrier();
     for (;;) {
         const uint32_t nx = g + gridDim.x;
@@ -574,23 +618,28 @@ __global__ __launch_bounds__(256) void k_batch_level(typename BT<R>::C2 *__restr
             run_stage<R, B, 4, 256>(s, stages[bp->stage_begin + t], mats);
             lds_barrier();
         }
-        if (cur.flags & kBatchLast) {
-            double *out = prob_base + cur.prob_off;
+        {
+            uint64_t h[PB];
+            batch_basis<PB>(h, bp->bm);
+            const uint32_t sb = opaque_u32(sbase);
+            if (cur.flags & kBatchLast) {
+                double *out = prob_base + cur.prob_off + base;
 #pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const C2 v = s[swz(threadIdx.x + 256 * k)];
-                const double re = (double)v.x, im = (double)v.y;
-                out[base + spread((uint32_t)(256 * k), bp->bm)] = re * re + im * im;
-            }
-        } else {
-            C2 *psi = psi_base + cur.state_off;
+                for (int k = 0; k < PER; ++k) {
+                    const C2 v = lds_at(s, batch_slot<C2>(sb, k));
+                    const double re = (double)v.x, im = (double)v.y;
+                    out[batch_hi<PB>(h, k)] = re * re + im * im;
+                }
+            } else {
+                C2 *psi = psi_base + cur.state_off + base;
 #pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const C2 v = s[swz(threadIdx.x + 256 * k)];
-                NV w;
-                w.x = v.x;
-                w.y = v.y;
-                __builtin_nontemporal_store(w, reinterpret_cast<NV *>(psi + base + spread((uint32_t)(256 * k), bp->bm)));
+                for (int k = 0; k < PER; ++k) {
+                    const C2 v = lds_at(s, batch_slot<C2>(sb, k));
+                    NV w;
+                    w.x = v.x;
+                    w.y = v.y;
+                    __builtin_nontemporal_store(w, reinterpret_cast<NV *>(psi + batch_hi<PB>(h, k)));
+                }
             }
         }
         if (nx >= nblocks)
@@ -600,7 +649,7 @@ __global__ __launch_bounds__(256) void k_batch_level(typename BT<R>::C2 *__restr
         bp = np;
         base = nbase;
         lds_barrier();  // every thread has read its stored values out of LDS
-        batch_to_lds<R, B>(s, pre, base, bp->bm, (cur.flags & kBatchFirst) != 0);
+        batch_to_lds<R, B>(s, pre, base, bp->bm, (cur.flags & kBatchFirst) != 0, sbase);
         lds_barrier();
     }
 }
