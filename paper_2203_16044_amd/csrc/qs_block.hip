@@ -215,9 +215,12 @@ __device__ __forceinline__ void run_stage_n(typename BT<R>::C2 *s, const BlkStag
 // NT threads per workgroup: one register group per thread with 4-position stages (64 threads for 10-qubit blocks,
 // 128 for 11, 256 for 12 and 13); 512 with 3-position stages (8 register amplitudes per thread, so that two 64 KB
 // complex128 blocks per CU run 16 waves when the kernel stays within 128 VGPRs).
-template <class R, int NT> struct BlockBounds { static constexpr int waves_per_eu = NT == 512 ? 4 : 1; };
-// (asking the complex64 256-thread instance for 4 waves per SIMD forces <= 128 VGPRs and spills: measured 22 %
-// slower than the compiler's own choice of ~150 VGPRs and 3 waves)
+template <class R, int B, int NT> struct BlockBounds {
+    static constexpr int waves_per_eu = NT == 512 || (sizeof(R) == 4 && NT >= 128 && B <= 12) ? 4 : 1;
+};
+// Complex64 blocks of 11-12 qubits (16-32 KB of LDS) are held to 128 VGPRs for 4 waves per SIMD: 2-4 % faster
+// at 33 qubits than the 3 waves of the unconstrained ~130-VGPR build (the bound costs three 64-bit scratch reloads
+// per block, outside the stage loop); 13-qubit complex64 blocks would spill far more and keep the compiler's choice.
 
 // Threads of a block workgroup: one 2^W-amplitude group per thread (at least one wave; 4-position stages of
 // 13-qubit blocks take two groups per thread).
@@ -227,7 +230,7 @@ template <int B, int W> struct BlockThreads {
 };
 
 template <class R, int B, int W, int NT>
-__global__ __launch_bounds__(NT, (BlockBounds<R, NT>::waves_per_eu)) void k_block(
+__global__ __launch_bounds__(NT, (BlockBounds<R, B, NT>::waves_per_eu)) void k_block(
     typename BT<R>::C2 *__restrict__ psi, uint64_t nblocks, InsBits outer, BlockMap bm,
     const BlkStage *__restrict__ stages, int nstages, const R *__restrict__ mats)
 {
