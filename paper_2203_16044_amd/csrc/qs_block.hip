@@ -575,7 +575,7 @@ __device__ __forceinline__ void batch_to_lds(typename BT<R>::C2 *s, const typena
 }
 
 template <class R, int B>
-__global__ __launch_bounds__(256) void k_batch_level(typename BT<R>::C2 *__restrict__ psi_base,
+__global__ __launch_bounds__(256, (sizeof(R) == 4 ? 4 : 1)) void k_batch_level(typename BT<R>::C2 *__restrict__ psi_base,
                                                      double *__restrict__ prob_base,
                                                      const BatchItem *__restrict__ items, int nitems, uint32_t nblocks,
                                                      const BatchPass *__restrict__ passes,
