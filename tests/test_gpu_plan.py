@@ -132,3 +132,19 @@ def test_plan_double_buffered_block_pass(gpu, block_async, low, dtype, tol):
         psi0 = C.random_state(circ.n, 8)
         got, _ = _run_plan(gpu, circ, "block", 12, low, psi0, dtype)
         assert _maxerr(got, oracle.run(circ, psi0)) <= tol, circ.name
+
+
+@pytest.mark.parametrize("bits,low", [(10, 4), (12, 3), (12, 4)])
+def test_plan_long_runs_of_ops_on_four_qubits(gpu, bits, low):
+    """40 two-qubit gates that cycle through the pairs of qubits 0-3 (no gate's qubits are a subset of its
+    neighbour's, so none merge) all fall into stages over the same 4 local positions; a stage record holds at most
+    8 ops, so the planner splits the run into several stages over those positions."""
+    rng = np.random.Generator(np.random.PCG64(71))
+    pairs = [(0, 1), (1, 2), (2, 3), (0, 3), (0, 2), (1, 3)]
+    ops = [C.Op("dense", pairs[i % len(pairs)], mat=C.haar_su4(rng)) for i in range(40)]
+    ops += [C.Op("dense", (5, 9), mat=C.haar_su4(rng)), C.Op("dense", (0, 11), mat=C.haar_su4(rng))]
+    circ = C.Circuit(14, ops=ops, name="four_qubit_run")
+    psi0 = C.random_state(14, 77)
+    got, info = _run_plan(gpu, circ, "block", bits, low, psi0)
+    assert info["fused_ops"] >= 40
+    assert _maxerr(got, oracle.run(circ, psi0)) <= TOL128
