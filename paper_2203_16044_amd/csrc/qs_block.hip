@@ -182,6 +182,68 @@ __device__ __forceinline__ void run_stage(typename BT<R>::C2 *s, const BlkStage 
     }
 }
 
+// A complex64 4-position stage as one dense product Y = M X on the matrix cores: M is the stage's fused 16 x 16
+// complex matrix (its ops multiplied on the host; stage index bit j <-> pos[j]), X the 16 x 2^(B-4) matrix whose
+// columns are the register groups. As in the dense MFMA kernel the product runs on real 16x16x4 FP32 tiles with
+// interleaved (re, im) rows: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16], and register r of lane l
+// holds D[4 (l / 16) + r][l % 16]; tile row i of A' is output member 8 rt + i / 2, component i % 2, so every lane's
+// accumulators are two complete outputs. Each wave owns whole 16-group column tiles, so a tile is read and
+// rewritten in place by one wave. slot_bytes is linear in XOR, so a member's LDS offset is the XOR of the offsets
+// of its bits: no register array is indexed by a lane-dependent value.
+template <int B, int NT>
+__device__ __forceinline__ void run_stage_mfma(float2 *s, const BlkStage &stg, const float2 *Ml)
+{
+    typedef float acc_t __attribute__((ext_vector_type(4)));
+    constexpr int NG = 1 << (B - 4);
+    constexpr int NW = NT / 64;
+    static_assert(NG % 16 == 0 && NT % 64 == 0, "MFMA stage shape");
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int j = lane & 15, kq = lane >> 4;
+    uint32_t soff[16];
+    stage_offsets<float2, 4>(stg, soff);
+    const uint32_t in_q = ((kq & 1) ? soff[1] : 0u) ^ ((kq & 2) ? soff[2] : 0u);   // members 4 t + kq
+    const uint32_t out_q = ((kq & 1) ? soff[2] : 0u) ^ ((kq & 2) ? soff[4] : 0u);  // members 8 rt + 2 kq (+1)
+    float afr[2][4][2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        const int ao = 8 * rt + (j >> 1), co = j & 1;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const float2 u = Ml[ao * 16 + 4 * t + kq];
+            afr[rt][t][0] = co == 0 ? u.x : u.y;   // multiplies Re x
+            afr[rt][t][1] = co == 0 ? -u.y : u.x;  // multiplies Im x
+        }
+    }
+    for (int ct = wv; ct < NG / 16; ct += NW) {
+        const uint32_t g = (uint32_t)(ct * 16 + j);
+        uint32_t m = 0;
+#pragma unroll
+        for (int b = 0; b < B - 4; ++b)
+            m |= ((g >> b) & 1u) << stg.order[b];
+        const uint32_t sm = slot_bytes<float2>(m);
+        acc_t acc[2][2];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+            acc[rt][0] = acc[rt][1] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const float2 bv = lds_at(s, sm ^ soff[4 * t] ^ in_q);
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) {
+                acc[rt][t & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[rt][t][0], bv.x, acc[rt][t & 1], 0, 0, 0);
+                acc[rt][t & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[rt][t][1], bv.y, acc[rt][t & 1], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            const acc_t y = acc[rt][0] + acc[rt][1];
+            const uint32_t o0 = sm ^ soff[8 * rt] ^ out_q;
+            lds_at(s, o0) = make_float2(y[0], y[1]);
+            lds_at(s, o0 ^ soff[1]) = make_float2(y[2], y[3]);
+        }
+    }
+}
+
 // A 4-position stage for a block of 2^nb amplitudes, nb <= B chosen at run time (whole small circuits in LDS).
 template <class R>
 __device__ __forceinline__ void run_stage_n(typename BT<R>::C2 *s, const BlkStage &stg,
@@ -232,12 +294,20 @@ template <int B, int W> struct BlockThreads {
 template <class R, int B, int W, int NT>
 __global__ __launch_bounds__(NT, (BlockBounds<R, B, NT>::waves_per_eu)) void k_block(
     typename BT<R>::C2 *__restrict__ psi, uint64_t nblocks, InsBits outer, BlockMap bm,
-    const BlkStage *__restrict__ stages, int nstages, const R *__restrict__ mats)
+    const BlkStage *__restrict__ stages, int nstages, const R *__restrict__ mats, BlkMfma mf)
 {
     using C2 = typename BT<R>::C2;
     extern __shared__ __align__(16) unsigned char smem_blk[];
     C2 *s = reinterpret_cast<C2 *>(smem_blk);
     constexpr int N = 1 << B;
+    constexpr bool MF = sizeof(R) == 4 && W == 4;  // complex64 stages may run fused on the matrix cores
+    C2 *Ml = s + N;                                  // the pass's fused stage matrices (visible after the first barrier)
+    if constexpr (MF) {
+        for (int i = threadIdx.x; i < 256 * mf.n; i += NT) {
+            const R *src = mats + mf.off[i >> 8] + 2 * (i & 255);
+            Ml[i] = C2{src[0], src[1]};
+        }
+    }
     constexpr int PER = N / NT;  // amplitudes per thread for load / store
     constexpr int LNT = __builtin_ctz(NT);
     constexpr int PB = B - LNT;  // bits of the per-thread amplitude counter it
@@ -315,7 +385,15 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, B, NT>::waves_per_eu)) void k_b
                 pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(pb + hi_of(h, it)));
         }
         for (int t = 0; t < nstages; ++t) {
-            run_stage<R, B, W, NT>(s, stages[t], mats);
+            if constexpr (MF) {
+                const int slot = stages[t].mfma;
+                if (slot >= 0)
+                    run_stage_mfma<B, NT>(s, stages[t], Ml + 256 * slot);
+                else
+                    run_stage<R, B, W, NT>(s, stages[t], mats);
+            } else {
+                run_stage<R, B, W, NT>(s, stages[t], mats);
+            }
             lds_barrier();
         }
         {
@@ -700,16 +778,20 @@ hipError_t batch_r(int b, void *psi, double *probs, const BatchItem *items, int 
 
 template <class R, int B, int W>
 hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm, const BlkStage *stages,
-                   int nstages, const void *mats, hipStream_t s)
+                   int nstages, const void *mats, const BlkMfma &mf, hipStream_t s)
 {
     using C2 = typename BT<R>::C2;
     constexpr int NT = BlockThreads<B, W>::value;
     static_assert((1 << B) >= NT, "block smaller than the workgroup");
-    const size_t shm = sizeof(C2) << B;
+    if (mf.n < 0 || mf.n > kMaxMfmaStages || (mf.n > 0 && (sizeof(R) != 4 || W != 4)))
+        return hipErrorInvalidValue;
+    const size_t data = sizeof(C2) << B;
+    const size_t shm = data + 256 * sizeof(C2) * mf.n;
     static bool attr_set = false;
-    if (!attr_set && shm > 65536) {
+    const size_t shm_max = data + (sizeof(R) == 4 && W == 4 ? 256 * sizeof(C2) * kMaxMfmaStages : 0);
+    if (!attr_set && shm_max > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)k_block<R, B, W, NT>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_max);
         if (e != hipSuccess)
             return e;
         attr_set = true;
@@ -743,30 +825,30 @@ hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const Bloc
         }
     }
     hipLaunchKernelGGL((k_block<R, B, W, NT>), dim3((unsigned)grid), dim3(NT), shm, s, (C2 *)psi, nblocks, outer, bm,
-                       stages, nstages, (const R *)mats);
+                       stages, nstages, (const R *)mats, mf);
     return hipGetLastError();
 }
 
 template <class R>
 hipError_t block_r(int b, int w, void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm,
-                   const BlkStage *stages, int nstages, const void *mats, hipStream_t s)
+                   const BlkStage *stages, int nstages, const void *mats, const BlkMfma &mf, hipStream_t s)
 {
     if (w == 3) {
         switch (b) {
-        case 12: return block_b<R, 12, 3>(psi, nblocks, outer, bm, stages, nstages, mats, s);
-        case 13: return block_b<R, 13, 3>(psi, nblocks, outer, bm, stages, nstages, mats, s);
+        case 12: return block_b<R, 12, 3>(psi, nblocks, outer, bm, stages, nstages, mats, mf, s);
+        case 13: return block_b<R, 13, 3>(psi, nblocks, outer, bm, stages, nstages, mats, mf, s);
         default: return hipErrorInvalidValue;
         }
     }
     if (w != 4)
         return hipErrorInvalidValue;
     switch (b) {
-    case 8: return block_b<R, 8, 4>(psi, nblocks, outer, bm, stages, nstages, mats, s);
-    case 9: return block_b<R, 9, 4>(psi, nblocks, outer, bm, stages, nstages, mats, s);
-    case 10: return block_b<R, 10, 4>(psi, nblocks, outer, bm, stages, nstages, mats, s);
-    case 11: return block_b<R, 11, 4>(psi, nblocks, outer, bm, stages, nstages, mats, s);
-    case 12: return block_b<R, 12, 4>(psi, nblocks, outer, bm, stages, nstages, mats, s);
-    case 13: return block_b<R, 13, 4>(psi, nblocks, outer, bm, stages, nstages, mats, s);
+    case 8: return block_b<R, 8, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, s);
+    case 9: return block_b<R, 9, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, s);
+    case 10: return block_b<R, 10, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, s);
+    case 11: return block_b<R, 11, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, s);
+    case 12: return block_b<R, 12, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, s);
+    case 13: return block_b<R, 13, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -784,10 +866,10 @@ hipError_t launch_batch_level(int dtype, int b, void *psi, double *probs, const 
 }
 
 hipError_t launch_block(int dtype, int b, int w, void *psi, uint64_t nblocks, const InsBits &outer,
-                        const BlockMap &bm, const BlkStage *stages_dev, int nstages, 
-                        const void *mats_dev, hipStream_t s)
+                        const BlockMap &bm, const BlkStage *stages_dev, int nstages, const void *mats_dev,
+                        const BlkMfma &mf, hipStream_t s)
 {
     return dtype == QS_C128
-               ? block_r<double>(b, w, psi, nblocks, outer, bm, stages_dev, nstages, mats_dev, s)
-               : block_r<float>(b, w, psi, nblocks, outer, bm, stages_dev, nstages, mats_dev, s);
+               ? block_r<double>(b, w, psi, nblocks, outer, bm, stages_dev, nstages, mats_dev, mf, s)
+               : block_r<float>(b, w, psi, nblocks, outer, bm, stages_dev, nstages, mats_dev, mf, s);
 }

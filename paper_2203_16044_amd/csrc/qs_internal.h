@@ -134,6 +134,9 @@ struct BlkStage {
     // kernel finds every op of the stage without a dependent load
     uint32_t masks;
     uint32_t mat_base;
+    // complex64 4-position stages with several ops: slot (0..kMaxMfmaStages-1) of the stage's fused 16 x 16 complex
+    // matrix among the pass's MFMA matrices, applied on the matrix cores; -1: ops applied one by one in registers
+    int mfma;
     // the other local positions in the order the bits of a thread's group counter fill them: the first four cover
     // the four residue classes (mod 4) of the LDS swizzle so that 16 consecutive lanes hit 16 distinct bank groups
     int order[kMaxBlockBits - 3];
@@ -143,9 +146,16 @@ struct BlkStageOp {  // host-side op table (planner statistics and batch relocat
     uint32_t mat_off;  // offset of its 2^k x 2^k matrix (bit order of the mask's positions) in real elements
 };
 // w = register stage width: 4 (256 threads, any b in 8..13) or 3 (512 threads, b = 12, 13)
+// Fused stage matrices of one pass (complex64): pool offsets (real elements) of n 16 x 16 complex matrices, row-major
+// and interleaved, whose stage index bit j <-> stage position pos[j]; the kernel keeps them in LDS.
+constexpr int kMaxMfmaStages = 4;
+struct BlkMfma {
+    int n = 0;
+    uint32_t off[kMaxMfmaStages] = {0, 0, 0, 0};
+};
 hipError_t launch_block(int dtype, int b, int w, void *psi, uint64_t nblocks, const InsBits &outer,
                         const BlockMap &bm, const BlkStage *stages_dev, int nstages, const void *mats_dev,
-                        hipStream_t s);
+                        const BlkMfma &mf, hipStream_t s);
 
 // batched circuits: one persistent launch per pass level (see qs_block.hip)
 struct BatchCirc {
@@ -203,5 +213,6 @@ struct Tunables {
     int block_stage_width = 4; // register stage width of new block plans: 4, or 3 (512-thread kernel, b = 12, 13)
     int plan_beam = 16;        // pass formation: beam width over local-set growth (0: fewest-new-qubits greedy)
     int block_async = 0;       // 12-qubit block passes: double-buffered LDS with direct-to-LDS loads
+    int mfma_stage_ops = 3;    // complex64 plans: stages of at least this many ops run fused on MFMA (0: never)
 };
 Tunables &qs_tunables();

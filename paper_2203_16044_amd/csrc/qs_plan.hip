@@ -120,6 +120,7 @@ struct PlanPass {
     int op_begin = 0, nops = 0;  // block: fused ops carried
     int stage_begin = 0, nstages = 0;  // block: range in stages
     int sw = 4;                        // block: register stage width (3 or 4)
+    BlkMfma mf{};                      // block, complex64: fused stage matrices run on the matrix cores
     // dense
     int k = 0;
     TPos tp{};
@@ -727,6 +728,7 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
         std::vector<char> placed(nf, 0);
         int left = nf;
         pp.stage_begin = (int)P->stages.size();
+        std::vector<std::vector<int>> stage_members;  // fused-op indices of each stage of this pass, in order
         while (left) {
             uint32_t S = 0;
             std::vector<int> members;
@@ -779,6 +781,7 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
                 for (int t = 0; t < b - W; ++t)
                     stg.order[t] = ord[t];
             }
+            stage_members.push_back(members);
             stg.op_begin = (int)P->sops.size();
             stg.nops = (int)members.size();
             stg.mat_base = (uint32_t)P->pool.size();
@@ -793,9 +796,54 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
                 P->sops.push_back(so);
                 stg.masks |= (uint32_t)so.mask << (4 * o);
             }
+            stg.mfma = -1;
             P->stages.push_back(stg);
         }
         pp.nstages = (int)P->stages.size() - pp.stage_begin;
+        // complex64: the pass's stages with the most ops (at least mfma_stage_ops; up to kMaxMfmaStages, the LDS
+        // they may take) become dense 16 x 16 products on the matrix cores. FP32 MFMA runs at twice the FP32 FMA
+        // rate, which pays for the denser matrix from about three ops on. The product of the stage's ops is formed
+        // here in FP64 (op o first), with stage index bit j <-> pos[j] as in the per-op masks.
+        const int mfma_ops = qs_tunables().mfma_stage_ops;
+        if (P->dtype == QS_C64 && W == 4 && mfma_ops > 0) {
+            std::vector<int> pick;
+            for (int t = 0; t < pp.nstages; ++t)
+                if (P->stages[pp.stage_begin + t].nops >= mfma_ops)
+                    pick.push_back(t);
+            std::stable_sort(pick.begin(), pick.end(), [&](int x, int y) {
+                return P->stages[pp.stage_begin + x].nops > P->stages[pp.stage_begin + y].nops;
+            });
+            if ((int)pick.size() > kMaxMfmaStages)
+                pick.resize(kMaxMfmaStages);
+            std::sort(pick.begin(), pick.end());
+            for (int t : pick) {
+                BlkStage &st = P->stages[pp.stage_begin + t];
+                std::vector<cd> M(256, cd(0, 0));
+                for (int r = 0; r < 16; ++r)
+                    M[r * 16 + r] = 1;
+                for (int o = 0; o < st.nops; ++o) {
+                    const int mk = (int)((st.masks >> (4 * o)) & 15u);
+                    const std::vector<cd> &U = sorted_ops[stage_members[t][o]].m;
+                    const int D = 1 << __builtin_popcount(mk);
+                    auto sub = [mk](int x) {  // bits of x at the op's positions, packed (j-th set bit -> bit j)
+                        int v = 0, jj = 0;
+                        for (int q = 0; q < 4; ++q)
+                            if ((mk >> q) & 1)
+                                v |= ((x >> q) & 1) << jj++;
+                        return v;
+                    };
+                    std::vector<cd> E(256, cd(0, 0));
+                    for (int r = 0; r < 16; ++r)
+                        for (int c2 = 0; c2 < 16; ++c2)
+                            if ((r & ~mk) == (c2 & ~mk))
+                                E[r * 16 + c2] = U[sub(r) * D + sub(c2)];
+                    M = matmul(E, M, 16);
+                }
+                st.mfma = pp.mf.n;
+                pp.mf.off[pp.mf.n++] = (uint32_t)P->pool.size();
+                push_matrix(P->pool, M);
+            }
+        }
         P->nfused_ops += pp.nops;
         P->passes.push_back(std::move(pp));
     }
@@ -826,7 +874,7 @@ QS_API int qs_plan_run_range(qs_state *st, qs_plan *P, int begin, int end)
         case 0: {
             const InsBits outer = qs_make_ins(pp.lmask, 0);
             QS_HIP(launch_block(st->dtype, pp.b, pp.sw, st->psi, (uint64_t)1 << (P->n - pp.b), outer, pp.bm,
-                                P->dstages + pp.stage_begin, pp.nstages, P->dpool, st->stream));
+                                P->dstages + pp.stage_begin, pp.nstages, P->dpool, pp.mf, st->stream));
             break;
         }
         case 1: {

@@ -134,17 +134,36 @@ def test_plan_double_buffered_block_pass(gpu, block_async, low, dtype, tol):
         assert _maxerr(got, oracle.run(circ, psi0)) <= tol, circ.name
 
 
+@pytest.mark.parametrize("dtype,tol", [("c128", TOL128), ("c64", 2e-5)])
 @pytest.mark.parametrize("bits,low", [(10, 4), (12, 3), (12, 4)])
-def test_plan_long_runs_of_ops_on_four_qubits(gpu, bits, low):
+def test_plan_long_runs_of_ops_on_four_qubits(gpu, bits, low, dtype, tol):
     """40 two-qubit gates that cycle through the pairs of qubits 0-3 (no gate's qubits are a subset of its
     neighbour's, so none merge) all fall into stages over the same 4 local positions; a stage record holds at most
-    8 ops, so the planner splits the run into several stages over those positions."""
+    8 ops, so the planner splits the run into several stages over those positions. In complex64 the first four of
+    those stages run as fused 16 x 16 products on the matrix cores and the rest op by op, in the same pass."""
     rng = np.random.Generator(np.random.PCG64(71))
     pairs = [(0, 1), (1, 2), (2, 3), (0, 3), (0, 2), (1, 3)]
     ops = [C.Op("dense", pairs[i % len(pairs)], mat=C.haar_su4(rng)) for i in range(40)]
     ops += [C.Op("dense", (5, 9), mat=C.haar_su4(rng)), C.Op("dense", (0, 11), mat=C.haar_su4(rng))]
     circ = C.Circuit(14, ops=ops, name="four_qubit_run")
     psi0 = C.random_state(14, 77)
-    got, info = _run_plan(gpu, circ, "block", bits, low, psi0)
+    if dtype == "c64":
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)  # the oracle starts from the rounded state
+    got, info = _run_plan(gpu, circ, "block", bits, low, psi0, dtype)
     assert info["fused_ops"] >= 40
-    assert _maxerr(got, oracle.run(circ, psi0)) <= TOL128
+    assert _maxerr(got, oracle.run(circ, psi0)) <= tol
+
+
+@pytest.mark.parametrize("ops_min", [0, 2, 3])
+def test_plan_complex64_mfma_stages_match_op_by_op(gpu, ops_min):
+    """The fused MFMA form of complex64 stages (tunable mfma_stage_ops; 0 turns it off) against the oracle on the
+    random SU(4)+U3 family, whose 12-qubit passes have stages of 1-8 ops."""
+    import paper_2203_16044_amd.binding as B
+    circ = C.su4_u3_random(n=18, seed=318, layers=8)
+    psi0 = C.random_state(18, 319).astype(np.complex64).astype(np.complex128)
+    B.qs_set_tunable("mfma_stage_ops", ops_min)
+    try:
+        got, _ = _run_plan(gpu, circ, "block", 12, 4, psi0, "c64")
+    finally:
+        B.qs_set_tunable("mfma_stage_ops", 3)
+    assert _maxerr(got, oracle.run(circ, psi0)) <= 2e-5
