@@ -38,10 +38,10 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (= FP64 MFMA): 256 CUs x 4 SIMDs x
 PMC_TRAFFIC = {
     "block_b12": {"fetch_kib": 33554693.8, "write_kib": 67111395.5, "fetch_scale": 2.0, "write_scale": 1.0,
                   "sources": ["paper_2203_16044_amd/csrc/qs_block.hip", "paper_2203_16044_amd/csrc/qs_internal.h"],
-                  "sha1": "04cd51978eadae06c098f65f7005b6d7309eee0e"},
+                  "sha1": "c579cd60f59aa3b482cc74c4bba38855befdff8c"},
     "dense_k1": {"fetch_kib": 33554444.3, "write_kib": 67110475.4, "fetch_scale": 2.0, "write_scale": 1.0,
                  "sources": ["paper_2203_16044_amd/csrc/qs_kernels.hip", "paper_2203_16044_amd/csrc/qs_internal.h"],
-                 "sha1": "28f4428f5128f8f85f16147fc51d94a4c74c7bed"},
+                 "sha1": "d373385fbfb64da6e6d2ee4b35df08586aedfc90"},
 }
 
 

@@ -639,10 +639,6 @@ QS_API int qs_set_tunable(const char *name, int64_t value)
         if (value < 0 || value > kStageMaxOps)
             return qs_fail(QS_EINVAL, "mfma_stage_ops must be in [0, %d]", kStageMaxOps);
         t.mfma_stage_ops = (int)value;
-    } else if (!std::strcmp(name, "mfma_stage_ops_c128")) {
-        if (value < 0 || value > kStageMaxOps)
-            return qs_fail(QS_EINVAL, "mfma_stage_ops_c128 must be in [0, %d]", kStageMaxOps);
-        t.mfma_stage_ops_c128 = (int)value;
     } else if (!std::strcmp(name, "plan_beam")) {
         if (value < 0 || value > 64)
             return qs_fail(QS_EINVAL, "plan_beam must be in [0, 64]");

@@ -182,58 +182,34 @@ __device__ __forceinline__ void run_stage(typename BT<R>::C2 *s, const BlkStage 
     }
 }
 
-// A 4-position stage as one dense product Y = M X on the matrix cores: M is the stage's fused 16 x 16 complex
-// matrix (its ops multiplied on the host; stage index bit j <-> pos[j]), X the 16 x 2^(B-4) matrix whose columns are
-// the register groups. As in the dense MFMA kernel the product runs on real 16x16x4 tiles (FP32 for complex64, FP64
-// for complex128) with interleaved (re, im) rows: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; register
-// r of lane l holds D[4 (l / 16) + r][l % 16] (FP32) or D[l / 16 + 4 r][l % 16] (FP64), and tile row i of A' is
-// assigned to (output member, component) so that either way registers (0, 1) and (2, 3) of lane l are members
-// 8 rt + 2 (l / 16) and 8 rt + 2 (l / 16) + 1, (re, im) each. Each wave owns whole 16-group column tiles, so a
-// tile is read and rewritten in place by one wave. slot_bytes is linear in XOR, so a member's LDS offset is the XOR
-// of the offsets of its bits: no register array is indexed by a lane-dependent value.
-template <class R> struct StageMma;
-template <> struct StageMma<float> {
-    typedef float acc_t __attribute__((ext_vector_type(4)));
-    static __device__ __forceinline__ acc_t mma(float a, float b, acc_t c)
-    {
-        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row_member(int i) { return i >> 1; }
-    static __device__ __forceinline__ int row_comp(int i) { return i & 1; }
-};
-template <> struct StageMma<double> {
-    typedef double acc_t __attribute__((ext_vector_type(4)));
-    static __device__ __forceinline__ acc_t mma(double a, double b, acc_t c)
-    {
-        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-    }
-    static __device__ __forceinline__ int row_member(int i) { return 2 * (i & 3) + (i >> 3); }
-    static __device__ __forceinline__ int row_comp(int i) { return (i >> 2) & 1; }
-};
-
-template <class R, int B, int NT>
-__device__ __forceinline__ void run_stage_mfma(typename BT<R>::C2 *s, const BlkStage &stg,
-                                               const typename BT<R>::C2 *Ml)
+// A complex64 4-position stage as one dense product Y = M X on the matrix cores: M is the stage's fused 16 x 16
+// complex matrix (its ops multiplied on the host; stage index bit j <-> pos[j]), X the 16 x 2^(B-4) matrix whose
+// columns are the register groups. As in the dense MFMA kernel the product runs on real 16x16x4 FP32 tiles with
+// interleaved (re, im) rows: lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16], and register r of lane l
+// holds D[4 (l / 16) + r][l % 16]; tile row i of A' is output member 8 rt + i / 2, component i % 2, so every lane's
+// accumulators are two complete outputs. Each wave owns whole 16-group column tiles, so a tile is read and
+// rewritten in place by one wave. slot_bytes is linear in XOR, so a member's LDS offset is the XOR of the offsets
+// of its bits: no register array is indexed by a lane-dependent value.
+template <int B, int NT>
+__device__ __forceinline__ void run_stage_mfma(float2 *s, const BlkStage &stg, const float2 *Ml)
 {
-    using C2 = typename BT<R>::C2;
-    using MM = StageMma<R>;
-    using acc_t = typename MM::acc_t;
+    typedef float acc_t __attribute__((ext_vector_type(4)));
     constexpr int NG = 1 << (B - 4);
     constexpr int NW = NT / 64;
     static_assert(NG % 16 == 0 && NT % 64 == 0, "MFMA stage shape");
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int j = lane & 15, kq = lane >> 4;
     uint32_t soff[16];
-    stage_offsets<C2, 4>(stg, soff);
+    stage_offsets<float2, 4>(stg, soff);
     const uint32_t in_q = ((kq & 1) ? soff[1] : 0u) ^ ((kq & 2) ? soff[2] : 0u);   // members 4 t + kq
     const uint32_t out_q = ((kq & 1) ? soff[2] : 0u) ^ ((kq & 2) ? soff[4] : 0u);  // members 8 rt + 2 kq (+1)
-    R afr[2][4][2];
+    float afr[2][4][2];
 #pragma unroll
     for (int rt = 0; rt < 2; ++rt) {
-        const int ao = 8 * rt + MM::row_member(j), co = MM::row_comp(j);
+        const int ao = 8 * rt + (j >> 1), co = j & 1;
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const C2 u = Ml[ao * 16 + 4 * t + kq];
+            const float2 u = Ml[ao * 16 + 4 * t + kq];
             afr[rt][t][0] = co == 0 ? u.x : u.y;   // multiplies Re x
             afr[rt][t][1] = co == 0 ? -u.y : u.x;  // multiplies Im x
         }
@@ -244,31 +220,26 @@ __device__ __forceinline__ void run_stage_mfma(typename BT<R>::C2 *s, const BlkS
 #pragma unroll
         for (int b = 0; b < B - 4; ++b)
             m |= ((g >> b) & 1u) << stg.order[b];
-        const uint32_t sm = slot_bytes<C2>(m);
+        const uint32_t sm = slot_bytes<float2>(m);
         acc_t acc[2][2];
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt)
             acc[rt][0] = acc[rt][1] = acc_t{0, 0, 0, 0};
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            const C2 bv = lds_at(s, sm ^ soff[4 * t] ^ in_q);
+            const float2 bv = lds_at(s, sm ^ soff[4 * t] ^ in_q);
 #pragma unroll
             for (int rt = 0; rt < 2; ++rt) {
-                acc[rt][t & 1] = MM::mma(afr[rt][t][0], bv.x, acc[rt][t & 1]);
-                acc[rt][t & 1] = MM::mma(afr[rt][t][1], bv.y, acc[rt][t & 1]);
+                acc[rt][t & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[rt][t][0], bv.x, acc[rt][t & 1], 0, 0, 0);
+                acc[rt][t & 1] = __builtin_amdgcn_mfma_f32_16x16x4f32(afr[rt][t][1], bv.y, acc[rt][t & 1], 0, 0, 0);
             }
         }
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
             const acc_t y = acc[rt][0] + acc[rt][1];
             const uint32_t o0 = sm ^ soff[8 * rt] ^ out_q;
-            C2 y0, y1;
-            y0.x = y[0];
-            y0.y = y[1];
-            y1.x = y[2];
-            y1.y = y[3];
-            lds_at(s, o0) = y0;
-            lds_at(s, o0 ^ soff[1]) = y1;
+            lds_at(s, o0) = make_float2(y[0], y[1]);
+            lds_at(s, o0 ^ soff[1]) = make_float2(y[2], y[3]);
         }
     }
 }
@@ -307,8 +278,7 @@ __device__ __forceinline__ void run_stage_n(typename BT<R>::C2 *s, const BlkStag
 // 128 for 11, 256 for 12 and 13); 512 with 3-position stages (8 register amplitudes per thread, so that two 64 KB
 // complex128 blocks per CU run 16 waves when the kernel stays within 128 VGPRs).
 template <class R, int B, int NT> struct BlockBounds {
-    static constexpr int waves_per_eu =
-        NT == 512 || (sizeof(R) == 4 && NT >= 128 && B <= 12) ? 4 : (sizeof(R) == 8 && B <= 12 && B >= 10 ? 2 : 1);
+    static constexpr int waves_per_eu = NT == 512 || (sizeof(R) == 4 && NT >= 128 && B <= 12) ? 4 : 1;
 };
 // Complex64 blocks of 11-12 qubits (16-32 KB of LDS) are held to 128 VGPRs for 4 waves per SIMD: 2-4 % faster
 // at 33 qubits than the 3 waves of the unconstrained ~130-VGPR build (the bound costs three 64-bit scratch reloads
@@ -330,7 +300,7 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, B, NT>::waves_per_eu)) void k_b
     extern __shared__ __align__(16) unsigned char smem_blk[];
     C2 *s = reinterpret_cast<C2 *>(smem_blk);
     constexpr int N = 1 << B;
-    constexpr bool MF = W == 4 && B <= 12;  // stages may run fused on the matrix cores
+    constexpr bool MF = sizeof(R) == 4 && W == 4;  // complex64 stages may run fused on the matrix cores
     C2 *Ml = s + N;                                  // the pass's fused stage matrices (visible after the first barrier)
     if constexpr (MF) {
         for (int i = threadIdx.x; i < 256 * mf.n; i += NT) {
@@ -418,7 +388,7 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, B, NT>::waves_per_eu)) void k_b
             if constexpr (MF) {
                 const int slot = stages[t].mfma;
                 if (slot >= 0)
-                    run_stage_mfma<R, B, NT>(s, stages[t], Ml + 256 * slot);
+                    run_stage_mfma<B, NT>(s, stages[t], Ml + 256 * slot);
                 else
                     run_stage<R, B, W, NT>(s, stages[t], mats);
             } else {
@@ -813,12 +783,12 @@ hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const Bloc
     using C2 = typename BT<R>::C2;
     constexpr int NT = BlockThreads<B, W>::value;
     static_assert((1 << B) >= NT, "block smaller than the workgroup");
-    if (mf.n < 0 || mf.n > kMaxMfmaStages || (mf.n > 0 && (W != 4 || B > 12)))
+    if (mf.n < 0 || mf.n > kMaxMfmaStages || (mf.n > 0 && (sizeof(R) != 4 || W != 4)))
         return hipErrorInvalidValue;
     const size_t data = sizeof(C2) << B;
     const size_t shm = data + 256 * sizeof(C2) * mf.n;
     static bool attr_set = false;
-    const size_t shm_max = data + (W == 4 && B <= 12 ? 256 * sizeof(C2) * kMaxMfmaStages : 0);
+    const size_t shm_max = data + (sizeof(R) == 4 && W == 4 ? 256 * sizeof(C2) * kMaxMfmaStages : 0);
     if (!attr_set && shm_max > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)k_block<R, B, W, NT>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_max);

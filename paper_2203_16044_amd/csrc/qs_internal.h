@@ -214,6 +214,5 @@ struct Tunables {
     int plan_beam = 16;        // pass formation: beam width over local-set growth (0: fewest-new-qubits greedy)
     int block_async = 0;       // 12-qubit block passes: double-buffered LDS with direct-to-LDS loads
     int mfma_stage_ops = 3;    // complex64 plans: stages of at least this many ops run fused on MFMA (0: never)
-    int mfma_stage_ops_c128 = 0;  // the same for complex128 plans (FP64 MFMA)
 };
 Tunables &qs_tunables();

@@ -804,8 +804,8 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
         // they may take) become dense 16 x 16 products on the matrix cores. FP32 MFMA runs at twice the FP32 FMA
         // rate, which pays for the denser matrix from about three ops on. The product of the stage's ops is formed
         // here in FP64 (op o first), with stage index bit j <-> pos[j] as in the per-op masks.
-        const int mfma_ops = P->dtype == QS_C64 ? qs_tunables().mfma_stage_ops : qs_tunables().mfma_stage_ops_c128;
-        if (W == 4 && b <= 12 && mfma_ops > 0) {
+        const int mfma_ops = qs_tunables().mfma_stage_ops;
+        if (P->dtype == QS_C64 && W == 4 && mfma_ops > 0) {
             std::vector<int> pick;
             for (int t = 0; t < pp.nstages; ++t)
                 if (P->stages[pp.stage_begin + t].nops >= mfma_ops)

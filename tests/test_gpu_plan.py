@@ -167,23 +167,3 @@ def test_plan_complex64_mfma_stages_match_op_by_op(gpu, ops_min):
     finally:
         B.qs_set_tunable("mfma_stage_ops", 3)
     assert _maxerr(got, oracle.run(circ, psi0)) <= 2e-5
-
-
-@pytest.mark.parametrize("ops_min", [3, 5])
-def test_plan_complex128_mfma_stages(gpu, ops_min):
-    """complex128 stages fused into 16 x 16 products on the FP64 matrix cores (tunable mfma_stage_ops_c128) against
-    the oracle: the random SU(4)+U3 family and a 40-op run over four qubits (stages of 8 ops, 4 of them fused)."""
-    import paper_2203_16044_amd.binding as B
-    rng = np.random.Generator(np.random.PCG64(72))
-    pairs = [(0, 1), (1, 2), (2, 3), (0, 3), (0, 2), (1, 3)]
-    run = C.Circuit(14, ops=[C.Op("dense", pairs[i % len(pairs)], mat=C.haar_su4(rng)) for i in range(40)],
-                    name="four_qubit_run")
-    cases = [(C.su4_u3_random(n=18, seed=320, layers=8), 321), (run, 322)]
-    B.qs_set_tunable("mfma_stage_ops_c128", ops_min)
-    try:
-        for circ, sd in cases:
-            psi0 = C.random_state(circ.n, sd)
-            got, _ = _run_plan(gpu, circ, "block", 12, 4, psi0, "c128")
-            assert _maxerr(got, oracle.run(circ, psi0)) <= TOL128
-    finally:
-        B.qs_set_tunable("mfma_stage_ops_c128", 0)
