@@ -36,10 +36,10 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (= FP64 MFMA): 256 CUs x 4 SIMDs x
 # the bytes read, WRITE_SIZE 4194304 KiB, all bytes written). Commands and figures: profiles/*_pmc_traffic.md. The readings hold for the kernel sources they were taken on: `sha1` fingerprints
 # those files and the traffic is reported as null once they differ.
 PMC_TRAFFIC = {
-    "block_b12": {"fetch_kib": 33554693.8, "write_kib": 67111395.5, "fetch_scale": 2.0, "write_scale": 1.0,
+    "block_b12": {"fetch_kib": 33554673.3, "write_kib": 67111620.8, "fetch_scale": 2.0, "write_scale": 1.0,
                   "sources": ["paper_2203_16044_amd/csrc/qs_block.hip", "paper_2203_16044_amd/csrc/qs_internal.h"],
                   "sha1": "c579cd60f59aa3b482cc74c4bba38855befdff8c"},
-    "dense_k1": {"fetch_kib": 33554444.3, "write_kib": 67110475.4, "fetch_scale": 2.0, "write_scale": 1.0,
+    "dense_k1": {"fetch_kib": 33554444.2, "write_kib": 67110489.2, "fetch_scale": 2.0, "write_scale": 1.0,
                  "sources": ["paper_2203_16044_amd/csrc/qs_kernels.hip", "paper_2203_16044_amd/csrc/qs_internal.h"],
                  "sha1": "d373385fbfb64da6e6d2ee4b35df08586aedfc90"},
 }
