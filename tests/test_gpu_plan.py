@@ -135,7 +135,7 @@ def test_plan_double_buffered_block_pass(gpu, block_async, low, dtype, tol):
 
 
 @pytest.mark.parametrize("dtype,tol", [("c128", TOL128), ("c64", 2e-5)])
-@pytest.mark.parametrize("bits,low", [(10, 4), (12, 3), (12, 4)])
+@pytest.mark.parametrize("bits,low", [(10, 4), (11, 3), (12, 3), (12, 4), (13, 4)])
 def test_plan_long_runs_of_ops_on_four_qubits(gpu, bits, low, dtype, tol):
     """40 two-qubit gates that cycle through the pairs of qubits 0-3 (no gate's qubits are a subset of its
     neighbour's, so none merge) all fall into stages over the same 4 local positions; a stage record holds at most
