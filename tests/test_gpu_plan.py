@@ -167,3 +167,19 @@ def test_plan_complex64_mfma_stages_match_op_by_op(gpu, ops_min):
     finally:
         B.qs_set_tunable("mfma_stage_ops", 3)
     assert _maxerr(got, oracle.run(circ, psi0)) <= 2e-5
+
+
+@pytest.mark.parametrize("dtype,tol", [("c128", TOL128), ("c64", 2e-5)])
+def test_plan_runs_on_three_qubits_pad_the_stage(gpu, dtype, tol):
+    """Gates cycling over the pairs of qubits 0-2 only: their stages hold 3 positions and are padded with an unused
+    one (in complex64 the fused stage matrix acts as the identity on it)."""
+    rng = np.random.Generator(np.random.PCG64(73))
+    pairs = [(0, 1), (1, 2), (0, 2)]
+    ops = [C.Op("dense", pairs[i % len(pairs)], mat=C.haar_su4(rng)) for i in range(24)]
+    ops += [C.Op("dense", (4, 10), mat=C.haar_su4(rng))]
+    circ = C.Circuit(13, ops=ops, name="three_qubit_run")
+    psi0 = C.random_state(13, 78)
+    if dtype == "c64":
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)
+    got, _ = _run_plan(gpu, circ, "block", 12, 3, psi0, dtype)
+    assert _maxerr(got, oracle.run(circ, psi0)) <= tol
