@@ -6,16 +6,17 @@ SU(4) on every pair, then a random U3 on every qubit; 1,920 gates), a synthetic 
 Quantum Volume / QSB suites (Sec. IV-E, IV-F). One step = reset to |0..0>, apply the whole circuit, FP64 norm
 (the probability reduction) -- every step of the hot path -- with the state resident in HBM.
 
-Reported: gates/s of the timed steps (whole job, one GPU); the dominant kernel's achieved HBM bandwidth against
-the 8 TB/s peak, from HIP events recorded around every launch on the stream the kernels run on; the FP64 CPU
-oracle timed on the host's cores over a bounded sample of the same circuit.
+Reported: gates/s of the timed steps (whole job, one GPU); the dominant kernel's achieved rate against its binding
+roof (HBM at 8 TB/s or FP64 at 78.6 TFLOP/s, both fractions given), from HIP events recorded around every launch on
+the stream the kernels run on, with its PMC-measured HBM traffic; the FP64 CPU oracle timed on the host's cores
+over a bounded sample of the same circuit.
 
 Modes: "plain" applies the circuit gate by gate (one HBM pass per gate); "tuned" runs the fused plan (see
 paper_2203_16044_amd.plan) and also reports plain on a prefix of the circuit for the speedup.
 
 Further legs in the same JSON line: "c64" (the 33-qubit complex64 circuit of the same family with FP64
-renormalisation every 10 layers, and the complex64 error at 24 qubits) and "batch" (512 small circuits in one
-persistent launch, autotuned, eager and graph-replayed, against the per-circuit plain loop).
+renormalisation every 10 layers, and the complex64 error at 24 qubits) and "batch" (512 circuits of 10-22 qubits,
+one persistent launch per pass level, autotuned, eager and graph-replayed, against the per-circuit plain loop).
 """
 import argparse
 import json
@@ -33,8 +34,9 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (= FP64 MFMA): 256 CUs x 4 SIMDs x
 # HBM traffic per dispatch of the dominant kernels, from two rocprofv3 PMC runs of this script (FETCH_SIZE, then
 # WRITE_SIZE; KiB per dispatch, mean over the 32-qubit dispatches), each scaled by what the same counter reads for
 # a device copy of known size (paper_2203_16044_amd.probe copy of 4 GiB: FETCH_SIZE reports 2097194 KiB, half of
-# the bytes read, WRITE_SIZE 4194304 KiB, all bytes written). Commands and figures: profiles/*_pmc_traffic.md. The readings hold for the kernel sources they were taken on: `sha1` fingerprints
-# those files and the traffic is reported as null once they differ.
+# the bytes read, WRITE_SIZE 4194304 KiB, all bytes written). Commands and figures: profiles/*_pmc_traffic.md.
+# The readings hold for the kernel sources they were taken on: `sha1` fingerprints those files and the traffic is
+# reported as null once they differ.
 PMC_TRAFFIC = {
     "block_b12": {"fetch_kib": 33554673.3, "write_kib": 67111620.8, "fetch_scale": 2.0, "write_scale": 1.0,
                   "sources": ["paper_2203_16044_amd/csrc/qs_block.hip", "paper_2203_16044_amd/csrc/qs_internal.h"],
