@@ -678,13 +678,39 @@ __global__ __launch_bounds__(256, (sizeof(R) == 4 ? 4 : 1)) void k_batch_level(t
     if (g >= nblocks)
         return;
     // HBM blocks: the rotated pipeline of k_block (prefetch of the next block before the stages; waits only on the
-    // prefetch loads, the previous block's stores keep draining).
+    // prefetch loads, the previous block's stores keep draining). Complex64: the fused stage matrices of the next
+    // block's pass (entry threadIdx.x of each) are fetched after the stages, before the stores, and written to LDS
+    // beside the prefetched block.
+    constexpr bool MF = sizeof(R) == 4;
+    C2 *Ml = s + (1 << B);
+    C2 mreg[kMaxMfmaStages];
+    auto mfetch = [&](const BatchPass *p) {
+        if constexpr (MF) {
+#pragma unroll
+            for (int i = 0; i < kMaxMfmaStages; ++i)
+                if (i < p->mf.n) {
+                    const R *src = mats + p->mf.off[i] + 2 * threadIdx.x;
+                    mreg[i].x = src[0];
+                    mreg[i].y = src[1];
+                }
+        }
+    };
+    auto mstore = [&](const BatchPass *p) {
+        if constexpr (MF) {
+#pragma unroll
+            for (int i = 0; i < kMaxMfmaStages; ++i)
+                if (i < p->mf.n)
+                    Ml[256 * i + threadIdx.x] = mreg[i];
+        }
+    };
     const uint32_t sbase = slot_bytes<C2>(threadIdx.x);
     NV pre[PER];
     const BatchPass *bp = &passes[cur.pass];
     uint64_t base = ins0b(g - cur.blk_begin, bp->outer) | spread(threadIdx.x, bp->bm);
     batch_fetch<R, B>(pre, psi_base + cur.state_off, base, bp->bm);
+    mfetch(bp);
     batch_to_lds<R, B>(s, pre, base, bp->bm, (cur.flags & kBatchFirst) != 0, sbase);
+    mstore(bp);
     lds_barrier();
     for (;;) {
         const uint32_t nx = g + gridDim.x;
@@ -696,9 +722,20 @@ __global__ __launch_bounds__(256, (sizeof(R) == 4 ? 4 : 1)) void k_batch_level(t
         if (more)
             batch_fetch<R, B>(pre, psi_base + nt.state_off, nbase, np->bm);
         for (int t = 0; t < bp->nstages; ++t) {
-            run_stage<R, B, 4, 256>(s, stages[bp->stage_begin + t], mats);
+            const BlkStage &stg = stages[bp->stage_begin + t];
+            if constexpr (MF) {
+                if (stg.mfma >= 0)
+                    run_stage_mfma<B, 256>(s, stg, Ml + 256 * stg.mfma);
+                else
+                    run_stage<R, B, 4, 256>(s, stg, mats);
+            } else {
+                run_stage<R, B, 4, 256>(s, stg, mats);
+            }
             lds_barrier();
         }
+        // issued before this block's stores, so the wait for the prefetch before the boundary covers them too
+        if (more)
+            mfetch(np);
         {
             uint64_t h[PB];
             batch_basis<PB>(h, bp->bm);
@@ -731,6 +768,7 @@ __global__ __launch_bounds__(256, (sizeof(R) == 4 ? 4 : 1)) void k_batch_level(t
         base = nbase;
         lds_barrier();  // every thread has read its stored values out of LDS
         batch_to_lds<R, B>(s, pre, base, bp->bm, (cur.flags & kBatchFirst) != 0, sbase);
+        mstore(bp);
         lds_barrier();
     }
 }
@@ -741,7 +779,8 @@ hipError_t batch_b(void *psi, double *probs, const BatchItem *items, int nitems,
                    int wg_per_cu, hipStream_t s)
 {
     using C2 = typename BT<R>::C2;
-    const size_t shm = sizeof(C2) << B;
+    // complex64: room for a pass's fused stage matrices next to the block
+    const size_t shm = (sizeof(C2) << B) + (sizeof(R) == 4 ? 256 * sizeof(C2) * kMaxMfmaStages : 0);
     static bool attr_set = false;
     if (!attr_set && shm > 65536) {
         hipError_t e = hipFuncSetAttribute((const void *)k_batch_level<R, B>,

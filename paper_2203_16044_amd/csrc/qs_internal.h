@@ -168,6 +168,7 @@ struct BatchPass {
     InsBits outer;  // block number -> base index (zeros at the local positions)
     BlockMap bm;
     int stage_begin, nstages;
+    BlkMfma mf;     // complex64: the pass's fused stage matrices (pool offsets in the batch's pool)
 };
 // one work item of a level: a whole small circuit in LDS, or one pass of a circuit held in HBM
 constexpr int kBatchFirst = 1;  // first pass: generate |0..0> instead of reading the state

@@ -1169,6 +1169,9 @@ QS_API int qs_batch_add(qs_batch *Bt, const qs_circuit *c)
         bp.bm = pp.bm;
         bp.stage_begin = s0 + pp.stage_begin;
         bp.nstages = pp.nstages;
+        bp.mf = pp.mf;
+        for (int i = 0; i < bp.mf.n; ++i)
+            bp.mf.off[i] += m0;
         Bt->passes.push_back(bp);
     }
     if (P->passes.empty() && c->n > Bt->b) {
