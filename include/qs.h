@@ -290,8 +290,9 @@ QS_API int qs_probe_rmw(void *buf, size_t bytes, void *hip_stream);
  * "block_async" 0/1: 12-qubit complex128 block passes double-buffer the next block in LDS with direct-to-LDS loads
  *               (default 0: one workgroup per CU fits, measured slower than two with register prefetch);
  * "mfma_stage_ops" complex64 block plans and batches created afterwards: in each pass, up to 4 of the 4-position
- *               stages with at least this many ops (the ones with the most) run as one fused 16 x 16 product on
- *               the FP32 matrix cores (0..8, default 3; 0: every stage op by op on the vector ALUs);
+ *               stages whose ops amount to at least this many 2-qubit ops' arithmetic (a k-qubit op counts
+ *               2^(k-2); the stages with the most) run as one fused 16 x 16 product on the FP32 matrix cores
+ *               (0..8, default 3; 0: every stage op by op on the vector ALUs);
  * "plan_beam"   beam width of pass formation for plans created afterwards (0..64, default 16): the local set of a
  *               pass grows one ready gate at a time, keeping the candidates that take the most gates; 0 selects
  *               the fewest-new-qubits greedy. Batches always plan with 4-position stages.

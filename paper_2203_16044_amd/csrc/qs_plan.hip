@@ -800,19 +800,25 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
             P->stages.push_back(stg);
         }
         pp.nstages = (int)P->stages.size() - pp.stage_begin;
-        // complex64: the pass's stages with the most ops (at least mfma_stage_ops; up to kMaxMfmaStages, the LDS
-        // they may take) become dense 16 x 16 products on the matrix cores. FP32 MFMA runs at twice the FP32 FMA
-        // rate, which pays for the denser matrix from about three ops on. The product of the stage's ops is formed
-        // here in FP64 (op o first), with stage index bit j <-> pos[j] as in the per-op masks.
+        // complex64: the pass's stages with the most arithmetic (at least that of mfma_stage_ops 2-qubit ops; up to
+        // kMaxMfmaStages, the LDS they may take) become dense 16 x 16 products on the matrix cores. A k-qubit op
+        // costs 2^(k+2) FMAs per amplitude op by op, the dense product 64 at twice the FP32 FMA rate of FP32 MFMA,
+        // which pays from about three 2-qubit ops' worth on. The product of the stage's ops is formed here in FP64
+        // (op o first), with stage index bit j <-> pos[j] as in the per-op masks.
         const int mfma_ops = qs_tunables().mfma_stage_ops;
         if (P->dtype == QS_C64 && W == 4 && mfma_ops > 0) {
+            auto weight = [&](int t) {  // FMAs per amplitude of stage t, op by op
+                const BlkStage &st = P->stages[pp.stage_begin + t];
+                int w = 0;
+                for (int o = 0; o < st.nops; ++o)
+                    w += 4 << __builtin_popcount((st.masks >> (4 * o)) & 15u);
+                return w;
+            };
             std::vector<int> pick;
             for (int t = 0; t < pp.nstages; ++t)
-                if (P->stages[pp.stage_begin + t].nops >= mfma_ops)
+                if (weight(t) >= 16 * mfma_ops)
                     pick.push_back(t);
-            std::stable_sort(pick.begin(), pick.end(), [&](int x, int y) {
-                return P->stages[pp.stage_begin + x].nops > P->stages[pp.stage_begin + y].nops;
-            });
+            std::stable_sort(pick.begin(), pick.end(), [&](int x, int y) { return weight(x) > weight(y); });
             if ((int)pick.size() > kMaxMfmaStages)
                 pick.resize(kMaxMfmaStages);
             std::sort(pick.begin(), pick.end());
