@@ -801,10 +801,10 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
         }
         pp.nstages = (int)P->stages.size() - pp.stage_begin;
         // complex64: the pass's stages with the most arithmetic (at least that of mfma_stage_ops 2-qubit ops; up to
-        // kMaxMfmaStages, the LDS they may take) become dense 16 x 16 products on the matrix cores. A k-qubit op
-        // costs 2^(k+2) FMAs per amplitude op by op, the dense product 64 at twice the FP32 FMA rate of FP32 MFMA,
-        // which pays from about three 2-qubit ops' worth on. The product of the stage's ops is formed here in FP64
-        // (op o first), with stage index bit j <-> pos[j] as in the per-op masks.
+        // kMaxMfmaStages, the LDS they may take) become dense 16 x 16 products on the matrix cores. Op by op a
+        // k-qubit op costs 2^(k+2) FMAs per amplitude; the dense product costs 64, but FP32 MFMA runs at twice the
+        // FP32 FMA rate, so it pays from about three 2-qubit ops' worth on. The product of the stage's ops is formed
+        // here in FP64 (op o first), with stage index bit j <-> pos[j] as in the per-op masks.
         const int mfma_ops = qs_tunables().mfma_stage_ops;
         if (P->dtype == QS_C64 && W == 4 && mfma_ops > 0) {
             auto weight = [&](int t) {  // FMAs per amplitude of stage t, op by op
