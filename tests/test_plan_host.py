@@ -41,6 +41,25 @@ def test_block_plan_cuts_passes_on_the_random_circuit():
     assert _gates_placed(p) == _gates_placed(f) == 1920
 
 
+def test_beam_search_beats_greedy_on_the_benchmark_circuit():
+    """The 32-qubit, 40-layer random SU(4)+U3 circuit with 12-qubit blocks and 3 always-local qubits: the beam
+    search over local sets (width 16) needs 56 passes, the fewest-new-qubits greedy 66; both place every gate."""
+    circ = C.su4_u3_random(n=32, seed=32, layers=40)
+    c = Circuit.from_ops(circ.n, circ.ops)
+    counts = {}
+    try:
+        for beam in (0, 16):
+            B.qs_set_tunable("plan_beam", beam)
+            p = Plan(c, "block", 12, 3)
+            counts[beam] = p.info()["passes"]
+            assert _gates_placed(p) == len(circ.ops)
+            p.close()
+    finally:
+        B.qs_set_tunable("plan_beam", 16)
+        c.close()
+    assert counts[16] <= 58 and counts[0] >= counts[16] + 6, counts
+
+
 def test_fused_swaps_stay_passes_of_their_own():
     circ = C.mixed_layers(n=16)
     c = Circuit.from_ops(circ.n, circ.ops)
