@@ -41,6 +41,28 @@ def test_batch_complex64_error(gpu):
     b.close()
 
 
+@pytest.mark.parametrize("dtype,tol", [("c128", 1e-12), ("c64", 1e-5)])
+def test_batch_edge_circuits(gpu, dtype, tol):
+    """Empty circuits inside and beyond the 12-qubit LDS block (the latter get one empty pass that generates |0..0>
+    and writes its probabilities), the smallest batched size (8 qubits), circuits of exactly the block size and one
+    qubit beyond it, GHZ across the block boundary (CNOT chain) and a single gate on the highest qubit."""
+    rng = np.random.Generator(np.random.PCG64(91))
+    x_top = C.Circuit(14, ops=[C.Op("dense", (13,), mat=C.x_gate())], name="x_top")
+    circs = [C.Circuit(8, name="empty8"), C.Circuit(14, name="empty14"), C._batch_circuit(rng, 8, 5, 0),
+             C._batch_circuit(rng, 12, 6, 1), C._batch_circuit(rng, 13, 6, 2), C.ghz(13), x_top,
+             C._batch_circuit(rng, 16, 3, 3)]
+    b = BT.Batch(circs, dtype, block_bits=12, low_bits=4, wg_per_cu=2)
+    b.run()
+    for i, circ in enumerate(circs):
+        P = b.probs(i)
+        assert P.shape == (1 << circ.n,)
+        assert np.max(np.abs(P - _oracle_probs(circ))) <= tol, (i, circ.name)
+    for i in (0, 1):
+        assert b.probs(i)[0] == 1.0 and not np.any(b.probs(i)[1:])
+    assert b.probs(6)[1 << 13] == 1.0
+    b.close()
+
+
 def test_graph_replays_match_eager(gpu):
     circs = C.serving_batch(count=40, seed=79, nmin=10, nmax=18, dmin=4, dmax=10)
     b = BT.Batch(circs, "c128")

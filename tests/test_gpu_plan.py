@@ -183,3 +183,11 @@ def test_plan_runs_on_three_qubits_pad_the_stage(gpu, dtype, tol):
         psi0 = psi0.astype(np.complex64).astype(np.complex128)
     got, _ = _run_plan(gpu, circ, "block", 12, 3, psi0, dtype)
     assert _maxerr(got, oracle.run(circ, psi0)) <= tol
+
+
+@pytest.mark.parametrize("mode,bits,low", [("block", 12, 4), ("fuse", 4, 0)])
+def test_plan_of_an_empty_circuit_leaves_the_state_unchanged(gpu, mode, bits, low):
+    psi0 = C.random_state(14, 92)
+    got, info = _run_plan(gpu, C.Circuit(14, name="empty"), mode, bits, low, psi0)
+    assert info["passes"] == 0
+    assert np.asarray(got, np.complex128).tobytes() == psi0.astype(np.complex128).tobytes()
