@@ -1045,7 +1045,6 @@ struct qs_batch {
     std::vector<int> nops;  // fused ops per circuit (schedule cost)
     std::vector<BatchPass> passes;
     std::vector<BlkStage> stages;
-    std::vector<BlkStageOp> sops;
     std::vector<double> pool;
     std::vector<BatchItem> items;      // all levels, level after level
     std::vector<int> level_begin;      // items of level k: [level_begin[k], level_begin[k + 1])
@@ -1167,7 +1166,7 @@ QS_API int qs_batch_add(qs_batch *Bt, const qs_circuit *c)
         bc.state_off = Bt->state_amps;
         Bt->state_amps += (uint64_t)1 << c->n;
     }
-    const int s0 = (int)Bt->stages.size(), o0 = (int)Bt->sops.size();
+    const int s0 = (int)Bt->stages.size();
     const uint32_t m0 = (uint32_t)Bt->pool.size();
     for (const PlanPass &pp : P->passes) {
         BatchPass bp{};
@@ -1193,13 +1192,8 @@ QS_API int qs_batch_add(qs_batch *Bt, const qs_circuit *c)
         bc.npass = 1;
     }
     for (BlkStage st : P->stages) {
-        st.op_begin += o0;
-        st.mat_base += m0;
+        st.mat_base += m0;  // op_begin keeps indexing the circuit plan's host op table, which the batch drops
         Bt->stages.push_back(st);
-    }
-    for (BlkStageOp so : P->sops) {
-        so.mat_off += m0;
-        Bt->sops.push_back(so);
     }
     Bt->pool.insert(Bt->pool.end(), P->pool.begin(), P->pool.end());
     int fused = 0;
