@@ -20,7 +20,6 @@ one persistent launch per pass level, autotuned, eager and graph-replayed, again
 """
 import argparse
 import json
-import math
 import os
 import sys
 import time

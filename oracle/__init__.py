@@ -14,7 +14,6 @@ Pinned by ``tests/test_oracle_pins.py`` (closed forms, brute force, invariants, 
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 from typing import Iterable, Optional
 

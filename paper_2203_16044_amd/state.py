@@ -5,7 +5,7 @@ stream; libqs does every step of the gate path. Nothing here computes on the sta
 """
 from __future__ import annotations
 
-from typing import Iterable, Optional
+from typing import Iterable
 
 import numpy as np
 

@@ -1,6 +1,5 @@
 """complex64 engine: FP32 state and FP32 MFMA / VALU arithmetic, FP64 reductions and renormalisation every 10
 layers; its error against the FP64 oracle is measured (and bounded) on the 24-qubit run of the 33-qubit family."""
-import math
 
 import numpy as np
 import pytest
