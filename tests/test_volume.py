@@ -101,3 +101,50 @@ def test_bench_traffic_is_null_once_the_kernel_sources_change(tmp_path):
     t = dict(bench.PMC_TRAFFIC["block_b12"], sources=["k.hip"])
     bench.PMC_TRAFFIC["block_b12"] = t
     assert bench.pmc_traffic("block_b12") is None
+
+
+def _load_bench():
+    import importlib.util
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_alg", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    return bench
+
+
+def test_bench_algorithmic_bytes_and_flops_by_hand():
+    """The roofline's algorithmic figures, counted by hand: every changed amplitude read and written once
+    (16 B each in complex128), 8 real flops per complex multiply-add (2^k of them per amplitude of a k-qubit
+    gate), 6 per amplitude for a diagonal; a controlled gate touches the 2^(n-c) amplitudes whose controls are 1;
+    a fused-swap moves all but the 2^(n-s) fixed points (Sec. III-D)."""
+    import circuits as C
+    bench = _load_bench()
+    n = 32
+    full = 2 * 16 * 2 ** n
+    assert bench._alg_bytes(C.Op("dense", (5,), mat=C.h()), n, 16) == full == 2 ** 37
+    assert bench._alg_bytes(C.Op("dense", (5,), mat=C.h()), n, 8) == 2 ** 36
+    assert bench._alg_bytes(C.Op("ctrl", (7,), controls=(3, 4), mat=C.x_gate()), n, 16) == full // 4
+    assert bench._alg_bytes(C.Op("fswap", (), p=0, q=20, s=6), n, 16) == full - full // 64
+    assert bench._alg_flops(C.Op("dense", (1, 9), mat=np.eye(4)), n) == 32 * 2 ** n
+    assert bench._alg_flops(C.Op("dense", (1, 2, 9), mat=np.eye(8)), n) == 64 * 2 ** n
+    assert bench._alg_flops(C.Op("diag", (3,), mat=np.ones(2)), n) == 6 * 2 ** n
+    assert bench._alg_flops(C.Op("ctrl", (7,), controls=(3,), mat=C.x_gate()), n) == 16 * 2 ** (n - 1)
+    assert bench._alg_flops(C.Op("fswap", (), p=0, q=20, s=6), n) == 0
+
+
+def test_planner_flops_per_amplitude_match_the_gate_count():
+    """The tuned roofline takes each block pass's flops from the planner (flops per amplitude x 2^n). On the
+    benchmark circuit every fused op is a 2-qubit op (an SU(4) with its neighbouring U3s folded in), so the plan's
+    flops per amplitude summed over passes equal 32 x the fused ops it reports."""
+    import circuits as C
+    from paper_2203_16044_amd import binding as B
+    from paper_2203_16044_amd.plan import Circuit, Plan
+    circ = C.su4_u3_random(n=32, seed=32, layers=40)
+    c = Circuit.from_ops(circ.n, circ.ops)
+    p = Plan(c, "block", 12, 3)
+    try:
+        tot = sum(B.qs_plan_features(p.h, i)[14] * 256 for i in range(p.info()["passes"]))
+        assert abs(tot - 32 * p.info()["fused_ops"]) <= 1e-3 * tot
+    finally:
+        p.close()
+        c.close()
