@@ -84,3 +84,44 @@ def test_binding_rejects_matrix_shape_mismatch():
         B.qs_apply_diag(1, (0,), np.ones(4))
     with pytest.raises(ValueError):
         B.qs_apply_controlled(1, (0,), (1, 2), np.eye(2))
+
+
+C_CONSUMER = r"""
+#include <stdio.h>
+#include <string.h>
+#include "qs.h"
+int main(void)
+{
+    qs_state *st = (qs_state *)0;
+    if (qs_set_tunable("no_such_tunable", 1) != QS_EINVAL || strstr(qs_last_error(), "no_such_tunable") == NULL)
+        return 1;
+    if (qs_set_tunable("plan_beam", 16) != QS_OK || qs_last_error()[0] != '\0')
+        return 2;
+    if (qs_alloc(&st, 0, QS_C128, NULL, NULL) != QS_EINVAL || st != NULL)
+        return 3;
+    if (qs_free(NULL) != QS_EINVAL)
+        return 4;
+    puts("c consumer ok");
+    return 0;
+}
+"""
+
+
+@pytest.mark.parametrize("compiler,std", [("gcc", "-std=c99"), ("g++", "-std=c++17")])
+def test_header_is_plain_c_and_links_from_c(tmp_path, compiler, std):
+    """A C (or C++) program includes qs.h under strict warnings, links libqs.so and gets status codes and thread-
+    local messages from host-only calls: the boundary needs no torch and no C++ on the caller's side."""
+    import shutil
+    import subprocess
+    if shutil.which(compiler) is None:
+        pytest.skip(f"{compiler} not installed")
+    src = tmp_path / ("consumer.c" if compiler == "gcc" else "consumer.cpp")
+    src.write_text(C_CONSUMER)
+    exe = tmp_path / "consumer"
+    libdir = os.path.dirname(B.LIB_PATH)
+    cmd = [compiler, std, "-Wall", "-Wextra", "-Werror", "-pedantic", "-I", os.path.join(ROOT, "include"), str(src),
+           "-o", str(exe), B.LIB_PATH, f"-Wl,-rpath,{libdir}"]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 0 and "c consumer ok" in r.stdout, (r.returncode, r.stdout, r.stderr)
