@@ -119,3 +119,19 @@ def test_batch_host_validation():
     assert info["levels"] == 0  # not finalized
     assert info["circuits"] == 6 and info["prob_count"] == sum(1 << c.n for c in C.serving_batch(count=6, nmax=15))
     B.qs_batch_free(b)
+
+
+@pytest.mark.parametrize("mode,bits,low,dtype", [("block", 12, 3, "c128"), ("block", 12, 4, "c64"), ("fuse", 5, 0, "c128")])
+def test_planning_is_deterministic(mode, bits, low, dtype):
+    """The same circuit planned twice gives the same passes and the same cost-model features, pass by pass."""
+    circ = C.su4_u3_random(n=24, seed=5, layers=12)
+    c = Circuit.from_ops(circ.n, circ.ops)
+    plans = [Plan(c, mode, bits, low, dtype) for _ in range(2)]
+    try:
+        assert plans[0].passes() == plans[1].passes()
+        for i in range(plans[0].info()["passes"]):
+            assert B.qs_plan_features(plans[0].h, i).tobytes() == B.qs_plan_features(plans[1].h, i).tobytes()
+    finally:
+        for p in plans:
+            p.close()
+        c.close()
