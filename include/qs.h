@@ -209,6 +209,14 @@ QS_API int qs_plan_info(const qs_plan *p, int *npasses, int *nblock, int *ndense
  * and circuit gates it carries. */
 QS_API int qs_plan_pass_info(const qs_plan *p, int i, int *type, int *nqubits, int64_t *qmask, int *nops,
                              int *ngates);
+/* The circuit gates pass i carries, in the order the pass applies them (inside a block pass: stage by stage, each
+ * fused op's gates in circuit order). A gate is named by its position among the operations the circuit recorded
+ * (every qs_circuit_add_* call that returned QS_OK, except fused-swaps with s = 0, which record nothing). Writes
+ * min(cap, count) indices to gates (may be NULL when cap = 0) and the full count to *count (nullable). Over all
+ * passes every recorded gate appears exactly once; two gates that share a qubit keep their circuit order (Sec.
+ * II-A: a circuit is an ordered product of gates; gates on disjoint qubits commute). Host only.
+ * QS_EINVAL for a NULL plan, a negative cap, gates NULL with cap > 0, or i out of range. */
+QS_API int qs_plan_pass_gates(const qs_plan *p, int i, int *gates, int cap, int *count);
 QS_API int qs_plan_free(qs_plan *p);
 
 /* ---- learned cost model (an MLP trained on the simulator's own pass timings) ----

@@ -74,6 +74,7 @@ SIGNATURES = {
     "qs_plan_run_range": [_P, _P, _I, _I],
     "qs_plan_info": [_P, _IP, _IP, _IP, _IP, _IP],
     "qs_plan_pass_info": [_P, _I, _IP, _IP, ctypes.POINTER(ctypes.c_int64), _IP, _IP],
+    "qs_plan_pass_gates": [_P, _I, _IP, _I, _IP],
     "qs_plan_free": [_P],
     "qs_plan_features": [_P, _I, ctypes.POINTER(ctypes.c_float)],
     "qs_batch_create": [ctypes.POINTER(_P), _I, _I, _I, _I, _P],
@@ -330,6 +331,14 @@ def qs_plan_pass_info(p: int, i: int):
     _check(lib().qs_plan_pass_info(p, int(i), ctypes.byref(t), ctypes.byref(nq), ctypes.byref(m), ctypes.byref(no),
                                    ctypes.byref(ng)), "qs_plan_pass_info")
     return {"type": t.value, "nqubits": nq.value, "qmask": m.value, "nops": no.value, "ngates": ng.value}
+
+
+def qs_plan_pass_gates(p: int, i: int) -> list:
+    cnt = ctypes.c_int()
+    _check(lib().qs_plan_pass_gates(p, int(i), None, 0, ctypes.byref(cnt)), "qs_plan_pass_gates")
+    buf = (ctypes.c_int * max(cnt.value, 1))()
+    _check(lib().qs_plan_pass_gates(p, int(i), buf, cnt.value, ctypes.byref(cnt)), "qs_plan_pass_gates")
+    return list(buf[:cnt.value])
 
 
 def qs_plan_free(p: int) -> None:

@@ -36,7 +36,8 @@ struct PG {
     int kind = 0;
     std::vector<int> q;
     std::vector<cd> m;
-    int raw = -1;  // index of the raw op
+    int raw = -1;              // index of the raw op
+    std::vector<int> members;  // a fused op: the circuit gates it carries, in the order it applies them
 };
 
 std::vector<cd> embed(const PG &g, const std::vector<int> &Q)
@@ -129,7 +130,8 @@ struct PlanPass {
     size_t mat_off = 0;      // offset in the matrix pool (real elements)
     int p = 0, q = 0, s = 0;
     int raw = -1;
-    int ngates = 0;  // circuit gates carried by the pass
+    int ngates = 0;          // circuit gates carried by the pass
+    std::vector<int> order;  // their raw-op indices, in the order the pass applies them
 };
 
 struct qs_plan {
@@ -345,20 +347,24 @@ std::vector<PG> fuse_pass(const qs_circuit &c, const std::vector<int> &gates)
         for (int h = (int)out.size() - 1; h >= 0; --h) {
             if (subset(g.q, out[h].q)) {
                 out[h].m = matmul(embed(g, out[h].q), out[h].m, 1 << out[h].q.size());
+                out[h].members.push_back(gi);
                 merged = true;
                 break;
             }
             if (intersects(g.q, out[h].q))
                 break;
         }
-        if (!merged)
+        if (!merged) {
             out.push_back(g);
+            out.back().members.assign(1, gi);
+        }
     }
     for (size_t i = 0; i < out.size();) {
         bool moved = false;
         for (size_t j = i + 1; j < out.size(); ++j) {
             if (subset(out[i].q, out[j].q)) {
                 out[j].m = matmul(out[j].m, embed(out[i], out[j].q), 1 << out[j].q.size());
+                out[j].members.insert(out[j].members.begin(), out[i].members.begin(), out[i].members.end());
                 out.erase(out.begin() + i);
                 moved = true;
                 break;
@@ -664,6 +670,7 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
         pp.ngates = (int)gs.size();
         if (L.empty()) {  // a single non-blockable gate
             const PG &g = c->gates[gs[0]];
+            pp.order.assign(1, g.raw);
             if (g.kind == 1) {
                 pp.type = 2;
                 const RawOp &r = c->raw[g.raw];
@@ -686,8 +693,10 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
             blk.m.assign((size_t)D * D, cd(0, 0));
             for (int a = 0; a < D; ++a)
                 blk.m[(size_t)a * D + a] = cd(1, 0);
-            for (int gi : gs)
+            for (int gi : gs) {
                 blk.m = matmul(embed(c->gates[gi], L), blk.m, D);
+                pp.order.push_back(c->gates[gi].raw);
+            }
             make_dense_pass(P, blk, pp);
             P->nfused_ops += 1;
             P->passes.push_back(std::move(pp));
@@ -800,6 +809,10 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
             P->stages.push_back(stg);
         }
         pp.nstages = (int)P->stages.size() - pp.stage_begin;
+        for (const std::vector<int> &members : stage_members)
+            for (int i : members)
+                for (int gi : fused[i].members)
+                    pp.order.push_back(c->gates[gi].raw);
         // complex64: the pass's stages with the most arithmetic (at least that of mfma_stage_ops 2-qubit ops; up to
         // kMaxMfmaStages, the LDS they may take) become dense 16 x 16 products on the matrix cores. Op by op a
         // k-qubit op costs 2^(k+2) FMAs per amplitude; the dense product costs 64, but FP32 MFMA runs at twice the
@@ -965,6 +978,20 @@ QS_API int qs_plan_pass_info(const qs_plan *P, int i, int *type, int *nqubits, i
         *nops = pp.type == 0 ? pp.nops : 1;
     if (ngates)
         *ngates = pp.ngates;
+    return QS_OK;
+}
+
+QS_API int qs_plan_pass_gates(const qs_plan *P, int i, int *gates, int cap, int *count)
+{
+    qs_clear_error();
+    if (!P || i < 0 || i >= (int)P->passes.size() || cap < 0 || (cap > 0 && !gates))
+        return qs_fail(QS_EINVAL, "qs_plan_pass_gates: NULL plan or output, negative capacity or pass index out of "
+                                  "range");
+    const std::vector<int> &o = P->passes[i].order;
+    for (int j = 0; j < cap && j < (int)o.size(); ++j)
+        gates[j] = o[j];
+    if (count)
+        *count = (int)o.size();
     return QS_OK;
 }
 

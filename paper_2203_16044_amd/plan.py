@@ -67,6 +67,10 @@ class Plan:
     def passes(self):
         return [B.qs_plan_pass_info(self.h, i) for i in range(self.info()["passes"])]
 
+    def pass_gates(self):
+        """Per pass, the indices of the circuit operations it carries, in the order it applies them."""
+        return [B.qs_plan_pass_gates(self.h, i) for i in range(self.info()["passes"])]
+
     def run(self, state, begin: int = 0, end: int = None) -> None:
         if begin == 0 and end is None:
             B.qs_plan_run(state.h, self.h)

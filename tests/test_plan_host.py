@@ -1,4 +1,5 @@
 """Planner (host C++ in libqs) checks that need no GPU: every gate placed once, option validation."""
+import numpy as np
 import pytest
 
 import circuits as C
@@ -135,3 +136,81 @@ def test_planning_is_deterministic(mode, bits, low, dtype):
         for p in plans:
             p.close()
         c.close()
+
+
+def _op_qubits(op):
+    if op.kind == "fswap":
+        return set(range(op.p, op.p + op.s)) | set(range(op.q, op.q + op.s))
+    return set(op.targets) | set(op.controls)
+
+
+def _checked_order(circ, plan):
+    """The plan's gate order: every op exactly once, the ops on each qubit in circuit order (so the reordering only
+    exchanges gates on disjoint qubits, which commute), block-pass gates inside the pass's local set."""
+    per_pass = plan.pass_gates()
+    order = [g for gs in per_pass for g in gs]
+    assert sorted(order) == list(range(len(circ.ops)))
+    for q in range(circ.n):
+        seq = [i for i in order if q in _op_qubits(circ.ops[i])]
+        assert seq == sorted(seq), f"qubit {q}"
+    for info, gs in zip(plan.passes(), per_pass):
+        assert len(gs) == info["ngates"]
+        if info["type"] == 0:
+            for i in gs:
+                assert all((info["qmask"] >> q) & 1 for q in _op_qubits(circ.ops[i])), (i, circ.ops[i].kind)
+    return order
+
+
+@pytest.mark.parametrize("beam", [0, 4, 16, 64])
+@pytest.mark.parametrize("mode,bits,low,width", [("block", 8, 0, 4), ("block", 10, 3, 4), ("block", 12, 4, 4),
+                                                 ("block", 12, 3, 3), ("block", 13, 3, 4), ("fuse", 3, 0, 4),
+                                                 ("fuse", 6, 0, 4)])
+def test_plan_gate_order_reproduces_the_circuit(beam, mode, bits, low, width):
+    """The order in which a plan applies the gates, replayed gate by gate on the oracle, gives the circuit's own
+    state (up to rounding: only gates on disjoint qubits change places), for every beam width."""
+    import oracle
+    circs = [C.random_circuit(13, seed=600 + beam, num_ops=160, kmax=4), C.mixed_layers(n=14, seed=7, layers=4),
+             C.su4_u3_random(n=14, seed=8, layers=8)]
+    try:
+        B.qs_set_tunable("plan_beam", beam)
+        B.qs_set_tunable("block_stage_width", width)
+        for circ in circs:
+            c = Circuit.from_ops(circ.n, circ.ops)
+            p = Plan(c, mode, bits, low)
+            order = _checked_order(circ, p)
+            p.close()
+            c.close()
+            psi0 = C.random_state(circ.n, 3)
+            ref = oracle.run(circ, psi0)
+            got = oracle.run(circ, psi0, ops=[circ.ops[i] for i in order])
+            assert np.max(np.abs(got - ref)) <= 1e-12, circ.name
+    finally:
+        B.qs_set_tunable("plan_beam", 16)
+        B.qs_set_tunable("block_stage_width", 4)
+
+
+@pytest.mark.parametrize("beam", [16, 64])
+def test_benchmark_plan_gate_order(beam):
+    """The 32-qubit benchmark circuit's plans (12-qubit blocks, 3 low qubits): the same structural checks."""
+    circ = C.su4_u3_random(n=32, seed=32, layers=40)
+    c = Circuit.from_ops(circ.n, circ.ops)
+    try:
+        B.qs_set_tunable("plan_beam", beam)
+        p = Plan(c, "block", 12, 3)
+        _checked_order(circ, p)
+        p.close()
+    finally:
+        B.qs_set_tunable("plan_beam", 16)
+        c.close()
+
+
+def test_pass_gates_validates():
+    circ = C.u3_cnot_layers(n=12)
+    c = Circuit.from_ops(12, circ.ops)
+    p = Plan(c, "block", 10, 3)
+    with pytest.raises(B.QSError):
+        B.qs_plan_pass_gates(p.h, p.info()["passes"])
+    with pytest.raises(B.QSError):
+        B.qs_plan_pass_gates(p.h, -1)
+    p.close()
+    c.close()
