@@ -125,3 +125,17 @@ def test_header_is_plain_c_and_links_from_c(tmp_path, compiler, std):
     assert r.returncode == 0, r.stderr
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=60)
     assert r.returncode == 0 and "c consumer ok" in r.stdout, (r.returncode, r.stdout, r.stderr)
+
+
+def test_product_path_never_loads_the_oracle():
+    """Importing the package and planning a circuit through the library loads nothing from oracle/ (the oracle is
+    test infrastructure; the product path has no CPU fallback)."""
+    import subprocess
+    import sys
+    code = ("import sys; import paper_2203_16044_amd as qs; from paper_2203_16044_amd import plan, batch, costmodel; "
+            "import circuits as C; c = plan.Circuit.from_ops(12, C.u3_cnot_layers(n=12).ops); "
+            "p = plan.Plan(c, 'block', 10, 3); p.pass_gates(); p.close(); c.close(); "
+            "bad = [m for m in sys.modules if m == 'oracle' or m.startswith('oracle.')]; "
+            "print('loaded:', bad); sys.exit(1 if bad else 0)")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr

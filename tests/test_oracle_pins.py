@@ -349,3 +349,16 @@ def test_oracle_rejects_matrix_shape_mismatch():
         oracle.apply_controlled(psi, [2], [0, 1], np.eye(2))
     with pytest.raises(ValueError):
         oracle.apply_diag(psi, [0], np.ones(4))
+
+
+def test_seeded_generators_are_deterministic():
+    """The shared input generators give bit-identical circuits and states for the same seed (both sides of every
+    comparison draw from them), and different ones for another seed."""
+    a, b = C.su4_u3_random(n=10, seed=3, layers=4), C.su4_u3_random(n=10, seed=3, layers=4)
+    assert [(o.kind, o.targets, o.mat.tobytes()) for o in a.ops] == [(o.kind, o.targets, o.mat.tobytes()) for o in b.ops]
+    c = C.su4_u3_random(n=10, seed=4, layers=4)
+    assert [o.mat.tobytes() for o in a.ops] != [o.mat.tobytes() for o in c.ops]
+    assert C.random_state(9, 5).tobytes() == C.random_state(9, 5).tobytes()
+    x, y = C.serving_batch(count=6, seed=9, nmin=10, nmax=12, dmin=2, dmax=3), C.serving_batch(count=6, seed=9, nmin=10, nmax=12, dmin=2, dmax=3)
+    assert [len(u.ops) for u in x] == [len(v.ops) for v in y]
+    assert all(p.mat.tobytes() == q.mat.tobytes() for u, v in zip(x, y) for p, q in zip(u.ops, v.ops))
