@@ -416,6 +416,34 @@ int run_raw(qs_state *st, const RawOp &r)
     }
 }
 
+// Each buffer is recorded in the plan as soon as it exists, so upload() can release whatever a failed attempt left.
+int upload_tables(qs_plan *P)
+{
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(P->stages.size(), 1) * sizeof(BlkStage));
+    if (e != hipSuccess)
+        return qs_hip_fail(e, "hipMalloc(plan stages)");
+    P->dstages = static_cast<BlkStage *>(p);
+    if (!P->stages.empty())
+        QS_HIP(hipMemcpy(P->dstages, P->stages.data(), P->stages.size() * sizeof(BlkStage), hipMemcpyHostToDevice));
+    const size_t npool = std::max<size_t>(P->pool.size(), 2);
+    const size_t esz = P->dtype == QS_C128 ? sizeof(double) : sizeof(float);
+    p = nullptr;
+    e = hipMalloc(&p, npool * esz);
+    if (e != hipSuccess)
+        return qs_hip_fail(e, "hipMalloc(plan matrices)");
+    P->dpool = p;
+    if (P->dtype == QS_C128) {
+        if (!P->pool.empty())
+            QS_HIP(hipMemcpy(P->dpool, P->pool.data(), P->pool.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> f(P->pool.begin(), P->pool.end());
+        if (!f.empty())
+            QS_HIP(hipMemcpy(P->dpool, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    return QS_OK;
+}
+
 int upload(qs_plan *P)
 {
     int dev = 0;
@@ -425,19 +453,14 @@ int upload(qs_plan *P)
             return QS_OK;
         return qs_fail(QS_EINVAL, "qs_plan_run: plan was uploaded to device %d, current device is %d", P->dev, dev);
     }
-    QS_HIP(hipMalloc((void **)&P->dstages, std::max<size_t>(P->stages.size(), 1) * sizeof(BlkStage)));
-    if (!P->stages.empty())
-        QS_HIP(hipMemcpy(P->dstages, P->stages.data(), P->stages.size() * sizeof(BlkStage), hipMemcpyHostToDevice));
-    const size_t npool = std::max<size_t>(P->pool.size(), 2);
-    if (P->dtype == QS_C128) {
-        QS_HIP(hipMalloc(&P->dpool, npool * sizeof(double)));
-        if (!P->pool.empty())
-            QS_HIP(hipMemcpy(P->dpool, P->pool.data(), P->pool.size() * sizeof(double), hipMemcpyHostToDevice));
-    } else {
-        std::vector<float> f(P->pool.begin(), P->pool.end());
-        QS_HIP(hipMalloc(&P->dpool, npool * sizeof(float)));
-        if (!f.empty())
-            QS_HIP(hipMemcpy(P->dpool, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+    if (int rc = upload_tables(P)) {  // leave nothing half-uploaded: a later run starts over
+        if (P->dstages)
+            (void)hipFree(P->dstages);
+        if (P->dpool)
+            (void)hipFree(P->dpool);
+        P->dstages = nullptr;
+        P->dpool = nullptr;
+        return rc;
     }
     P->dev = dev;
     return QS_OK;
@@ -1089,6 +1112,8 @@ struct qs_batch {
 };
 
 namespace {
+void batch_free_device(qs_batch *Bt);
+
 void batch_release(qs_batch *Bt)
 {
     if (!Bt)
@@ -1098,19 +1123,73 @@ void batch_release(qs_batch *Bt)
         (void)hipGraphExecDestroy(Bt->exec);
     if (Bt->graph)
         (void)hipGraphDestroy(Bt->graph);
+    batch_free_device(Bt);
+    delete Bt;
+}
+
+// *dst is set only once the table is on the device; on failure nothing stays allocated.
+template <class T> int upload_vec(T **dst, const std::vector<T> &v)
+{
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<size_t>(v.size(), 1) * sizeof(T));
+    if (e != hipSuccess)
+        return qs_hip_fail(e, "hipMalloc(batch table)");
+    if (!v.empty() && (e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice)) != hipSuccess) {
+        (void)hipFree(p);
+        return qs_hip_fail(e, "hipMemcpy(batch table)");
+    }
+    *dst = static_cast<T *>(p);
+    return QS_OK;
+}
+
+// State and probability slices, then the tables. Each buffer is recorded in the batch as soon as it exists, so
+// batch_free_device releases whatever a failed attempt left.
+int batch_upload(qs_batch *Bt)
+{
+    const size_t esz = Bt->dtype == QS_C128 ? 16 : 8;
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, std::max<uint64_t>(Bt->state_amps, 1) * esz);
+    if (e != hipSuccess)
+        return qs_hip_fail(e, "hipMalloc(batch states)");
+    Bt->psi = p;
+    p = nullptr;
+    e = hipMalloc(&p, std::max<uint64_t>(Bt->prob_count, 1) * sizeof(double));
+    if (e != hipSuccess)
+        return qs_hip_fail(e, "hipMalloc(batch probabilities)");
+    Bt->probs = static_cast<double *>(p);
+    if (int rc = upload_vec(&Bt->ditems, Bt->items))
+        return rc;
+    if (int rc = upload_vec(&Bt->dpasses, Bt->passes))
+        return rc;
+    if (int rc = upload_vec(&Bt->dstages, Bt->stages))
+        return rc;
+    if (Bt->dtype == QS_C128) {
+        double *d = nullptr;
+        if (int rc = upload_vec(&d, Bt->pool))
+            return rc;
+        Bt->dmats = d;
+    } else {
+        std::vector<float> f(Bt->pool.begin(), Bt->pool.end());
+        float *d = nullptr;
+        if (int rc = upload_vec(&d, f))
+            return rc;
+        Bt->dmats = d;
+    }
+    return QS_OK;
+}
+
+void batch_free_device(qs_batch *Bt)
+{
     void *bufs[] = {Bt->psi, Bt->probs, Bt->ditems, Bt->dpasses, Bt->dstages, Bt->dmats};
     for (void *p : bufs)
         if (p)
             (void)hipFree(p);
-    delete Bt;
-}
-
-template <class T> int upload_vec(T **dst, const std::vector<T> &v)
-{
-    QS_HIP(hipMalloc((void **)dst, std::max<size_t>(v.size(), 1) * sizeof(T)));
-    if (!v.empty())
-        QS_HIP(hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-    return QS_OK;
+    Bt->psi = nullptr;
+    Bt->probs = nullptr;
+    Bt->ditems = nullptr;
+    Bt->dpasses = nullptr;
+    Bt->dstages = nullptr;
+    Bt->dmats = nullptr;
 }
 }  // namespace
 
@@ -1285,26 +1364,9 @@ QS_API int qs_batch_finalize(qs_batch *Bt)
         Bt->level_blocks.push_back((uint32_t)blk);
     }
     Bt->level_begin.push_back((int)Bt->items.size());
-    const size_t esz = Bt->dtype == QS_C128 ? 16 : 8;
-    QS_HIP(hipMalloc(&Bt->psi, std::max<uint64_t>(Bt->state_amps, 1) * esz));
-    QS_HIP(hipMalloc((void **)&Bt->probs, std::max<uint64_t>(Bt->prob_count, 1) * sizeof(double)));
-    if (int rc = upload_vec(&Bt->ditems, Bt->items))
+    if (int rc = batch_upload(Bt)) {  // leave nothing allocated: a later finalize starts over
+        batch_free_device(Bt);
         return rc;
-    if (int rc = upload_vec(&Bt->dpasses, Bt->passes))
-        return rc;
-    if (int rc = upload_vec(&Bt->dstages, Bt->stages))
-        return rc;
-    if (Bt->dtype == QS_C128) {
-        double *d = nullptr;
-        if (int rc = upload_vec(&d, Bt->pool))
-            return rc;
-        Bt->dmats = d;
-    } else {
-        std::vector<float> f(Bt->pool.begin(), Bt->pool.end());
-        float *d = nullptr;
-        if (int rc = upload_vec(&d, f))
-            return rc;
-        Bt->dmats = d;
     }
     Bt->finalized = true;
     return QS_OK;
