@@ -199,7 +199,8 @@ typedef struct {
  * falls back to FUSE mode with 4-qubit blocks. Errors: QS_EINVAL for out-of-range options. */
 QS_API int qs_plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts);
 /* Enqueue every pass (or passes [begin, end)) on the state's stream. The first run uploads the plan's matrices
- * to the current device (synchronous copy). QS_EINVAL if n or dtype differ from the plan's. */
+ * to the current device (synchronous copy; if it fails, nothing stays allocated and a later run retries).
+ * QS_EINVAL if n or dtype differ from the plan's, or if the plan was uploaded to another device. */
 QS_API int qs_plan_run(qs_state *st, qs_plan *p);
 QS_API int qs_plan_run_range(qs_state *st, qs_plan *p, int begin, int end);
 /* Pass counts: all passes, LDS block passes, dense passes, others (fused-swaps, large controlled gates), and the
@@ -265,7 +266,8 @@ QS_API int qs_batch_set_launch(qs_batch *b, int wg_per_cu);
 /* Plan and append a circuit (host only). QS_EUNSUPPORTED for circuits outside the batch's scope. */
 QS_API int qs_batch_add(qs_batch *b, const qs_circuit *c);
 /* Build the pass levels, allocate state and probability slices, upload the tables (synchronous). QS_EUNSUPPORTED if
- * one level would exceed 2^31 blocks. */
+ * one level would exceed 2^31 blocks; QS_ENOMEM (or QS_EDEVICE) if an allocation or copy fails, in which case
+ * nothing stays allocated and a later call retries. */
 QS_API int qs_batch_finalize(qs_batch *b);
 /* Enqueue the whole batch (one launch per level) on the batch's stream. use_graph != 0 captures the launches once
  * into a HIP graph (kernel nodes only) and replays it on later calls. Finalizes the batch if needed. */
