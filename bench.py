@@ -197,11 +197,10 @@ def cpu_baseline(circ, budget_s, torch):
 def bench_c64(head_rate, steps, torch):
     """complex64 engine: the 33-qubit circuit of the same family (64 GiB state, as large as the 32-qubit complex128
     one) through the block plan with FP64 renormalisation after layers 10/20/30/40, and its error on the 24-qubit
-    run against the complex128 path."""
-    import numpy as np
-
+    run against the complex128 path (which matches the FP64 oracle to 1e-12 in the tests)."""
     import circuits as C
     import paper_2203_16044_amd as qs
+    from paper_2203_16044_amd.metrics import state_error
     from paper_2203_16044_amd.plan import Circuit, Plan, SegmentedPlan
 
     circ = C.su4_u3_renorm()
@@ -237,9 +236,7 @@ def bench_c64(head_rate, steps, torch):
     c = Circuit.from_ops(e.n, e.ops)
     p = Plan(c, "block", 12, 4, "c128")
     p.run(b)
-    x, y = a.get().astype(np.complex128), b.get()
-    infid = max(0.0, 1.0 - abs(np.vdot(y, x)) ** 2 / (np.vdot(x, x).real * np.vdot(y, y).real))
-    maxd = float(np.max(np.abs(x - y)))
+    infid, maxd = state_error(a.get(), b.get())
     for h in (sp, p, c, a, b):
         h.close()
     return {"workload": f"random SU(4)+U3 circuit, n={circ.n}, 40 layers, {len(circ.ops)} gates, complex64, "

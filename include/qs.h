@@ -90,8 +90,11 @@ QS_API int qs_apply_gate(qs_state *st, const int *targets, int k, const double *
 /*
  * qs_apply_diag -- diagonal gate: a_i <- d[a(i)] a_i, a(i) = the target bits of i in targets order
  * (Eq. 4 with a diagonal U; RZ, CZ, controlled phases). 1 <= k <= QS_MAX_DIAG_K.
- *   d  2^k complex FP64, interleaved. Entries exactly 1 leave their amplitudes untouched (not even read or
- *      written); entries exactly -1 are a sign flip (exact).
+ *   d  2^k complex FP64, interleaved. Entries exactly 1 leave their amplitudes' values bit-identical; entries
+ *      exactly -1 are a sign flip (exact). For complex128 states, amplitudes whose entry is exactly 1 are not
+ *      accessed at all. For complex64 states with k <= 2, memory is accessed in 16-byte pairs of adjacent
+ *      amplitudes: a pair with one non-unit entry is read and both amplitudes are rewritten, the one with entry 1
+ *      unchanged; a pair whose two entries are 1 is not accessed.
  * Errors: as qs_apply_gate.
  */
 QS_API int qs_apply_diag(qs_state *st, const int *targets, int k, const double *d);
@@ -107,8 +110,13 @@ QS_API int qs_apply_controlled(qs_state *st, const int *controls, int c, const i
 
 /*
  * qs_fused_swap -- fused_swap(p, q, s) of Sec. III-D, Listing 1: swap(p+i, q+i) for 0 <= i < s, in place:
- * psi'[sigma(i)] = psi[i] where sigma exchanges bit p+j with bit q+j. Pure moves, bit-exact; the
- * 2^(n-s) fixed points are neither read nor written. s = 0 is a no-op; p and q may come in either order.
+ * psi'[sigma(i)] = psi[i] where sigma exchanges bit p+j with bit q+j. Pure moves, bit-exact; the 2^(n-s)
+ * fixed points (sigma(i) = i) keep their values bit-identical. Whether a fixed point is accessed depends on the
+ * form chosen for the run length 2^min(p,q) and the tile size: runs of at least 256 bytes are exchanged
+ * directly, and short runs in tiles too small for LDS staging one index pair at a time, neither accessing fixed
+ * points; the LDS tile forms read the fixed points that share a tile with moved amplitudes, and the wide-row form
+ * (2^s x 2^s tiles of runs up to 32 KiB) also writes them back unchanged. s = 0 is a no-op; p and q may come in
+ * either order.
  * Errors: QS_EINVAL if s < 0, p < 0, q < 0, p+s > n, q+s > n, or the ranges overlap (|p - q| < s).
  */
 QS_API int qs_fused_swap(qs_state *st, int p, int q, int s);

@@ -294,6 +294,29 @@ def test_probs_norm_is_compensated_sum():
     assert abs(nrm - math.fsum(P.tolist())) <= 2e-16 * nrm
 
 
+def test_scale_closed_forms():
+    """a_i <- f a_i (the renormalisation step): f = -1 negates every component exactly (signed zeros too), powers of
+    two scale exactly, and f = 1/sqrt(norm) leaves the norm 1 (Sec. II-A: sum |a_i|^2 = 1)."""
+    psi = C.random_state(9, 11) * 3.0
+    psi[5] = complex(0.0, -0.0)
+    a = psi.copy()
+    oracle.scale(a, -1.0)
+    assert np.array_equal(a.view(np.float64), -psi.view(np.float64))
+    assert np.signbit(a.view(np.float64)[10]) and not np.signbit(a.view(np.float64)[11])
+    for f in (0.5, 4.0, 2.0 ** -30):
+        a = psi.copy()
+        oracle.scale(a, f)
+        assert np.array_equal(a.view(np.float64), psi.view(np.float64) * f)
+    _, nrm = oracle.probs(psi)
+    a = psi.copy()
+    oracle.scale(a, 1.0 / math.sqrt(nrm))
+    assert abs(oracle.probs(a)[1] - 1.0) < 1e-14
+    b = C.random_state(6, 12)
+    c = b.copy()
+    oracle.scale(c, 0.3)
+    assert np.max(np.abs(c - 0.3 * b)) <= 1e-16  # each component rounded once
+
+
 # ------------------------------------------------------------------------------------------------ planted mistakes
 
 def test_pins_catch_planted_mistakes():
