@@ -91,6 +91,68 @@ def test_product_state_sampled_amplitudes(gpu, big_state, how):
     assert _amps(st, sig).tobytes() == before.tobytes()
 
 
+def _product_pair_circuit(n, seed, layers):
+    """The benchmark circuit's structure (per layer a random qubit pairing with a dense 2-qubit gate on every pair, then
+    U3 on every qubit) with every 2-qubit gate a Kronecker product V (x) W of random U3s: the plans see the same dense
+    4 x 4 matrices on the same qubit pairs, yet the state stays a product state, so every amplitude is known in closed
+    form (the product over qubits of column 0 of that qubit's accumulated 2 x 2 factor) and is not invariant under
+    any exchange of blocks."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    fac = [np.eye(2, dtype=np.complex128) for _ in range(n)]
+    ops = []
+    for L in range(1, layers + 1):
+        perm = rng.permutation(n)
+        for j in range(n // 2):
+            a, b = int(perm[2 * j]), int(perm[2 * j + 1])
+            W, V = (C.u3(*rng.uniform(0, 2 * math.pi, 3)) for _ in range(2))
+            ops.append(C.Op("dense", (a, b), mat=np.kron(V, W), layer=L))  # matrix bit 0 <-> a (W), bit 1 <-> b (V)
+            fac[a], fac[b] = W @ fac[a], V @ fac[b]
+        for q in range(n):
+            U = C.u3(*rng.uniform(0, 2 * math.pi, 3))
+            ops.append(C.Op("dense", (q,), mat=U, layer=L))
+            fac[q] = U @ fac[q]
+    return C.Circuit(n, ops=ops, name="product_pairs"), fac
+
+
+def _learned_shape():
+    """The block shape the benchmark runs: the learned cost model's choice for its 32-qubit circuit (greedy 12/4
+    without weights)."""
+    import os
+    from paper_2203_16044_amd import costmodel as CM
+    if not os.path.exists(CM.WEIGHTS):
+        return ("block", 12, 4)
+    circ = C.su4_u3_random(n=N, seed=32, layers=40)
+    cc = Circuit.from_ops(N, circ.ops)
+    model = CM.CostModel.load()
+    lp, learned, _ = CM.choose_plan(cc, "c128", model)
+    lp.close()
+    model.close()
+    cc.close()
+    return learned or ("block", 12, 4)
+
+
+@pytest.mark.parametrize("shape", [("block", 12, 3), ("block", 12, 4), ("block", 13, 3), "learned"])
+def test_benchmark_structured_product_circuit_sampled_amplitudes(gpu, big_state, shape):
+    """40 layers of the benchmark's pairing structure at 32 qubits through the benchmark's plan shapes (the persistent
+    block pipeline walks 32 blocks per workgroup per pass): 4,096 sampled amplitudes against the closed form."""
+    mode, bits, low = _learned_shape() if shape == "learned" else shape
+    circ, fac = _product_pair_circuit(N, 3200, 40)
+    st = big_state
+    st.init_zero()
+    c = Circuit.from_ops(N, circ.ops)
+    p = Plan(c, mode, bits, low)
+    assert p.info()["passes"] >= 20
+    p.run(st)
+    p.close()
+    c.close()
+    idx = _samples(N, 4096, 5)
+    ref = np.ones(len(idx), dtype=np.complex128)
+    for q in range(N):
+        ref *= np.where((idx >> q) & 1, fac[q][1, 0], fac[q][0, 0])
+    assert np.max(np.abs(_amps(st, idx) - ref)) <= 1e-12
+    assert abs(st.norm() - 1.0) <= 1e-12
+
+
 def test_hadamard_x11_uniform_at_32_qubits(gpu, big_state):
     """Sec. IV-D's benchmark circuit (11 H per qubit) through the block plan: H^11 = H, so all 2^32 amplitudes
     equal 2^-16."""
@@ -114,19 +176,21 @@ def test_ghz_at_32_qubits(gpu, big_state):
     assert np.max(np.abs(_amps(st, nz) - 1 / math.sqrt(2))) <= 1e-15
 
 
-def test_random_circuit_norm_and_echo_block_plan(gpu, big_state):
-    """The benchmark's 32-qubit random circuit (40 layers, block plan b=12, 4 low bits) preserves the norm, and
-    running its inverse afterwards returns to |0..0>."""
+@pytest.mark.parametrize("shape", [("block", 12, 4), "learned"])
+def test_random_circuit_norm_and_echo_block_plan(gpu, big_state, shape):
+    """The benchmark's 32-qubit random circuit (40 layers) through the greedy block plan and through the plan the
+    benchmark runs preserves the norm, and running its inverse afterwards returns to |0..0>."""
+    mode, bits, low = _learned_shape() if shape == "learned" else shape
     circ = C.su4_u3_random(n=N, seed=32, layers=40)
     st = big_state
     st.init_zero()
     c = Circuit.from_ops(N, circ.ops)
-    p = Plan(c, "block", 12, 4)
+    p = Plan(c, mode, bits, low)
     p.run(st)
     assert abs(st.norm() - 1.0) <= 1e-12
     inv = C.inverse_circuit(circ)
     ci = Circuit.from_ops(N, inv.ops)
-    pi = Plan(ci, "block", 12, 4)
+    pi = Plan(ci, mode, bits, low)
     pi.run(st)
     a0 = _amps(st, np.array([0]))[0]
     assert abs(a0 - 1.0) <= 1e-12

@@ -13,7 +13,8 @@ from paper_2203_16044_amd.plan import Circuit, Plan
 pytestmark = pytest.mark.gpu
 
 TOL128 = 1e-12
-PLANS = [("block", 8, 0), ("block", 8, 3), ("block", 10, 4), ("block", 11, 3), ("block", 12, 4), ("block", 13, 3),
+PLANS = [("block", 8, 0), ("block", 8, 3), ("block", 10, 4), ("block", 11, 3), ("block", 12, 3), ("block", 12, 4),
+         ("block", 13, 3),
          ("fuse", 2, 0), ("fuse", 3, 0), ("fuse", 4, 0), ("fuse", 5, 0), ("fuse", 6, 0)]
 
 
@@ -52,7 +53,8 @@ def test_plan_u3_cnot_all_amplitudes(gpu, mode, bits, low):
     assert _maxerr(got, oracle.run(circ)) <= TOL128
 
 
-@pytest.mark.parametrize("mode,bits,low", [("block", 12, 4), ("block", 13, 3), ("fuse", 5, 0), ("fuse", 6, 0)])
+@pytest.mark.parametrize("mode,bits,low", [("block", 12, 3), ("block", 12, 4), ("block", 13, 3), ("fuse", 5, 0),
+                                           ("fuse", 6, 0)])
 def test_plan_su4_u3_family_18_qubits(gpu, mode, bits, low):
     circ = C.su4_u3_random(n=18, seed=32, layers=14)
     got, info = _run_plan(gpu, circ, mode, bits, low)
@@ -126,8 +128,9 @@ def block_async():
 @pytest.mark.parametrize("dtype,tol", [("c128", TOL128), ("c64", 2e-5)])
 def test_plan_double_buffered_block_pass(gpu, block_async, low, dtype, tol):
     """12-qubit block passes with double-buffered LDS filled by direct-to-LDS loads (complex128; complex64 keeps the
-    register-prefetch kernel under the same setting): same results as the oracle, on circuits whose passes span one
-    block per workgroup (15 qubits) and many (20 qubits)."""
+    register-prefetch kernel under the same setting): same results as the oracle at 15 and 20 qubits. With the default
+    grid (32 workgroups per CU, capped at the block count) every workgroup here runs exactly one block; the path of a
+    workgroup that walks several blocks is checked with a 256-workgroup grid in test_gpu_fullpath.py."""
     for circ in (C.random_circuit(15, seed=441, num_ops=150, kmax=3), C.su4_u3_random(n=20, seed=34, layers=12)):
         psi0 = C.random_state(circ.n, 8)
         got, _ = _run_plan(gpu, circ, "block", 12, low, psi0, dtype)
