@@ -39,10 +39,10 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (= FP64 MFMA): 256 CUs x 4 SIMDs x
 PMC_TRAFFIC = {
     "block_b12": {"fetch_kib": 33554691.5, "write_kib": 67111439.1, "fetch_scale": 2.0, "write_scale": 1.0,
                   "sources": ["paper_2203_16044_amd/csrc/qs_block.hip", "paper_2203_16044_amd/csrc/qs_internal.h"],
-                  "sha1": "278ea8ac71732e291c5574a93d9aef5ee4caf31d"},
+                  "sha1": "6fdb1c89f2c87c582c5b2ba6828026f54c99e3dd"},
     "dense_k1": {"fetch_kib": 33554444.3, "write_kib": 67110493.3, "fetch_scale": 2.0, "write_scale": 1.0,
                  "sources": ["paper_2203_16044_amd/csrc/qs_kernels.hip", "paper_2203_16044_amd/csrc/qs_internal.h"],
-                 "sha1": "4bb4205a1c06c53879ff84e16e567725432b15d6"},
+                 "sha1": "7c29bfe621ce9ac6e612ad14eec13084c024e8e6"},
 }
 
 

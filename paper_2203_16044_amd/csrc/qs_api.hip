@@ -7,8 +7,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "qs_internal.h"
@@ -83,6 +85,47 @@ void *qs_stage(qs_state *st, const void *host, size_t bytes)
     void *d = st->dring + st->ring_head;
     st->ring_head += need;
     return d;
+}
+
+// ---- device properties and kernel attributes, shared by the launchers ----
+namespace {
+constexpr int kMaxDev = 64;
+std::atomic<int> g_cus[kMaxDev];  // 0: not queried yet
+std::mutex g_lds_mu;
+std::vector<std::tuple<int, const void *, size_t>> g_lds_set;  // (device, kernel, bytes allowed)
+}  // namespace
+
+int qs_cu_count()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev)
+        return 256;
+    int c = g_cus[dev].load(std::memory_order_relaxed);
+    if (c > 0)
+        return c;
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+        c = 256;
+    g_cus[dev].store(c, std::memory_order_relaxed);
+    return c;
+}
+
+hipError_t qs_allow_lds(const void *fn, size_t bytes)
+{
+    if (bytes <= 65536)
+        return hipSuccess;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    std::lock_guard<std::mutex> lock(g_lds_mu);
+    for (auto &t : g_lds_set)
+        if (std::get<0>(t) == dev && std::get<1>(t) == fn && std::get<2>(t) >= bytes)
+            return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess)
+        return e;
+    g_lds_set.emplace_back(dev, fn, bytes);
+    return hipSuccess;
 }
 
 // ---- host helpers shared with the planner ----

@@ -781,18 +781,9 @@ hipError_t batch_b(void *psi, double *probs, const BatchItem *items, int nitems,
     using C2 = typename BT<R>::C2;
     // complex64: room for a pass's fused stage matrices next to the block
     const size_t shm = (sizeof(C2) << B) + (sizeof(R) == 4 ? 256 * sizeof(C2) * kMaxMfmaStages : 0);
-    static bool attr_set = false;
-    if (!attr_set && shm > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_batch_level<R, B>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
-        if (e != hipSuccess)
-            return e;
-        attr_set = true;
-    }
-    int cus = 0, dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-        cus = 256;
-    uint64_t grid = (uint64_t)cus * wg_per_cu;
+    if (hipError_t e = qs_allow_lds((const void *)k_batch_level<R, B>, shm))
+        return e;
+    uint64_t grid = (uint64_t)qs_cu_count() * wg_per_cu;
     if (grid > nblocks)
         grid = nblocks;
     if (grid == 0)
@@ -826,22 +817,14 @@ hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const Bloc
         return hipErrorInvalidValue;
     const size_t data = sizeof(C2) << B;
     const size_t shm = data + 256 * sizeof(C2) * mf.n;
-    static bool attr_set = false;
     const size_t shm_max = data + (sizeof(R) == 4 && W == 4 ? 256 * sizeof(C2) * kMaxMfmaStages : 0);
-    if (!attr_set && shm_max > 65536) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_block<R, B, W, NT>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_max);
-        if (e != hipSuccess)
-            return e;
-        attr_set = true;
-    }
+    if (hipError_t e = qs_allow_lds((const void *)k_block<R, B, W, NT>, shm_max))
+        return e;
     // persistent workgroups (each walks several blocks so its loads can run ahead of its arithmetic)
-    int cus = 0, dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-        cus = 256;
+    const uint64_t cus = (uint64_t)qs_cu_count();
     // block_wg_per_cu counts 256-thread workgroups: smaller workgroups get proportionally more
-    uint64_t grid = (uint64_t)cus * qs_tunables().block_wg_per_cu * 256 / NT;
-    if (grid < (uint64_t)cus)
+    uint64_t grid = cus * qs_tunables().block_wg_per_cu * 256 / NT;
+    if (grid < cus)
         grid = cus;
     if (grid > nblocks)
         grid = nblocks;
@@ -849,15 +832,9 @@ hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const Bloc
     // amplitudes into two adjacent slots, which the swizzle may need in the opposite order
     if constexpr (B == 12 && W == 4 && sizeof(R) == 8) {
         if (qs_tunables().block_async) {
-            static bool attr_async = false;
             const size_t shm2 = 2 * shm;
-            if (!attr_async && shm2 > 65536) {
-                hipError_t e = hipFuncSetAttribute((const void *)k_block_async<R, B>,
-                                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm2);
-                if (e != hipSuccess)
-                    return e;
-                attr_async = true;
-            }
+            if (hipError_t e = qs_allow_lds((const void *)k_block_async<R, B>, shm2))
+                return e;
             hipLaunchKernelGGL((k_block_async<R, B>), dim3((unsigned)grid), dim3(256), shm2, s, (C2 *)psi, nblocks,
                                outer, bm, stages, nstages, (const R *)mats);
             return hipGetLastError();

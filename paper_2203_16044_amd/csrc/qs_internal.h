@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstddef>
 #include <cstdint>
 #include <vector>
@@ -205,15 +206,22 @@ template <class R> struct NT2;
 template <> struct NT2<double> { typedef double type __attribute__((ext_vector_type(2))); };
 template <> struct NT2<float> { typedef float type __attribute__((ext_vector_type(2))); };
 
-// tunables (set through qs_set_tunable)
+// tunables (set through qs_set_tunable). Process-wide and atomic: a call on one thread may change them while
+// another thread plans or launches; each launch or plan reads every tunable it uses once.
 struct Tunables {
-    int dense_gpt = 1;       // groups per thread for k = 1, 2
-    int nontemporal = 1;     // use non-temporal loads/stores in the plain gate kernels
-    int mfma_wg_per_cu = 2;  // persistent workgroups per CU for the MFMA block kernel
-    int block_wg_per_cu = 32; // persistent workgroups per CU for the LDS block kernel (in 256-thread units)
-    int block_stage_width = 4; // register stage width of new block plans: 4, or 3 (512-thread kernel, b = 12, 13)
-    int plan_beam = 16;        // pass formation: beam width over local-set growth (0: fewest-new-qubits greedy)
-    int block_async = 0;       // 12-qubit block passes: double-buffered LDS with direct-to-LDS loads
-    int mfma_stage_ops = 3;    // complex64 plans: stages of at least this many ops run fused on MFMA (0: never)
+    std::atomic<int> dense_gpt{1};        // groups per thread for k = 1, 2
+    std::atomic<int> nontemporal{1};      // use non-temporal loads/stores in the plain gate kernels
+    std::atomic<int> mfma_wg_per_cu{2};   // persistent workgroups per CU for the MFMA block kernel
+    std::atomic<int> block_wg_per_cu{32}; // persistent workgroups per CU for the LDS block kernel (256-thread units)
+    std::atomic<int> block_stage_width{4}; // register stage width of new block plans: 4, or 3 (512 threads, b = 12, 13)
+    std::atomic<int> plan_beam{16};       // pass formation: beam width over local-set growth (0: fewest-new greedy)
+    std::atomic<int> block_async{0};      // 12-qubit block passes: double-buffered LDS with direct-to-LDS loads
+    std::atomic<int> mfma_stage_ops{3};   // complex64 plans: stages of at least this many ops run fused on MFMA
 };
 Tunables &qs_tunables();
+
+// Compute units of the current device (cached per device; 256 if the query fails).
+int qs_cu_count();
+// Allow `fn` up to `bytes` of dynamic LDS on the current device (hipFuncSetAttribute once per device, kernel and
+// larger size; thread-safe).
+hipError_t qs_allow_lds(const void *fn, size_t bytes);

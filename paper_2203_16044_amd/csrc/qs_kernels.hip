@@ -731,8 +731,9 @@ hipError_t dense_k(void *psi, uint64_t ngroups, const InsBits &ins, const TPos &
                    hipStream_t s)
 {
     using C2 = typename CT<R>::T;
-    Tunables tu = qs_tunables();
-    tu.nontemporal = nt_for<R>(tp, K);
+    struct {
+        int dense_gpt, nontemporal;
+    } tu{qs_tunables().dense_gpt.load(), nt_for<R>(tp, K)};
     const int bs = 256;
     if constexpr (K <= 3) {
         MatByVal<R, K> m;

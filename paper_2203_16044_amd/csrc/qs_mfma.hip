@@ -181,23 +181,11 @@ __global__ __launch_bounds__(256) void k_dense_mfma(typename MF<R>::C2 *__restri
     }
 }
 
-int cu_count()
-{
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess ||
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            cus = 256;
-    }
-    return cus;
-}
-
 template <class R, int K>
 hipError_t mfma_k(void *psi, uint64_t ngroups, const InsBits &ins, const TPos &tp, const void *U, hipStream_t s)
 {
     const uint64_t ntiles = (ngroups + 15) / 16;
-    uint64_t grid = (uint64_t)cu_count() * qs_tunables().mfma_wg_per_cu;
+    uint64_t grid = (uint64_t)qs_cu_count() * qs_tunables().mfma_wg_per_cu;
     if (grid > ntiles)
         grid = ntiles;
     hipLaunchKernelGGL((k_dense_mfma<R, K>), dim3((unsigned)grid), dim3(256), 0, s, (typename MF<R>::C2 *)psi,

@@ -1396,15 +1396,29 @@ QS_API int qs_batch_run(qs_batch *Bt, int use_graph)
         return QS_OK;
     }
     if (!Bt->exec) {
+        // a graph left by an earlier failed instantiation is dropped before capturing again
+        if (Bt->graph) {
+            (void)hipGraphDestroy(Bt->graph);
+            Bt->graph = nullptr;
+        }
         QS_HIP(hipStreamBeginCapture(Bt->stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = enqueue();
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(Bt->stream, &g);
-        if (e != hipSuccess)
-            return qs_hip_fail(e, "batch launch during capture");
-        QS_HIP(e2);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g)
+                (void)hipGraphDestroy(g);
+            return e != hipSuccess ? qs_hip_fail(e, "batch launch during capture")
+                                   : qs_hip_fail(e2, "hipStreamEndCapture(batch)");
+        }
+        hipGraphExec_t x = nullptr;
+        hipError_t e3 = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e3 != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return qs_hip_fail(e3, "hipGraphInstantiate(batch)");
+        }
         Bt->graph = g;
-        QS_HIP(hipGraphInstantiate(&Bt->exec, Bt->graph, nullptr, nullptr, 0));
+        Bt->exec = x;
     }
     QS_HIP(hipGraphLaunch(Bt->exec, Bt->stream));
     return QS_OK;
