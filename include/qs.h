@@ -130,6 +130,24 @@ QS_API int qs_fused_swap(qs_state *st, int p, int q, int s);
  */
 QS_API int qs_probs(qs_state *st, double *out_dev, double *norm_out);
 
+/* ---- allocation-free entry point ----
+ * qs_probs_noalloc -- qs_probs on a raw amplitude buffer, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation): it calls no hipMalloc, hipFree or
+ * allocating library routine and needs no state handle. The reduction's FP64 partial sums go to a library-held
+ * device array of 4096 doubles (32 KiB per GPU, resolved once per device on the first call made with that device
+ * current, kept until the process ends); every call on a GPU shares it, so calls whose work overlaps on one GPU
+ * (different streams) race, and calls on one stream are ordered. Results are bit-identical to qs_probs on the same
+ * amplitudes (same kernels, same fixed reduction order).
+ *   psi       device buffer of 2^n amplitudes in dtype's layout, 16-byte aligned (caller-owned).
+ *   n, dtype  1 <= n <= QS_MAX_QUBITS; QS_C128 or QS_C64.
+ *   out_dev   device buffer of 2^n doubles receiving |a_i|^2, or NULL.
+ *   norm_dev  device double receiving sum_i |a_i|^2 (fixed-order FP64 reduction), or NULL; at least one of out_dev
+ *             and norm_dev is non-NULL. Both 8-byte aligned.
+ *   hip_stream the hipStream_t to enqueue on (NULL = the null stream); the call does not synchronise.
+ * Errors: QS_EINVAL (NULL or misaligned buffers, n or dtype out of range, both outputs NULL), QS_EUNSUPPORTED (more
+ * partial sums than the scratch holds; cannot happen for valid n), QS_EDEVICE. A rejected call enqueues nothing. */
+QS_API int qs_probs_noalloc(const void *psi, int n, int dtype, double *out_dev, double *norm_dev, void *hip_stream);
+
 /* ---- state management and support calls (used by tests, renormalisation and harnesses) ---- */
 
 /* Reset to |0...0> (a fill kernel, no memset). */

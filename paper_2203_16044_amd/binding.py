@@ -49,6 +49,7 @@ SIGNATURES = {
     "qs_apply_controlled": [_P, _IP, _I, _IP, _I, _DP],
     "qs_fused_swap": [_P, _I, _I, _I],
     "qs_probs": [_P, _P, _DP],
+    "qs_probs_noalloc": [_P, _I, _I, _P, _P, _P],
     "qs_init_zero": [_P],
     "qs_copy_in": [_P, _P],
     "qs_copy_out": [_P, _P],
@@ -200,6 +201,12 @@ def qs_probs(h: int, out_dev: Optional[int] = None, want_norm: bool = False) -> 
     nrm = ctypes.c_double(0.0)
     _check(lib().qs_probs(h, out_dev, ctypes.byref(nrm) if want_norm else None), "qs_probs")
     return nrm.value if want_norm else None
+
+
+def qs_probs_noalloc(psi_dev: int, n: int, dtype: int, out_dev: Optional[int], norm_dev: Optional[int],
+                     hip_stream: Optional[int] = None) -> None:
+    """Probabilities and norm of a raw amplitude buffer, without allocating (device pointers in and out)."""
+    _check(lib().qs_probs_noalloc(psi_dev, int(n), int(dtype), out_dev, norm_dev, hip_stream), "qs_probs_noalloc")
 
 
 def qs_init_zero(h: int) -> None:
