@@ -37,12 +37,14 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (= FP64 MFMA): 256 CUs x 4 SIMDs x
 # The readings hold for the kernel sources they were taken on: `sha1` fingerprints those files and the traffic is
 # reported as null once they differ.
 PMC_TRAFFIC = {
-    "block_b12": {"fetch_kib": 33554691.5, "write_kib": 67111439.1, "fetch_scale": 2.0, "write_scale": 1.0,
-                  "sources": ["paper_2203_16044_amd/csrc/qs_block.hip", "paper_2203_16044_amd/csrc/qs_internal.h"],
-                  "sha1": "6fdb1c89f2c87c582c5b2ba6828026f54c99e3dd"},
-    "dense_k1": {"fetch_kib": 33554444.3, "write_kib": 67110493.3, "fetch_scale": 2.0, "write_scale": 1.0,
-                 "sources": ["paper_2203_16044_amd/csrc/qs_kernels.hip", "paper_2203_16044_amd/csrc/qs_internal.h"],
-                 "sha1": "7c29bfe621ce9ac6e612ad14eec13084c024e8e6"},
+    "block_b12": {"fetch_kib": None, "write_kib": None, "fetch_scale": 2.0, "write_scale": 1.0,
+                  "sources": ["paper_2203_16044_amd/csrc/qs_block.hip", "paper_2203_16044_amd/csrc/qs_internal.h",
+                              "paper_2203_16044_amd/csrc/qs_index.h"],
+                  "sha1": None},
+    "dense_k1": {"fetch_kib": None, "write_kib": None, "fetch_scale": 2.0, "write_scale": 1.0,
+                 "sources": ["paper_2203_16044_amd/csrc/qs_kernels.hip", "paper_2203_16044_amd/csrc/qs_internal.h",
+                             "paper_2203_16044_amd/csrc/qs_index.h"],
+                 "sha1": None},
 }
 
 
@@ -69,8 +71,9 @@ def _alg_bytes(op, n, amp):
     full = 2 * amp * (1 << n)
     if op.kind == "dense":
         return full
-    if op.kind == "diag":
-        return full  # the circuits here use diagonals with no unit entries
+    if op.kind == "diag":  # only amplitudes whose entry is not exactly 1 change
+        d = op.mat.ravel()
+        return full * int(sum(1 for x in d if x != 1)) // len(d)
     if op.kind == "ctrl":
         return full >> len(op.controls)
     if op.kind == "fswap":
@@ -248,6 +251,65 @@ def bench_c64(head_rate, steps, torch):
                           "against": "complex128 path (n=24, 40 layers, seed 24)"}}
 
 
+def copy_ceiling(torch, gib=4, reps=5):
+    """The measured HBM ceiling: the probe copy kernel (dst = src, 16-byte lanes) over `gib` GiB, best of `reps`,
+    in TB/s of bytes read + written."""
+    import paper_2203_16044_amd as qs
+    nbytes = gib << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    s = torch.cuda.current_stream()
+    best = float("inf")
+    for _ in range(reps + 1):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(s)
+        qs.binding.qs_probe_copy(dst.data_ptr(), src.data_ptr(), nbytes, s.cuda_stream)
+        b.record(s)
+        b.synchronize()
+        best = min(best, a.elapsed_time(b) / 1e3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / best / 1e12
+
+
+def bench_mixed28(torch, copy_tbs, steps=1, warmup=1):
+    """The 28-qubit mixed circuit (U3, CZ and RZ layers, Toffolis, fused-swaps; 1,425 operations), unfused: one pass
+    per operation, per-class HBM rates (algorithmic bytes) against 8 TB/s and against the measured copy ceiling; and
+    the same circuit through the greedy block plan."""
+    import circuits as C
+    import paper_2203_16044_amd as qs
+    from paper_2203_16044_amd.plan import Circuit, Plan
+    circ = C.mixed_layers()
+    n = circ.n
+    st = qs.State(n, "c128")
+    ops = circ.ops
+    units = [(o.label.lower(), _alg_bytes(o, n, 16), _alg_flops(o, n)) for o in ops]
+    times, per = time_steps(st, steps, warmup, lambda ev: run_plain(st, ops, ev) if ev else [st.apply_op(o) for o in ops],
+                            units, torch)
+    t = sum(times) / len(times)
+    classes = {}
+    for c, (sec, cnt, nbytes, _) in sorted(per.items()):
+        tbs = nbytes / sec / 1e12
+        classes[c] = {"ops": cnt // len(times), "avg_ms": sec / cnt * 1e3, "tbs": tbs, "frac_of_peak": tbs / HBM_PEAK_TBS,
+                      "frac_of_copy_ceiling": tbs / copy_tbs}
+    total_bytes = sum(u[1] for u in units)
+    cc = Circuit.from_ops(n, ops)
+    p = Plan(cc, "block", 12, 4, "c128")
+    npass = p.info()["passes"]
+    bt, _ = time_steps(st, steps, warmup, lambda ev: p.run(st), [], torch)
+    p.close()
+    cc.close()
+    st.close()
+    torch.cuda.empty_cache()
+    return {"workload": f"mixed circuit, n={n}, 20 layers (U3, CZ on alternating pairs, RZ), 32 Toffolis, 3 fused-swaps "
+                        f"(0, 22, 6); {len(ops)} operations, complex128, seed 28",
+            "plain_ops_per_s": len(ops) / t, "plain_ms_per_step": t * 1e3, "plain_tbs_whole": total_bytes / t / 1e12,
+            "per_class": classes,
+            "paper_effective_tbs": (1 << (n + 5)) * len(ops) / t / 1e12,
+            "block_plan": {"passes": npass, "ops_per_s": len(ops) / (sum(bt) / len(bt)),
+                           "ms_per_step": sum(bt) / len(bt) * 1e3}}
+
+
 def bench_batch(torch, log):
     """Batched serving form: 512 independent circuits (10..22 qubits, 10..40 layers) in one persistent launch,
     autotuned, eager and replayed from a HIP graph, against the per-circuit plain loop."""
@@ -298,6 +360,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-c64", action="store_true", help="skip the 33-qubit complex64 leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-circuit batched leg")
+    ap.add_argument("--no-mixed28", action="store_true", help="skip the 28-qubit mixed-circuit (plain kernels) leg")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the gate path is single-GPU (multi-GPU sharding is a design note only). "
@@ -335,21 +398,26 @@ def main():
     if args.mode == "tuned":
         from paper_2203_16044_amd import costmodel as CM
         cc = Circuit.from_ops(n, ops)
-        learned = None
+        greedy = ("block", args.block_bits, args.low_bits)
+        learned, head_plan = None, None
         if not args.greedy and os.path.exists(CM.WEIGHTS):
             model = CM.CostModel.load()
-            lp, learned, pred = CM.choose_plan(cc, "c128", model)
-            lp.close()
+            head_plan, learned, pred = CM.choose_plan(cc, "c128", model)
             model.close()
-        head_v = learned or ("block", args.block_bits, args.low_bits)
-        greedy_v = [] if args.no_compare_greedy else [("block", args.block_bits, args.low_bits)]
+        head_v = learned or greedy
+        key = lambda v: "learned_per_pass" if v == CM.LEARNED else (  # noqa: E731
+            f"{v[0]}{v[1]}" + (f"_low{v[2]}" if v[0] == "block" else ""))
+        greedy_v = [] if args.no_compare_greedy else [greedy]
         variants = [head_v] + [v for v in greedy_v + [("fuse", k, 0) for k in args.compare_fuse] if v != head_v]
-        for vi, (mode, bits, low) in enumerate(variants):
-            log0(f"bench: plan {mode} {bits} {low}")
-            plan = Plan(cc, mode, bits, low, "c128")
+        for vi, v in enumerate(variants):
+            log0(f"bench: plan {key(v)}")
+            if vi == 0 and head_plan is not None:
+                plan = head_plan
+            else:
+                plan = Plan(cc, *v, "c128")
             info = plan.info()
             passes = plan.passes()
-            kinds = {0: f"block_b{bits}", 1: "dense_k{}", 2: "fswap", 3: "other"}
+            kinds = {0: "block_b{}", 1: "dense_k{}", 2: "fswap", 3: "other"}
             # flops of a pass from the planner's features (flops per amplitude, / 256) x amplitudes
             fl = [float(qs.binding.qs_plan_features(plan.h, i)[14]) * 256 * (1 << n) for i in range(len(passes))]
             units = [(kinds[ps["type"]].format(ps["nqubits"]),
@@ -359,16 +427,15 @@ def main():
             times, per = time_steps(st, args.steps if main else 1, args.warmup if main else 1,
                                     lambda ev, plan=plan, npass=len(passes): run_plan(st, plan, npass, ev) if ev
                                     else plan.run(st), units, torch)
-            results[f"{mode}{bits}" + (f"_low{low}" if mode == "block" else "")] = {
+            results[key(v)] = {
                 "passes": info["passes"], "gates_per_s": gates / (sum(times) / len(times)),
                 "ms_per_step": sum(times) / len(times) * 1e3, "per_kernel": summarize(per, len(times)),
                 "_times": times, "_per": per}
             plan.close()
         cc.close()
-        hm, hb, hl = head_v
-        head = results[f"{hm}{hb}" + (f"_low{hl}" if hm == "block" else "")]
+        head = results[key(head_v)]
         step_times, per_class = head["_times"], head["_per"]
-        greedy_key = f"block{args.block_bits}_low{args.low_bits}"
+        greedy_key = key(greedy)
     else:
         step_times, per_class = p_times, p_per
     nrm = st.norm()
@@ -405,9 +472,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"random SU(4)+U3 circuit, n={n}, {args.layers} layers, {gates} gates, complex128 "
                                f"(seed 32)", "n": n, "gates": gates, "mode": args.mode,
-                   "plan": (("learned: " if args.mode == "tuned" and learned else "greedy: ") +
-                            (f"{head_v[0]} b={head_v[1]} low={head_v[2]}" if args.mode == "tuned"
-                             else "one pass per gate")),
+                   "plan": ("one pass per gate" if args.mode != "tuned" else
+                            "learned: every pass chosen by the cost model" if learned == ("learned", 0, 0) else
+                            ("learned: " if learned else "greedy: ") + f"{head_v[0]} b={head_v[1]} low={head_v[2]}"),
                    "parallelism": "none"},
         "roofline": dict(roof, traffic=pmc_traffic(dom), kernel=dom, avg_launch_ms=avg * 1e3,
                          launches_per_step=cnt // len(step_times), alg_bytes_per_launch=bsum // cnt,
@@ -421,11 +488,22 @@ def main():
                                    if args.mode == "tuned" and greedy_key in results else None),
         "hbm_tbs_whole_step": (sum(v[2] for v in per_class.values()) / len(step_times)) / t_step / 1e12,
         "paper_nominal_tbs": (1 << (n + 5)) * gates / t_step / 1e12,
+        # quantum B/F ratio (Sec. IV-B): 2^(n+5) x #gates / (execution time x peak FP64 FLOP/s)
+        "qbf": (1 << (n + 5)) * gates / t_step / (FP64_PEAK_TFLOPS * 1e12),
         "alternatives": {k: {kk: vv for kk, vv in v.items() if not kk.startswith("_")} for k, v in results.items()},
         "norm_after": nrm,
         "wall_s": wall,
     }
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
+    log("bench: copy ceiling")
+    copy_tbs = copy_ceiling(torch)
+    out["copy_ceiling_tbs"] = copy_tbs
+    out["roofline"]["hbm_frac_of_copy_ceiling"] = out["roofline"]["hbm_tbs"] / copy_tbs
+    for c, v in out["plain"]["per_kernel"].items():
+        v["frac_of_copy_ceiling"] = v["tbs"] / copy_tbs
+    if not args.no_mixed28:
+        log("bench: 28-qubit mixed circuit")
+        out["mixed28"] = bench_mixed28(torch, copy_tbs)
     if not args.no_c64:
         log("bench: complex64 leg")
         out["c64"] = bench_c64(gates / t_step, 1, torch)

@@ -256,11 +256,36 @@ QS_API int qs_plan_free(qs_plan *p);
 #define QS_PLAN_NFEAT 48
 QS_API int qs_plan_features(const qs_plan *p, int i, float *features);
 
+/* ---- learned planning: the cost model chooses every pass ----
+ * Pass formation as in qs_plan_create (a gate joins a pass only when every earlier gate on its qubits is placed), but
+ * at every step the planner forms candidate passes for each of the `nshapes` block shapes (block_bits, low_bits), up
+ * to `per_shape` per shape (the local sets its beam search ends with, most gates first), describes each candidate by
+ * its QS_PLAN_NFEAT features (qs_plan_features), lets `model` predict log(pass milliseconds) from the features
+ * standardised as (f - mean) / std, and keeps the candidate with the lowest predicted time per circuit gate carried
+ * among those that carry at least (the most gates any candidate carries) - gate_slack gates.
+ * Passes of a plan may therefore differ in block size and low bits. Gates that no block pass can carry run as their
+ * own passes, as in qs_plan_create. opts->mode must be QS_PLAN_BLOCK; opts->block_bits / low_bits are ignored.
+ * The model runs on its own stream (one synchronising prediction per pass). Host arrays are read during the call.
+ *   shape_bits[i] in [10, 13] (and <= n), shape_low[i] in [0, shape_bits[i]], 1 <= nshapes <= 16,
+ *   1 <= per_shape <= 8, gate_slack >= 0; model built with nin = QS_PLAN_NFEAT; std entries > 0.
+ * Errors: QS_EINVAL for NULL pointers, out-of-range fields (a shape wider than the circuit included) or a model of
+ * another input width; the errors of qs_mlp_predict. */
+typedef struct qs_mlp qs_mlp;
+typedef struct {
+    qs_mlp *model;
+    const float *mean, *std; /* QS_PLAN_NFEAT each */
+    int nshapes;
+    const int *shape_bits, *shape_low;
+    int per_shape;
+    int gate_slack;
+} qs_plan_model;
+QS_API int qs_plan_create_learned(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts,
+                                  const qs_plan_model *model);
+
 /* An MLP nin -> hidden -> hidden -> 1 (ReLU between layers), FP32, trained with MSE loss and Adam on the GPU by
  * the library's own kernels (deterministic fixed-order reductions). Parameters are one flat array:
  * W1[hidden][nin], b1[hidden], W2[hidden][hidden], b2[hidden], W3[hidden], b3. Batches hold 1..4096 samples;
  * X is row-major (sample, feature); host arrays are copied during the call. All calls synchronise. */
-typedef struct qs_mlp qs_mlp;
 QS_API int qs_mlp_create(qs_mlp **out, int nin, int hidden, void *hip_stream);
 QS_API int qs_mlp_free(qs_mlp *m);
 QS_API int qs_mlp_num_params(const qs_mlp *m, int *nparams);

@@ -27,9 +27,11 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        path = _build.LIB
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
-            _build.build()
+        path = os.environ.get("QS_LIBQS_ORACLE")  # a sanitizer build (oracle/build.py --sanitize)
+        if not path:
+            path = _build.LIB
+            if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+                _build.build()
         L = ctypes.CDLL(path)
         dp = ctypes.POINTER(ctypes.c_double)
         ip = ctypes.POINTER(ctypes.c_int)

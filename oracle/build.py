@@ -1,4 +1,7 @@
-"""Build the C oracle (test infrastructure): gcc -O2 -fopenmp -ffp-contract=off, no hand SIMD."""
+"""Build the C oracle (test infrastructure): gcc -O2 -fopenmp -ffp-contract=off, no hand SIMD.
+
+--sanitize builds a second copy with AddressSanitizer and UndefinedBehaviorSanitizer (LLVM clang, so that one
+sanitizer runtime serves it and the library's sanitizer build in one process) into SANITIZE_LIB."""
 from __future__ import annotations
 
 import os
@@ -20,5 +23,23 @@ def build(force: bool = True) -> str:
     return LIB
 
 
+ROOT = os.path.dirname(HERE)
+SANITIZE_LIB = os.path.join(ROOT, "_build", "sanitize", "libqs_oracle.so")
+CLANG = "/opt/rocm/llvm/bin/clang"
+
+
+def build_sanitized() -> str:
+    os.makedirs(os.path.dirname(SANITIZE_LIB), exist_ok=True)
+    cmd = [CLANG, "-std=c11", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-shared-libsan", "-ffp-contract=off", "-shared", "-fPIC", "-Wall",
+           "-Wextra", "-o", SANITIZE_LIB + ".tmp", SRC]
+    subprocess.run(cmd, check=True)
+    os.replace(SANITIZE_LIB + ".tmp", SANITIZE_LIB)
+    return SANITIZE_LIB
+
+
 if __name__ == "__main__":
-    print(build(force="--if-stale" not in sys.argv))
+    if "--sanitize" in sys.argv:
+        print(build_sanitized())
+    else:
+        print(build(force="--if-stale" not in sys.argv))

@@ -13,7 +13,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libqs.so")
+# QS_LIBQS selects another build of the same library (the sanitizer build of build.py --sanitize)
+LIB_PATH = os.environ.get("QS_LIBQS") or os.path.join(PKG, "libqs.so")
 
 QS_OK, QS_EINVAL, QS_ENOMEM, QS_EDEVICE, QS_EUNSUPPORTED = 0, -1, -2, -3, -4
 QS_C128, QS_C64 = 0, 1
@@ -25,6 +26,14 @@ QS_PLAN_NFEAT = 48
 class qs_plan_opts(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("block_bits", ctypes.c_int), ("low_bits", ctypes.c_int),
                 ("dtype", ctypes.c_int)]
+
+
+class qs_plan_model(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_void_p), ("mean", ctypes.POINTER(ctypes.c_float)),
+                ("std", ctypes.POINTER(ctypes.c_float)), ("nshapes", ctypes.c_int),
+                ("shape_bits", ctypes.POINTER(ctypes.c_int)), ("shape_low", ctypes.POINTER(ctypes.c_int)),
+                ("per_shape", ctypes.c_int), ("gate_slack", ctypes.c_int)]
+
 
 _lib = None
 
@@ -71,6 +80,7 @@ SIGNATURES = {
     "qs_circuit_size": [_P, _IP],
     "qs_circuit_run": [_P, _P],
     "qs_plan_create": [ctypes.POINTER(_P), _P, _P],
+    "qs_plan_create_learned": [ctypes.POINTER(_P), _P, _P, _P],
     "qs_plan_run": [_P, _P],
     "qs_plan_run_range": [_P, _P, _I, _I],
     "qs_plan_info": [_P, _IP, _IP, _IP, _IP, _IP],
@@ -314,6 +324,25 @@ def qs_plan_create(c: int, mode: int, block_bits: int, low_bits: int = 0, dtype:
     o = qs_plan_opts(int(mode), int(block_bits), int(low_bits), int(dtype))
     h = _P()
     _check(lib().qs_plan_create(ctypes.byref(h), c, ctypes.byref(o)), "qs_plan_create")
+    return h.value
+
+
+def qs_plan_create_learned(c: int, dtype: int, model: int, mean, std, shapes, per_shape: int,
+                           gate_slack: int = 0) -> int:
+    """shapes: sequence of (block_bits, low_bits); mean / std: QS_PLAN_NFEAT floats each."""
+    mean = np.ascontiguousarray(mean, dtype=np.float32)
+    std = np.ascontiguousarray(std, dtype=np.float32)
+    if mean.size != QS_PLAN_NFEAT or std.size != QS_PLAN_NFEAT:
+        raise ValueError(f"mean and std must hold {QS_PLAN_NFEAT} floats")
+    bits = (ctypes.c_int * len(shapes))(*[int(b) for b, _ in shapes])
+    low = (ctypes.c_int * len(shapes))(*[int(w) for _, w in shapes])
+    fp = ctypes.POINTER(ctypes.c_float)
+    m = qs_plan_model(model, mean.ctypes.data_as(fp), std.ctypes.data_as(fp), len(shapes), bits, low, int(per_shape),
+                      int(gate_slack))
+    o = qs_plan_opts(QS_PLAN_BLOCK, 0, 0, int(dtype))
+    h = _P()
+    _check(lib().qs_plan_create_learned(ctypes.byref(h), c, ctypes.byref(o), ctypes.byref(m)),
+           "qs_plan_create_learned")
     return h.value
 
 

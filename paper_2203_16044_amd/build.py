@@ -57,5 +57,36 @@ def build(jobs: int | None = None) -> str:
     return LIB
 
 
+SANITIZE_DIR = os.path.join(ROOT, "_build", "sanitize")
+# host code only: AddressSanitizer + UndefinedBehaviorSanitizer on the CPU side (planner, validation, ABI); the GPU
+# code objects are built as usual
+SANITIZE_FLAGS = ["-Xarch_host", "-fsanitize=address,undefined", "-Xarch_host", "-fno-sanitize-recover=undefined",
+                  "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+
+
+def build_sanitized(jobs: int | None = None) -> str:
+    """libqs with sanitized host code, in _build/sanitize (selected at run time with QS_LIBQS)."""
+    global OBJ, LIB, CFLAGS
+    saved = OBJ, LIB, CFLAGS
+    OBJ, LIB = os.path.join(SANITIZE_DIR, "obj"), os.path.join(SANITIZE_DIR, "libqs.so")
+    CFLAGS = CFLAGS + SANITIZE_FLAGS
+    try:
+        os.makedirs(OBJ, exist_ok=True)
+        srcs = sources()
+        jobs = jobs or min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)), 16)
+        with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
+            objs = list(ex.map(_compile, srcs))
+        tmp = LIB + ".tmp"
+        cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address,undefined",
+               "-shared-libsan", "-o", tmp, *objs]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+        os.replace(tmp, LIB)
+        return LIB
+    finally:
+        OBJ, LIB, CFLAGS = saved
+
+
 if __name__ == "__main__":
-    print(build())
+    print(build_sanitized() if "--sanitize" in sys.argv else build())

@@ -54,16 +54,45 @@ def time_plan_passes(state, plan, reps: int = 2) -> np.ndarray:
     return np.array([a.elapsed_time(b) for a, b in ev], dtype=np.float64)
 
 
-def training_circuits(seed: int = 1000):
-    """The circuit families the model is trained on (20-30 qubits), kept short: pass times do not depend on depth."""
+def training_circuits(seed: int = 1000, nmax: int = 32):
+    """The circuit families the model is trained on (20..nmax qubits), kept short: pass times do not depend on depth."""
     import circuits as C
     out = []
-    for n in range(20, 31):
+    for n in range(20, nmax + 1):
         out.append(C.su4_u3_random(n=n, seed=seed + n, layers=3))
         out.append(C.mixed_layers(n=n, seed=seed + 100 + n, layers=3, toffolis=8, swap_s=min(6, n // 4)))
         out.append(C.random_circuit(n, seed=seed + 200 + n, num_ops=60, kmax=3,
                                     kinds=("dense", "diag", "ctrl")))
     return out
+
+
+def collect_learned(circs, model: "CostModel", dtypes=("c128", "c64"), log=print):
+    """Time every pass of the plans the model itself chooses pass by pass (qs_plan_create_learned): the candidates a
+    model prefers are where its errors cost most, so they are added to its training data."""
+    import torch
+
+    from .plan import Circuit
+    from .state import State
+    X, y = [], []
+    for dt in dtypes:
+        for circ in circs:
+            n = circ.n
+            if dt == "c64" and n > 31:
+                continue
+            st = State(n, dt)
+            c = Circuit.from_ops(n, circ.ops)
+            p = learned_plan(c, dt, model)
+            if p is not None:
+                ms = time_plan_passes(st, p)
+                X.append(plan_features(p))
+                y.append(np.log(np.maximum(ms, 1e-4)))
+                p.close()
+            c.close()
+            st.close()
+            del st
+            torch.cuda.empty_cache()
+        log(f"collected learned plans ({dt}): {sum(len(v) for v in y)} samples so far")
+    return np.concatenate(X).astype(np.float32), np.concatenate(y).astype(np.float32)
 
 
 def collect(circs, dtypes=("c128", "c64"), log=print, groups=None):
@@ -78,6 +107,8 @@ def collect(circs, dtypes=("c128", "c64"), log=print, groups=None):
     for dt in dtypes:
         for circ in circs:
             n = circ.n
+            if dt == "c64" and n > 31:
+                continue  # complex64 runs stay within the same state sizes as complex128's
             st = State(n, dt)
             c = Circuit.from_ops(n, circ.ops)
             t0 = time.perf_counter()
@@ -186,12 +217,31 @@ class CostModel:
 
 
 MARGIN = 0.03  # switch away from the greedy plan only for a predicted saving above this fraction
+# block shapes (block bits, always-local low bits) among which the learned planner chooses each pass
+PASS_SHAPES = ((12, 3), (12, 4), (13, 3), (11, 3))
+PER_SHAPE = 4  # candidate local sets per shape and pass
+GATE_SLACK = 0  # a candidate pass must carry at least the largest candidate's gate count minus this
+LEARNED = ("learned", 0, 0)
+
+
+def learned_plan(circuit, dtype: str, model: CostModel, shapes=PASS_SHAPES, per_shape: int = PER_SHAPE,
+                 gate_slack: int = GATE_SLACK):
+    """The plan whose every pass the model chooses (qs_plan_create_learned), or None for circuits too small for the
+    shapes."""
+    from .plan import Plan
+    shapes = [s for s in shapes if s[0] <= circuit.n]
+    if not shapes:
+        return None
+    return Plan.learned(circuit, model, shapes, per_shape, dtype, gate_slack)
 
 
 def choose_plan(circuit, dtype: str = "c128", model: Optional[CostModel] = None,
-                cands: Optional[Sequence[Tuple[str, int, int]]] = None, margin: float = MARGIN):
-    """The candidate plan with the lowest predicted time, if it beats the greedy plan's prediction by more than
-    `margin`; otherwise (and without a model) the greedy plan. Returns (plan, (mode, bits, low), predicted ms)."""
+                cands: Optional[Sequence[Tuple[str, int, int]]] = None, margin: float = MARGIN,
+                per_pass: bool = True):
+    """The candidate with the lowest predicted time, if it beats the greedy plan's prediction by more than `margin`;
+    otherwise (and without a model) the greedy plan. Candidates: whole plans of one shape each (`cands`, default
+    candidates(n)) and, with per_pass, the plan whose passes the model chooses one by one (LEARNED). Returns
+    (plan, (mode, bits, low), predicted ms)."""
     from .plan import Plan
     n = circuit.n
     g = greedy_for(n)
@@ -200,17 +250,24 @@ def choose_plan(circuit, dtype: str = "c128", model: Optional[CostModel] = None,
     gp = Plan(circuit, *g, dtype)
     gt = model.predict_plan_ms(gp)
     best = (gp, g, gt)
-    for cand in (cands or candidates(n)):
-        if cand == g:
-            continue
-        p = Plan(circuit, *cand, dtype)
+
+    def offer(p, key):
+        nonlocal best
         t = model.predict_plan_ms(p)
         if t < (1.0 - margin) * gt and t < best[2]:
             if best[0] is not gp:
                 best[0].close()
-            best = (p, cand, t)
+            best = (p, key, t)
         else:
             p.close()
+
+    for cand in (cands or candidates(n)):
+        if cand != g:
+            offer(Plan(circuit, *cand, dtype), cand)
+    if per_pass:
+        lp = learned_plan(circuit, dtype, model)
+        if lp is not None:
+            offer(lp, LEARNED)
     if best[0] is not gp:
         gp.close()
     return best
@@ -221,8 +278,10 @@ def main():
     ap.add_argument("--out", default=WEIGHTS)
     ap.add_argument("--epochs", type=int, default=300)
     ap.add_argument("--data", default=None, help="save / reuse the timing dataset (.npz)")
+    ap.add_argument("--rounds", type=int, default=2, help="rounds of learned planning added to the data")
     args = ap.parse_args()
-    if args.data and os.path.exists(args.data):
+    fresh = not (args.data and os.path.exists(args.data))  # timings collected in this run (not reused from a file)
+    if not fresh:
         d = np.load(args.data, allow_pickle=False)
         X, y = d["X"], d["y"]
     else:
@@ -238,14 +297,35 @@ def main():
     m = CostModel()
     m.fit(X[tr], y[tr], epochs=args.epochs, log=lambda s: print(s, flush=True))
     m.fit_more(X[tr], y[tr], epochs=args.epochs // 3, lr=3e-4)
+    # rounds of learned planning: the passes the model prefers are timed and added, and the model is trained again
+    if fresh:
+        circs = training_circuits()
+        for r in range(args.rounds):
+            X2, y2 = collect_learned(circs, m, log=lambda s: print(s, flush=True))
+            pv2 = m.predict_log_ms(X2)
+            print(f"round {r}: model error on its own choices: median {np.median(np.abs(np.exp(pv2 - y2) - 1)):.3f},"
+                  f" mean log bias {float(np.mean(pv2 - y2)):+.3f}", flush=True)
+            X, y = np.concatenate([X, X2]), np.concatenate([y, y2])
+            perm = rng.permutation(len(y))
+            cut = int(0.85 * len(y))
+            tr, va = perm[:cut], perm[cut:]
+            m.close()
+            m = CostModel()
+            m.fit(X[tr], y[tr], epochs=args.epochs, log=lambda s: print(s, flush=True))
+            m.fit_more(X[tr], y[tr], epochs=args.epochs // 3, lr=3e-4)
+            groups = groups + [(-1 - r, 0)] * len(y2)
+        if args.data:
+            np.savez(args.data, X=X, y=y, groups=np.array(groups, dtype=np.int32))
     pv = m.predict_log_ms(X[va])
     mse = float(np.mean((pv - y[va]) ** 2))
     rel = float(np.median(np.abs(np.exp(pv - y[va]) - 1)))
     print(f"validation mse(log ms) {mse:.4f}, median relative error {rel:.3f}", flush=True)
     if "groups" in locals() or (args.data and os.path.exists(args.data)):
         g = np.asarray(groups if "groups" in locals() else np.load(args.data)["groups"])
-        pall = np.exp(m.predict_log_ms(X).astype(np.float64))
-        tall = np.exp(np.asarray(y, np.float64))
+        keep = g[:, 0] >= 0  # the whole-plan candidate groups (learned-plan rounds carry negative ids)
+        g = g[keep]
+        pall = np.exp(m.predict_log_ms(X[keep]).astype(np.float64))
+        tall = np.exp(np.asarray(y[keep], np.float64))
         agree, regret = 0, []
         for gid in np.unique(g[:, 0]):
             sel = g[:, 0] == gid

@@ -129,16 +129,6 @@ hipError_t qs_allow_lds(const void *fn, size_t bytes)
 }
 
 // ---- host helpers shared with the planner ----
-InsBits qs_make_ins(uint64_t mask, uint64_t orm)
-{
-    InsBits ins{};
-    ins.np = 0;
-    for (int p = 0; p < 64; ++p)
-        if ((mask >> p) & 1)
-            ins.lowmask[ins.np++] = ((uint64_t)1 << p) - 1;
-    ins.orm = orm;
-    return ins;
-}
 
 // Sort the targets ascending; perm[j'] = the original matrix bit carried by sorted position j'.
 void qs_sort_targets(const int *t, int k, TPos &tp, int *perm)

@@ -21,28 +21,15 @@ template <class R> struct BT;
 template <> struct BT<double> { using C2 = double2; };
 template <> struct BT<float> { using C2 = float2; };
 
-__device__ __forceinline__ uint64_t ins0b(uint64_t g, const InsBits &s)
-{
-    for (int j = 0; j < s.np; ++j) {
-        const uint64_t lo = g & s.lowmask[j];
-        g = ((g ^ lo) << 1) | lo;
-    }
-    return g | s.orm;
-}
+__device__ __forceinline__ uint64_t ins0b(uint64_t g, const InsBits &s) { return qs_ins0(g, s); }
 
 // local index m -> global offset: bit t of m goes to global bit lpos[t]
-__device__ __forceinline__ uint64_t spread(uint32_t m, const BlockMap &bm)
-{
-    uint64_t o = 0;
-    for (int t = 0; t < bm.b; ++t)
-        o |= (uint64_t)((m >> t) & 1) << bm.lpos[t];
-    return o;
-}
+__device__ __forceinline__ uint64_t spread(uint32_t m, const BlockMap &bm) { return qs_spread(m, bm); }
 
 // LDS slot of local index m: its low 4 bits are XOR-ed with bits 4-7, 8-11 and 12, so local position p moves the
 // 16-byte slot's bank group by the unit vector of class p mod 4. A stage's threads walk one position of each class
 // with their lowest counter bits, so 16 consecutive lanes always touch 16 different bank groups.
-__device__ __forceinline__ uint32_t swz(uint32_t m) { return m ^ (((m >> 4) ^ (m >> 8) ^ (m >> 12)) & 15u); }
+__device__ __forceinline__ uint32_t swz(uint32_t m) { return blk_swz(m); }
 
 // Apply a k-qubit op (k = popcount(MASK) <= 3) to the 2^W register amplitudes x[a], a = the W stage bits. Matrix
 // bit j <-> the j-th set bit of MASK (ascending); U is 2^k x 2^k, interleaved, in the compute precision.
@@ -126,6 +113,26 @@ __device__ __forceinline__ void reg_op_dispatch(typename BT<R>::C2 *x, int mask,
     }
 }
 
+// Ops on at most two stage positions, their matrix read from U (which may be a register array of 32 values: the
+// largest such matrix, 4 x 4 complex, has 16 entries).
+template <class R, int W>
+__device__ __forceinline__ void reg_op_dispatch_k2(typename BT<R>::C2 *x, int mask, const R *U)
+{
+    static_assert(W == 4, "4-position stages");
+    switch (mask) {
+    case 1: reg_op<R, 4, 1>(x, U); break;
+    case 2: reg_op<R, 4, 2>(x, U); break;
+    case 3: reg_op<R, 4, 3>(x, U); break;
+    case 4: reg_op<R, 4, 4>(x, U); break;
+    case 5: reg_op<R, 4, 5>(x, U); break;
+    case 6: reg_op<R, 4, 6>(x, U); break;
+    case 8: reg_op<R, 4, 8>(x, U); break;
+    case 9: reg_op<R, 4, 9>(x, U); break;
+    case 10: reg_op<R, 4, 10>(x, U); break;
+    default: reg_op<R, 4, 12>(x, U); break;
+    }
+}
+
 // Byte offset in LDS of local index m. swz is linear over XOR and a group's base index m and a register offset
 // off[a] have disjoint bits, so slot(m | off[a]) = slot(m) ^ slot(off[a]): the register offsets of a stage are
 // computed once per stage (uniform) and every LDS access costs one XOR.
@@ -137,17 +144,13 @@ __device__ __forceinline__ C2 &lds_at(C2 *s, uint32_t bytes)
     return *reinterpret_cast<C2 *>(reinterpret_cast<unsigned char *>(s) + bytes);
 }
 
+// the stage's member offsets, formed by the planner for the plan's precision (slot_bytes of each member's offset)
 template <class C2, int W>
 __device__ __forceinline__ void stage_offsets(const BlkStage &stg, uint32_t *soff)
 {
 #pragma unroll
-    for (int a = 0; a < (1 << W); ++a) {
-        uint32_t o = 0;
-#pragma unroll
-        for (int j = 0; j < W; ++j)
-            o |= ((uint32_t)(a >> j) & 1u) << stg.pos[j];
-        soff[a] = slot_bytes<C2>(o);
-    }
+    for (int a = 0; a < (1 << W); ++a)
+        soff[a] = stg.soff[a];
 }
 
 // One stage: every thread takes groups of 2^W amplitudes (the W stage positions varying), applies the stage's ops
@@ -180,6 +183,77 @@ __device__ __forceinline__ void run_stage(typename BT<R>::C2 *s, const BlkStage 
         for (int a = 0; a < (1 << W); ++a)
             lds_at(s, sm ^ soff[a]) = x[a];
     }
+}
+
+// Stage pipeline for workgroups with exactly one register group per thread (2^(B-W) == NT): the LDS addresses of a
+// stage's 2^W members and its op fields are formed at the end of the previous stage, between its arithmetic and
+// the barrier (the scalar load of the record and the address arithmetic then overlap the LDS writes and the wait
+// for the other waves), so a stage starts with its reads right after the barrier. The group of thread t is t itself
+// (its bits deposited at the positions `order` lists).
+template <class R, int B, int W>
+struct StagePipe {
+    uint32_t addr[1 << W];  // LDS byte address of member a of this thread's group
+    uint32_t masks, mat_base;
+    int nops, mfma;
+    R m0[32];  // the first op's matrix when it acts on at most two positions (the pool is padded past its end)
+};
+
+template <class R, int B, int W>
+__device__ __forceinline__ void stage_fetch(StagePipe<R, B, W> &p, const BlkStage &stg, const R *__restrict__ mats)
+{
+    using C2 = typename BT<R>::C2;
+    uint32_t m = 0;
+#pragma unroll
+    for (int j = 0; j < B - W; ++j)
+        m |= (((uint32_t)threadIdx.x >> j) & 1u) << stg.order[j];
+    const uint32_t sm = slot_bytes<C2>(m);
+#pragma unroll
+    for (int a = 0; a < (1 << W); ++a)
+        p.addr[a] = sm ^ stg.soff[a];
+    p.masks = stg.masks;
+    p.mat_base = stg.mat_base;
+    p.nops = stg.nops;
+    p.mfma = stg.mfma;
+    if constexpr (W == 4) {
+        const R *u = mats + stg.mat_base;
+#pragma unroll
+        for (int i = 0; i < 32; ++i)
+            p.m0[i] = u[i];
+    }
+}
+
+// Run stage `cur` (one group per thread) and form `nxt` from record `next` meanwhile.
+template <class R, int B, int W>
+__device__ __forceinline__ void run_stage_piped(typename BT<R>::C2 *s, const StagePipe<R, B, W> &cur,
+                                                StagePipe<R, B, W> &nxt, const BlkStage &next,
+                                                const R *__restrict__ mats)
+{
+    using C2 = typename BT<R>::C2;
+    C2 x[1 << W];
+#pragma unroll
+    for (int a = 0; a < (1 << W); ++a)
+        x[a] = lds_at(s, cur.addr[a]);
+    uint32_t moff = cur.mat_base;
+    int o = 0;
+    if constexpr (W == 4) {
+        // the first op takes its matrix from the registers loaded during the previous stage, so its arithmetic can
+        // start on the first LDS reads to arrive instead of waiting for a scalar load as well
+        const int mask = (int)(cur.masks & 15u);
+        if (cur.nops > 0 && __builtin_popcount(mask) <= 2) {
+            reg_op_dispatch_k2<R, W>(x, mask, cur.m0);
+            moff += 2u << (2 * __builtin_popcount(mask));
+            o = 1;
+        }
+    }
+    for (; o < cur.nops; ++o) {
+        const int mask = (int)(cur.masks >> (4 * o)) & 15;
+        reg_op_dispatch<R, W>(x, mask, mats + moff);
+        moff += 2u << (2 * __builtin_popcount(mask));
+    }
+#pragma unroll
+    for (int a = 0; a < (1 << W); ++a)
+        lds_at(s, cur.addr[a]) = x[a];
+    stage_fetch<R, B, W>(nxt, next, mats);
 }
 
 // A complex64 4-position stage as one dense product Y = M X on the matrix cores: M is the stage's fused 16 x 16
@@ -322,17 +396,8 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, B, NT>::waves_per_eu)) void k_b
     for (int j = 0; j < PB; ++j)
         hb[j] = (uint64_t)1 << bm.lpos[LNT + j];
     const uint32_t sbase = slot_bytes<C2>(threadIdx.x);
-    auto hi_of = [&](const uint64_t *h, int it) {
-        uint64_t o = 0;
-#pragma unroll
-        for (int j = 0; j < PB; ++j)
-            if ((it >> j) & 1)
-                o |= h[j];
-        return o;
-    };
-    auto slot_of = [&](uint32_t sb, int it) {
-        return (sb ^ ((swz((uint32_t)(NT * it)) & 15u) * (uint32_t)sizeof(C2))) + (uint32_t)(NT * it * sizeof(C2));
-    };
+    auto hi_of = [&](const uint64_t *h, int it) { return blk_hi<PB>(h, it); };
+    auto slot_of = [&](uint32_t sb, int it) { return blk_phase_slot(sb, it, NT, (uint32_t)sizeof(C2)); };
     auto opaque_h = [&](uint64_t *h) {
 #pragma unroll
         for (int j = 0; j < PB; ++j) {
@@ -354,6 +419,14 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, B, NT>::waves_per_eu)) void k_b
     uint64_t blk = blockIdx.x;
     if (blk >= nblocks)
         return;
+    // one register group per thread: stage records are pipelined (complex128; the complex64 kernels, held to 128
+    // VGPRs for 4 waves per SIMD, spill more with the addresses of the next stage live and measured slower)
+    constexpr bool PIPED = (1 << (B - W)) == NT && sizeof(R) == 8;
+    StagePipe<R, B, W> spc{}, spn{};  // the running stage and the next one
+    if constexpr (PIPED) {
+        if (nstages > 0)
+            stage_fetch<R, B, W>(spc, stages[0], mats);
+    }
     uint64_t base = ins0b(blk, outer) | own;
     {
         uint64_t h[PB];
@@ -384,17 +457,36 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, B, NT>::waves_per_eu)) void k_b
             for (int it = 0; it < PER; ++it)
                 pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(pb + hi_of(h, it)));
         }
-        for (int t = 0; t < nstages; ++t) {
-            if constexpr (MF) {
-                const int slot = stages[t].mfma;
-                if (slot >= 0)
-                    run_stage_mfma<B, NT>(s, stages[t], Ml + 256 * slot);
-                else
-                    run_stage<R, B, W, NT>(s, stages[t], mats);
-            } else {
-                run_stage<R, B, W, NT>(s, stages[t], mats);
+        if constexpr (PIPED) {
+            for (int t = 0; t < nstages; ++t) {
+                // the record after the last stage is the first one again: the next block starts with it
+                const BlkStage &next = stages[t + 1 < nstages ? t + 1 : 0];
+                bool done = false;
+                if constexpr (MF) {
+                    if (spc.mfma >= 0) {
+                        run_stage_mfma<B, NT>(s, stages[t], Ml + 256 * spc.mfma);
+                        stage_fetch<R, B, W>(spn, next, mats);
+                        done = true;
+                    }
+                }
+                if (!done)
+                    run_stage_piped<R, B, W>(s, spc, spn, next, mats);
+                lds_barrier();
+                spc = spn;
             }
-            lds_barrier();
+        } else {
+            for (int t = 0; t < nstages; ++t) {
+                if constexpr (MF) {
+                    const int slot = stages[t].mfma;
+                    if (slot >= 0)
+                        run_stage_mfma<B, NT>(s, stages[t], Ml + 256 * slot);
+                    else
+                        run_stage<R, B, W, NT>(s, stages[t], mats);
+                } else {
+                    run_stage<R, B, W, NT>(s, stages[t], mats);
+                }
+                lds_barrier();
+            }
         }
         {
             uint64_t h[PB];
@@ -592,18 +684,13 @@ __device__ __forceinline__ void batch_basis(uint64_t *h, const BlockMap &bm)
 template <int PB>
 __device__ __forceinline__ uint64_t batch_hi(const uint64_t *h, int k)
 {
-    uint64_t o = 0;
-#pragma unroll
-    for (int j = 0; j < PB; ++j)
-        if ((k >> j) & 1)
-            o |= h[j];
-    return o;
+    return blk_hi<PB>(h, k);
 }
 // LDS slot (bytes) of local index tid + 256 k from sb = slot_bytes(tid): swz only folds bits into the low 4
 template <class C2>
 __device__ __forceinline__ uint32_t batch_slot(uint32_t sb, int k)
 {
-    return (sb ^ ((swz((uint32_t)(256 * k)) & 15u) * (uint32_t)sizeof(C2))) + (uint32_t)(256 * k * sizeof(C2));
+    return blk_phase_slot(sb, k, 256, (uint32_t)sizeof(C2));
 }
 __device__ __forceinline__ uint32_t opaque_u32(uint32_t v)
 {

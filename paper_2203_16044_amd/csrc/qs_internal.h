@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "qs.h"
+#include "qs_index.h"
 
 // ------------------------------------------------------------------------------------------------------------
 // error reporting (thread-local message, status code returned through the ABI)
@@ -54,29 +55,14 @@ void *qs_stage(qs_state *st, const void *host, size_t bytes);
 
 inline size_t amp_bytes(int dtype) { return dtype == QS_C128 ? 16 : 8; }
 
-struct InsBits;
-struct TPos;
-// host helpers (qs_api.hip): bit-insert mask, ascending target order, matrix in ascending target order
-InsBits qs_make_ins(uint64_t mask, uint64_t orm);
+// host helpers (qs_api.hip): ascending target order, matrix in ascending target order (qs_make_ins: qs_index.h)
 void qs_sort_targets(const int *t, int k, TPos &tp, int *perm);
 void qs_permute_matrix(const double *U, int k, const int *perm, std::vector<double> &out);
 
 // ------------------------------------------------------------------------------------------------------------
 // kernel argument blocks (passed by value)
 // ------------------------------------------------------------------------------------------------------------
-constexpr int kMaxIns = QS_MAX_K + QS_MAX_CONTROLS + 2;
-
-// Positions (ascending) at which zero bits are inserted into a group counter, then OR-ed with `orm`.
-struct InsBits {
-    int np;
-    uint64_t lowmask[kMaxIns];  // (1 << pos) - 1 for each position, ascending
-    uint64_t orm;
-};
-
-// Target bit positions (ascending) of the group members: member a sits at base + sum_j bit_j(a) << tpos[j].
-struct TPos {
-    int tpos[QS_MAX_K];
-};
+// InsBits, TPos and BlockMap (index maps) are defined in qs_index.h.
 
 // ------------------------------------------------------------------------------------------------------------
 // launchers (defined in the .hip files). All enqueue on `s` and return hipError_t of the launch.
@@ -119,13 +105,8 @@ hipError_t launch_scale(int dtype, void *psi, uint64_t dim, double f, hipStream_
 hipError_t launch_scale_dev(int dtype, void *psi, uint64_t dim, const double *norm_dev, hipStream_t s);
 
 // LDS block passes: local qubit set L (ascending global positions), stage table in device memory
-constexpr int kMaxBlockBits = 13;
 constexpr int kMaxBlockOpK = 3;
 constexpr int kStageMaxOps = 8;  // ops per stage (their masks share one 32-bit word)
-struct BlockMap {
-    int b;
-    int lpos[kMaxBlockBits];  // global bit of local bit t (ascending)
-};
 struct BlkStage {
     int pos[4];    // local positions held in registers during the stage (the first W, ascending; W = 3 or 4)
     int op_begin;  // first op of the stage in the host op table
@@ -141,7 +122,12 @@ struct BlkStage {
     // the other local positions in the order the bits of a thread's group counter fill them: the first four cover
     // the four residue classes (mod 4) of the LDS swizzle so that 16 consecutive lanes hit 16 distinct bank groups
     int order[kMaxBlockBits - 3];
+    // LDS byte offset of each register member a (bit j of a <-> pos[j]; 2^W entries used): the slot of local index
+    // sum_j bit_j(a) << pos[j] (blk_swz) times the amplitude size of the plan's precision, so that a kernel forms a
+    // member's address with one XOR against its group's slot
+    uint32_t soff[16];
 };
+
 struct BlkStageOp {  // host-side op table (planner statistics and batch relocation)
     int mask;          // stage positions the op acts on (bit j of the mask <-> pos[j], j < W); 1..3 bits set
     uint32_t mat_off;  // offset of its 2^k x 2^k matrix (bit order of the mask's positions) in real elements
@@ -225,3 +211,6 @@ int qs_cu_count();
 // Allow `fn` up to `bytes` of dynamic LDS on the current device (hipFuncSetAttribute once per device, kernel and
 // larger size; thread-safe).
 hipError_t qs_allow_lds(const void *fn, size_t bytes);
+
+// input width of a cost-model MLP (qs_mlp.hip)
+int qs_mlp_nin(const qs_mlp *m);

@@ -15,22 +15,11 @@ template <class R> struct CT;
 template <> struct CT<double> { using T = double2; };
 template <> struct CT<float> { using T = float2; };
 
-__device__ __forceinline__ uint64_t ins0(uint64_t g, const InsBits &s)
-{
-    for (int j = 0; j < s.np; ++j) {
-        uint64_t lo = g & s.lowmask[j];
-        g = ((g ^ lo) << 1) | lo;
-    }
-    return g | s.orm;
-}
+__device__ __forceinline__ uint64_t ins0(uint64_t g, const InsBits &s) { return qs_ins0(g, s); }
 
 template <int K> __device__ __forceinline__ uint64_t member_off(int a, const TPos &tp)
 {
-    uint64_t o = 0;
-#pragma unroll
-    for (int j = 0; j < K; ++j)
-        o |= (uint64_t)((a >> j) & 1) << tp.tpos[j];
-    return o;
+    return qs_member_off<K>(a, tp);
 }
 
 // Loads/stores with an optional non-temporal hint (the nontemporal builtins need native vector types).
@@ -419,8 +408,7 @@ __global__ __launch_bounds__(256) void k_diag_sparse(typename CT<R>::T *__restri
 // ---------------------------------------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t sigma_bits(uint64_t i, int lo, int hi, uint64_t smask)
 {
-    const uint64_t d = ((i >> lo) ^ (i >> hi)) & smask;
-    return i ^ (d << lo) ^ (d << hi);
+    return fsw_sigma(i, lo, hi, smask);
 }
 
 // Generic form: one thread per index; the member of each moved pair with the smaller index does the swap.
@@ -444,26 +432,10 @@ template <class C2>
 __global__ __launch_bounds__(256) void k_fswap_runs(C2 *__restrict__ psi, uint64_t total, int lo, int hi, int s,
                                                     uint64_t npairs)
 {
-    const uint64_t E = (uint64_t)1 << lo;
-    const int nmid = hi - lo - s;
     for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (uint64_t)gridDim.x * blockDim.x) {
-        const uint64_t e = t & (E - 1);
-        const uint64_t r = t >> lo;
-        const uint64_t pr = r % npairs;
-        const uint64_t o = r / npairs;
-        // pr -> (a, b), a > b, pr = a (a - 1) / 2 + b
-        uint64_t a = (uint64_t)((1.0 + sqrt(1.0 + 8.0 * (double)pr)) * 0.5);
-        while (a * (a - 1) / 2 > pr)
-            --a;
-        while ((a + 1) * a / 2 <= pr)
-            ++a;
-        const uint64_t b = pr - a * (a - 1) / 2;
-        const uint64_t mid = o & (((uint64_t)1 << nmid) - 1);
-        const uint64_t top = o >> nmid;
-        const uint64_t common = e | (mid << (lo + s)) | (top << (hi + s));
-        const uint64_t i1 = common | (b << lo) | (a << hi);
-        const uint64_t i2 = common | (a << lo) | (b << hi);
+        uint64_t i1, i2;
+        fsw_runs_pair(t, lo, hi, s, npairs, i1, i2);
         const C2 x1 = psi[i1], x2 = psi[i2];
         psi[i1] = x2;
         psi[i2] = x1;
@@ -484,44 +456,28 @@ __global__ __launch_bounds__(256) void k_fswap_lds(C2 *__restrict__ psi, uint64_
     extern __shared__ __align__(16) unsigned char smem_raw[];
     C2 *X = reinterpret_cast<C2 *>(smem_raw);
     C2 *Y = X + (size_t)T * rstride;
-    const int nmid = hi - lo - s;
     const int nel = T * row;
+    (void)ntile;
     for (uint64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
-        const uint64_t pr = w % npairs_t;
-        const uint64_t o = w / npairs_t;
-        uint64_t I = (uint64_t)((1.0 + sqrt(1.0 + 8.0 * (double)pr)) * 0.5) - 1;  // pr = I (I + 1) / 2 + J, J <= I
-        while (I * (I + 1) / 2 > pr)
-            --I;
-        while ((I + 1) * (I + 2) / 2 <= pr)
-            ++I;
-        const uint64_t J = pr - I * (I + 1) / 2;
-        (void)ntile;
-        const uint64_t mid = o & (((uint64_t)1 << nmid) - 1);
-        const uint64_t top = o >> nmid;
-        const uint64_t common = (mid << (lo + s)) | (top << (hi + s));
+        uint64_t I, J, common;
+        fsw_lds_item(w, lo, hi, s, npairs_t, I, J, common);
         // X: rows A in I-range, columns B in J-range.  Y: rows A in J-range, columns B in I-range.
         for (int u = threadIdx.x; u < nel; u += blockDim.x) {
             const int ra = u / row, rc = u % row;  // rc = cb * E + e
-            const uint64_t cb = rc / E, e = rc % E;
-            const uint64_t ix = common | e | ((J * T + cb) << lo) | ((I * T + ra) << hi);
-            X[ra * rstride + rc] = psi[ix];
-            if (I != J) {
-                const uint64_t iy = common | e | ((I * T + cb) << lo) | ((J * T + ra) << hi);
-                Y[ra * rstride + rc] = psi[iy];
-            }
+            X[ra * rstride + rc] = psi[fsw_lds_x(common, I, J, ra, rc, lo, hi, TS)];
+            if (I != J)
+                Y[ra * rstride + rc] = psi[fsw_lds_y(common, I, J, ra, rc, lo, hi, TS)];
         }
         lds_barrier();
         for (int u = threadIdx.x; u < nel; u += blockDim.x) {
             const int ra = u / row, rc = u % row;
             const int cb = rc / E, e = rc % E;
             // position (A = I*T + ra, B = J*T + cb) receives the old value at (A = J*T + cb, B = I*T + ra)
-            const uint64_t ix = common | (uint64_t)e | ((J * T + cb) << lo) | ((I * T + ra) << hi);
             if (I != J) {
-                psi[ix] = Y[cb * rstride + ra * E + e];
-                const uint64_t iy = common | (uint64_t)e | ((I * T + cb) << lo) | ((J * T + ra) << hi);
-                psi[iy] = X[cb * rstride + ra * E + e];
+                psi[fsw_lds_x(common, I, J, ra, rc, lo, hi, TS)] = Y[cb * rstride + ra * E + e];
+                psi[fsw_lds_y(common, I, J, ra, rc, lo, hi, TS)] = X[cb * rstride + ra * E + e];
             } else if (ra != cb) {
-                psi[ix] = X[cb * rstride + ra * E + e];
+                psi[fsw_lds_x(common, I, J, ra, rc, lo, hi, TS)] = X[cb * rstride + ra * E + e];
             }
         }
         lds_barrier();
@@ -541,24 +497,21 @@ __global__ __launch_bounds__(256) void k_fswap_wide(C2 *__restrict__ psi, uint64
     C2 *X = reinterpret_cast<C2 *>(smem_raw);
     const int R = 1 << (x + s + lo);  // amplitudes per row
     const int RP = R + 1;             // padded LDS row
-    const int S = 1 << s;
-    const int nel = S * R;
-    const int nmid_hi = hi - lo - s - x;  // mid bits above the carried ones
-    const int bshift = lo, bmask = S - 1;
+    const int nel = (1 << s) * R;
     for (uint64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
-        const uint64_t midh = w & (((uint64_t)1 << nmid_hi) - 1);
-        const uint64_t top = w >> nmid_hi;
-        const uint64_t base = (top << (hi + s)) | (midh << (lo + s + x));
+        const uint64_t base = fsw_wide_base(w, lo, hi, s, x);
         for (int u = threadIdx.x; u < nel; u += blockDim.x) {
-            const int a = u / R, c = u - a * R;
-            X[a * RP + c] = psi[base | ((uint64_t)a << hi) | (uint64_t)c];
+            uint64_t g;
+            int a, c;
+            fsw_wide_load(base, u, lo, hi, s, x, g, a, c);
+            X[a * RP + c] = psi[g];
         }
         lds_barrier();
         for (int u = threadIdx.x; u < nel; u += blockDim.x) {
-            const int b = u / R, c = u - b * R;
-            const int a = (c >> bshift) & bmask;                       // B field of the destination = source row
-            const int cs = (c & ~(bmask << bshift)) | (b << bshift);  // source column: B field = b
-            psi[base | ((uint64_t)b << hi) | (uint64_t)c] = X[a * RP + cs];
+            uint64_t g;
+            int a, cs;
+            fsw_wide_store(base, u, lo, hi, s, x, g, a, cs);
+            psi[g] = X[a * RP + cs];
         }
         lds_barrier();
     }
@@ -886,57 +839,31 @@ template <class C2>
 hipError_t fswap_t(void *psi_, int n, int lo, int hi, int s_, hipStream_t s)
 {
     C2 *psi = (C2 *)psi_;
-    const uint64_t dim = (uint64_t)1 << n;
-    const int sz = (int)sizeof(C2);
-    const uint64_t smask = ((uint64_t)1 << s_) - 1;
-    const int run_bytes = (1 << lo) * sz;
-    if (run_bytes >= 256) {
-        const uint64_t S = (uint64_t)1 << s_;
-        const uint64_t npairs = S * (S - 1) / 2;
-        const uint64_t outer = (uint64_t)1 << (n - 2 * s_ - lo);
-        const uint64_t total = outer * npairs * ((uint64_t)1 << lo);
-        hipLaunchKernelGGL(k_fswap_runs<C2>, dim3(grid_for(total, 256)), dim3(256), 0, s, psi, total, lo, hi, s_,
-                           npairs);
-        return hipGetLastError();
-    }
-    if (((size_t)1 << (2 * s_ + lo)) * sz <= 32768) {
-        // wide rows whenever the 2^s x 2^s tile of runs fits 32 KiB (larger tiles with short rows measured slower
-        // than the sub-tile form below): carry x low mid bits so that a tile holds about 32 KiB (or all mid bits
-        // if fewer)
-        const int nmid = hi - lo - s_;
-        const int tile_log = (sz == 16 ? 11 : 12);
-        int x = tile_log - 2 * s_ - lo;
-        if (x > nmid)
-            x = nmid;
-        if (x < 0)
-            x = 0;
-        const uint64_t nwork = (uint64_t)1 << (n - 2 * s_ - lo - x);
-        const size_t shm = (size_t)(1 << s_) * ((1 << (x + s_ + lo)) + 1) * sz;
-        const unsigned g = (unsigned)(nwork < (1u << 20) ? nwork : (1u << 20));
-        hipLaunchKernelGGL(k_fswap_wide<C2>, dim3(g), dim3(256), shm, s, psi, nwork, lo, hi, s_, x);
-        return hipGetLastError();
-    }
-    // LDS sub-tiles: largest T = 2^ts <= 2^s with T*T*2^lo amplitudes <= 16 KiB per tile
-    int ts = s_;
-    while (ts > 0 && ((size_t)1 << (2 * ts + lo)) * sz > 16384)
-        --ts;
-    if ((1 << (ts + lo)) * sz >= 128 && ts >= 2) {
-        const int T = 1 << ts;
-        const int ntile = 1 << (s_ - ts);
-        const uint64_t npt = (uint64_t)ntile * (ntile + 1) / 2;
-        const uint64_t outer = (uint64_t)1 << (n - 2 * s_ - lo);
-        const uint64_t nwork = outer * npt;
-        const size_t shm = 2 * (size_t)T * (T * (1 << lo) + 1) * sz;
-        const unsigned g = (unsigned)(nwork < (1u << 20) ? nwork : (1u << 20));
-        switch (ts) {
-        case 2: hipLaunchKernelGGL((k_fswap_lds<C2, 2>), dim3(g), dim3(256), shm, s, psi, nwork, lo, hi, s_, ntile, npt); break;
-        case 3: hipLaunchKernelGGL((k_fswap_lds<C2, 3>), dim3(g), dim3(256), shm, s, psi, nwork, lo, hi, s_, ntile, npt); break;
-        case 4: hipLaunchKernelGGL((k_fswap_lds<C2, 4>), dim3(g), dim3(256), shm, s, psi, nwork, lo, hi, s_, ntile, npt); break;
-        default: hipLaunchKernelGGL((k_fswap_lds<C2, 5>), dim3(g), dim3(256), shm, s, psi, nwork, lo, hi, s_, ntile, npt); break;
+    const FswPlan f = fsw_plan(n, lo, hi, s_, (int)sizeof(C2));
+    const unsigned g = (unsigned)(f.nwork < (1u << 20) ? f.nwork : (1u << 20));
+    switch (f.form) {
+    case FSW_RUNS:
+        hipLaunchKernelGGL(k_fswap_runs<C2>, dim3(grid_for(f.nwork, 256)), dim3(256), 0, s, psi, f.nwork, lo, hi, s_,
+                           f.npairs);
+        break;
+    case FSW_WIDE:
+        hipLaunchKernelGGL(k_fswap_wide<C2>, dim3(g), dim3(256), f.shm, s, psi, f.nwork, lo, hi, s_, f.x);
+        break;
+    case FSW_LDS: {
+        const int ntile = 1 << (s_ - f.ts);
+        switch (f.ts) {
+        case 2: hipLaunchKernelGGL((k_fswap_lds<C2, 2>), dim3(g), dim3(256), f.shm, s, psi, f.nwork, lo, hi, s_, ntile, f.npairs); break;
+        case 3: hipLaunchKernelGGL((k_fswap_lds<C2, 3>), dim3(g), dim3(256), f.shm, s, psi, f.nwork, lo, hi, s_, ntile, f.npairs); break;
+        case 4: hipLaunchKernelGGL((k_fswap_lds<C2, 4>), dim3(g), dim3(256), f.shm, s, psi, f.nwork, lo, hi, s_, ntile, f.npairs); break;
+        default: hipLaunchKernelGGL((k_fswap_lds<C2, 5>), dim3(g), dim3(256), f.shm, s, psi, f.nwork, lo, hi, s_, ntile, f.npairs); break;
         }
-        return hipGetLastError();
+        break;
     }
-    hipLaunchKernelGGL(k_fswap_pairs<C2>, dim3(grid_for(dim, 256)), dim3(256), 0, s, psi, dim, lo, hi, smask);
+    default:
+        hipLaunchKernelGGL(k_fswap_pairs<C2>, dim3(grid_for(f.nwork, 256)), dim3(256), 0, s, psi, f.nwork, lo, hi,
+                           ((uint64_t)1 << s_) - 1);
+        break;
+    }
     return hipGetLastError();
 }
 }  // namespace

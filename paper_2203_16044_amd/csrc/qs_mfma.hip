@@ -45,23 +45,9 @@ template <> struct MF<float> {
     static __device__ __forceinline__ int row_comp(int i) { return i & 1; }
 };
 
-__device__ __forceinline__ uint64_t ins0m(uint64_t g, const InsBits &s)
-{
-    for (int j = 0; j < s.np; ++j) {
-        uint64_t lo = g & s.lowmask[j];
-        g = ((g ^ lo) << 1) | lo;
-    }
-    return g | s.orm;
-}
+__device__ __forceinline__ uint64_t ins0m(uint64_t g, const InsBits &s) { return qs_ins0(g, s); }
 
-template <int K> __device__ __forceinline__ uint64_t moff(int a, const TPos &tp)
-{
-    uint64_t o = 0;
-#pragma unroll
-    for (int j = 0; j < K; ++j)
-        o |= (uint64_t)((a >> j) & 1) << tp.tpos[j];
-    return o;
-}
+template <int K> __device__ __forceinline__ uint64_t moff(int a, const TPos &tp) { return qs_member_off<K>(a, tp); }
 
 template <class R, int K>
 __global__ __launch_bounds__(256) void k_dense_mfma(typename MF<R>::C2 *__restrict__ psi, uint64_t ngroups,

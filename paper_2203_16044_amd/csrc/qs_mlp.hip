@@ -270,6 +270,12 @@ QS_API int qs_mlp_get_params(qs_mlp *M, float *host)
     return QS_OK;
 }
 
+}  // extern "C"
+
+int qs_mlp_nin(const qs_mlp *m) { return m ? m->d.nin : 0; }
+
+extern "C" {
+
 QS_API int qs_mlp_predict(qs_mlp *M, const float *X, int B, float *Y)
 {
     qs_clear_error();

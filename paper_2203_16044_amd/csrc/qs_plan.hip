@@ -11,6 +11,7 @@
 // placed. Fused-swaps and gates too large for a pass run as passes of their own. The plan's final state equals
 // the circuit's (up to rounding): no qubit relabelling is left behind.
 #include <algorithm>
+#include <cmath>
 #include <complex>
 #include <cstring>
 #include <new>
@@ -236,6 +237,27 @@ struct Former {
     // gates (fewest qubits on ties); the pass is the candidate taking the most gates once none can grow.
     Cand form_pass() const
     {
+        std::vector<Cand> leaves;
+        return form_pass(leaves, 1);
+    }
+    // As above; `leaves` also receives up to `keep` of the final candidates (those that could not grow), most gates
+    // first (fewest qubits on ties), distinct local sets: the alternatives a cost model may prefer.
+    Cand form_pass(std::vector<Cand> &leaves, int keep) const
+    {
+        leaves.clear();
+        auto offer = [&](const Cand &x) {
+            if (x.gates.empty() || keep <= 0)
+                return;
+            for (const Cand &u : leaves)
+                if (u.L == x.L && u.gates.size() == x.gates.size())
+                    return;
+            leaves.push_back(x);
+            std::stable_sort(leaves.begin(), leaves.end(), [](const Cand &a, const Cand &b2) {
+                return a.gates.size() != b2.gates.size() ? a.gates.size() > b2.gates.size() : a.L.size() < b2.L.size();
+            });
+            if ((int)leaves.size() > keep)
+                leaves.pop_back();
+        };
         Cand s0;
         for (int q = 0; q < w && q < c.n; ++q)
             s0.L.push_back(q);
@@ -255,8 +277,10 @@ struct Former {
                         bestnew = nw;
                     }
                 }
-                if (best < 0)
+                if (best < 0) {
+                    offer(s0);
                     return s0;
+                }
                 for (int q : c.gates[best].q)
                     if (std::find(s0.L.begin(), s0.L.end(), q) == s0.L.end())
                         s0.L.push_back(q);
@@ -286,8 +310,11 @@ struct Former {
                     nxt.push_back(std::move(t));
                     grown = true;
                 }
-                if (!grown && st.gates.size() > best.gates.size())
-                    best = st;
+                if (!grown) {
+                    offer(st);
+                    if (st.gates.size() > best.gates.size())
+                        best = st;
+                }
             }
             std::stable_sort(nxt.begin(), nxt.end(), [](const Cand &x, const Cand &y) {
                 return x.gates.size() != y.gates.size() ? x.gates.size() > y.gates.size() : x.L.size() < y.L.size();
@@ -426,7 +453,9 @@ int upload_tables(qs_plan *P)
     P->dstages = static_cast<BlkStage *>(p);
     if (!P->stages.empty())
         QS_HIP(hipMemcpy(P->dstages, P->stages.data(), P->stages.size() * sizeof(BlkStage), hipMemcpyHostToDevice));
-    const size_t npool = std::max<size_t>(P->pool.size(), 2);
+    // 64 zero elements past the end: a block kernel loads 32 elements from the start of a stage's first matrix
+    // whatever its size
+    const size_t npool = P->pool.size() + 64;
     const size_t esz = P->dtype == QS_C128 ? sizeof(double) : sizeof(float);
     p = nullptr;
     e = hipMalloc(&p, npool * esz);
@@ -434,12 +463,13 @@ int upload_tables(qs_plan *P)
         return qs_hip_fail(e, "hipMalloc(plan matrices)");
     P->dpool = p;
     if (P->dtype == QS_C128) {
-        if (!P->pool.empty())
-            QS_HIP(hipMemcpy(P->dpool, P->pool.data(), P->pool.size() * sizeof(double), hipMemcpyHostToDevice));
+        std::vector<double> d(P->pool.begin(), P->pool.end());
+        d.resize(npool, 0.0);
+        QS_HIP(hipMemcpy(P->dpool, d.data(), d.size() * sizeof(double), hipMemcpyHostToDevice));
     } else {
         std::vector<float> f(P->pool.begin(), P->pool.end());
-        if (!f.empty())
-            QS_HIP(hipMemcpy(P->dpool, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+        f.resize(npool, 0.0f);
+        QS_HIP(hipMemcpy(P->dpool, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
     }
     return QS_OK;
 }
@@ -636,18 +666,371 @@ QS_API int qs_circuit_run(qs_state *st, const qs_circuit *c)
 }  // extern "C"
 
 namespace {
-int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, int stage_width);
+int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, int stage_width,
+                const qs_plan_model *model);
 }
 
 extern "C" QS_API int qs_plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts)
 {
     qs_clear_error();
-    return plan_create(out, c, opts, qs_tunables().block_stage_width);
+    return plan_create(out, c, opts, qs_tunables().block_stage_width, nullptr);
+}
+
+extern "C" QS_API int qs_plan_create_learned(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts,
+                                             const qs_plan_model *m)
+{
+    qs_clear_error();
+    if (!out || !c || !opts || !m || !m->model || !m->mean || !m->std || !m->shape_bits || !m->shape_low)
+        return qs_fail(QS_EINVAL, "qs_plan_create_learned: NULL argument");
+    *out = nullptr;
+    if (opts->mode != QS_PLAN_BLOCK)
+        return qs_fail(QS_EINVAL, "qs_plan_create_learned: mode must be QS_PLAN_BLOCK");
+    if (m->nshapes < 1 || m->nshapes > 16 || m->per_shape < 1 || m->per_shape > 8 || m->gate_slack < 0)
+        return qs_fail(QS_EINVAL, "qs_plan_create_learned: nshapes = %d, per_shape = %d or gate_slack = %d out of range",
+                       m->nshapes, m->per_shape, m->gate_slack);
+    for (int i = 0; i < m->nshapes; ++i)
+        if (m->shape_bits[i] < 10 || m->shape_bits[i] > kMaxBlockBits || m->shape_bits[i] > c->n ||
+            m->shape_low[i] < 0 || m->shape_low[i] > m->shape_bits[i])
+            return qs_fail(QS_EINVAL, "qs_plan_create_learned: shape %d (%d bits, %d low) invalid for %d qubits", i,
+                           m->shape_bits[i], m->shape_low[i], c->n);
+    if (qs_mlp_nin(m->model) != QS_PLAN_NFEAT)
+        return qs_fail(QS_EINVAL, "qs_plan_create_learned: the model takes %d inputs, not %d",
+                       qs_mlp_nin(m->model), QS_PLAN_NFEAT);
+    for (int j = 0; j < QS_PLAN_NFEAT; ++j)
+        if (!(m->std[j] > 0.0f))
+            return qs_fail(QS_EINVAL, "qs_plan_create_learned: std[%d] is not positive", j);
+    qs_plan_opts o = *opts;
+    o.block_bits = m->shape_bits[0];
+    o.low_bits = m->shape_low[0];
+    return plan_create(out, c, &o, 4, m);
 }
 
 namespace {
-int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, int stage_width)
+int append_pass(qs_plan *P, const qs_circuit *c, int mode, const std::vector<int> &L, const std::vector<int> &gs, int b,
+                int stage_width);
+
+struct PassSpec {
+    std::vector<int> L;      // local set (empty: a single non-blockable gate)
+    std::vector<int> gates;  // circuit gates in application order
+    int b;                   // block bits of the pass
+};
+
+// Pass formation driven by the cost model: at every step, candidate passes of every shape are built (as the plan
+// would run them), scored by predicted time per circuit gate, and the cheapest is kept. Gates that no block can
+// carry are emitted on their own, as the greedy formation does.
+int learned_passes(const qs_circuit &c, int dtype, const qs_plan_model &M, int stage_width, std::vector<PassSpec> &out)
 {
+    const int beam = std::max(1, qs_tunables().plan_beam.load());
+    std::vector<Former> F;
+    for (int i = 0; i < M.nshapes; ++i)
+        F.emplace_back(c, M.shape_bits[i], M.shape_low[i], kMaxBlockOpK, beam);
+    std::vector<size_t> head(c.n, 0);
+    size_t remaining = c.gates.size();
+    qs_plan tmp;
+    tmp.n = c.n;
+    tmp.dtype = dtype;
+    tmp.mode = QS_PLAN_BLOCK;
+    std::vector<Former::Cand> leaves, cands;
+    std::vector<int> cand_b;
+    std::vector<float> X, Y;
+    while (remaining) {
+        cands.clear();
+        cand_b.clear();
+        for (int i = 0; i < M.nshapes; ++i) {
+            F[i].head = head;
+            F[i].form_pass(leaves, M.per_shape);
+            for (Former::Cand &l : leaves) {
+                cands.push_back(std::move(l));
+                cand_b.push_back(M.shape_bits[i]);
+            }
+        }
+        if (cands.empty()) {  // nothing blockable is ready: the earliest ready gate runs on its own
+            std::vector<int> f = F[0].front(head);
+            if (f.empty())
+                break;  // cannot happen for a well-formed circuit
+            const int g = f[0];
+            for (int q : c.gates[g].q)
+                ++head[q];
+            --remaining;
+            out.push_back({std::vector<int>(), std::vector<int>{g}, 0});
+            continue;
+        }
+        // candidates that carry too few gates are dropped before the model is asked
+        {
+            size_t most = 0;
+            for (const Former::Cand &x : cands)
+                most = std::max(most, x.gates.size());
+            size_t keep = 0;
+            for (size_t k = 0; k < cands.size(); ++k)
+                if (cands[k].gates.size() + (size_t)M.gate_slack >= most) {
+                    if (keep != k) {
+                        cands[keep] = std::move(cands[k]);
+                        cand_b[keep] = cand_b[k];
+                    }
+                    ++keep;
+                }
+            cands.resize(keep);
+            cand_b.resize(keep);
+        }
+        int pick = 0;
+        if (cands.size() > 1) {
+            const int nc = (int)cands.size();
+            X.assign((size_t)nc * QS_PLAN_NFEAT, 0.0f);
+            Y.assign(nc, 0.0f);
+            for (int k = 0; k < nc; ++k) {
+                std::vector<int> L = cands[k].L;
+                std::sort(L.begin(), L.end());
+                tmp.passes.clear();
+                tmp.stages.clear();
+                tmp.sops.clear();
+                tmp.pool.clear();
+                if (int rc = append_pass(&tmp, &c, QS_PLAN_BLOCK, L, cands[k].gates, cand_b[k], stage_width))
+                    return rc;
+                float *x = &X[(size_t)k * QS_PLAN_NFEAT];
+                if (int rc = qs_plan_features(&tmp, 0, x))
+                    return rc;
+                for (int j = 0; j < QS_PLAN_NFEAT; ++j)
+                    x[j] = (x[j] - M.mean[j]) / M.std[j];
+            }
+            for (int k0 = 0; k0 < nc; k0 += 4096)
+                if (int rc = qs_mlp_predict(M.model, &X[(size_t)k0 * QS_PLAN_NFEAT], std::min(4096, nc - k0), &Y[k0]))
+                    return rc;
+            double best = 0.0;
+            for (int k = 0; k < nc; ++k) {
+                const double per_gate = std::exp((double)Y[k]) / (double)cands[k].gates.size();
+                if (k == 0 || per_gate < best) {
+                    best = per_gate;
+                    pick = k;
+                }
+            }
+        }
+        Former::Cand &ch = cands[pick];
+        std::sort(ch.L.begin(), ch.L.end());
+        head = ch.h;
+        remaining -= ch.gates.size();
+        out.push_back({ch.L, ch.gates, cand_b[pick]});
+    }
+    return QS_OK;
+}
+
+// Append one pass to P: a single non-blockable gate (L empty), a fused dense block (FUSE mode) or an LDS block pass
+// over the local set L (padded to b qubits) applying `gs` in the given order.
+int append_pass(qs_plan *P, const qs_circuit *c, int mode, const std::vector<int> &L, const std::vector<int> &gs, int b,
+                int stage_width)
+{
+    PlanPass pp;
+    pp.ngates = (int)gs.size();
+    if (L.empty()) {  // a single non-blockable gate
+        const PG &g = c->gates[gs[0]];
+        pp.order.assign(1, g.raw);
+        if (g.kind == 1) {
+            pp.type = 2;
+            const RawOp &r = c->raw[g.raw];
+            pp.p = std::min(r.p, r.q);
+            pp.q = std::max(r.p, r.q);
+            pp.s = r.s;
+        } else if (g.kind == 2 || (int)g.q.size() > QS_MAX_K) {
+            pp.type = 3;
+            pp.raw = g.raw;
+        } else {
+            make_dense_pass(P, g, pp);
+        }
+        P->passes.push_back(std::move(pp));
+        return QS_OK;
+    }
+    if (mode == QS_PLAN_FUSE) {
+        PG blk;
+        blk.q = L;
+        const int D = 1 << L.size();
+        blk.m.assign((size_t)D * D, cd(0, 0));
+        for (int a = 0; a < D; ++a)
+            blk.m[(size_t)a * D + a] = cd(1, 0);
+        for (int gi : gs) {
+            blk.m = matmul(embed(c->gates[gi], L), blk.m, D);
+            pp.order.push_back(c->gates[gi].raw);
+        }
+        make_dense_pass(P, blk, pp);
+        P->nfused_ops += 1;
+        P->passes.push_back(std::move(pp));
+        return QS_OK;
+    }
+    // LDS block pass
+    pp.type = 0;
+    pp.b = b;
+    // pad L to b qubits with unused low qubits (any qubits work; low ones keep segments long)
+    std::vector<int> LL = L;
+    for (int q = 0; (int)LL.size() < b && q < c->n; ++q)
+        if (std::find(LL.begin(), LL.end(), q) == LL.end())
+            LL.push_back(q);
+    std::sort(LL.begin(), LL.end());
+    pp.lmask = 0;
+    pp.bm.b = b;
+    for (int t = 0; t < b; ++t) {
+        pp.bm.lpos[t] = LL[t];
+        pp.lmask |= (uint64_t)1 << LL[t];
+    }
+    std::vector<PG> fused = fuse_pass(*c, gs);
+    pp.nops = (int)fused.size();
+    // local positions of every fused op (ascending, as its sorted matrix expects)
+    std::vector<PG> sorted_ops;
+    std::vector<uint32_t> posmask;
+    for (const PG &f : fused) {
+        sorted_ops.push_back(sorted_gate(f));
+        uint32_t pm = 0;
+        for (int q : sorted_ops.back().q)
+            pm |= 1u << (int)(std::find(LL.begin(), LL.end(), q) - LL.begin());
+        posmask.push_back(pm);
+    }
+    // stages of at most W positions (W = 3 only where a 512-thread kernel exists): repeatedly take ready ops
+    // (every earlier op sharing a position placed) that keep the stage within W positions, fewest new first
+    const int W = (stage_width == 3 && (b == 12 || b == 13)) ? 3 : 4;
+    pp.sw = W;
+    const int nf = (int)fused.size();
+    std::vector<char> placed(nf, 0);
+    int left = nf;
+    pp.stage_begin = (int)P->stages.size();
+    std::vector<std::vector<int>> stage_members;  // fused-op indices of each stage of this pass, in order
+    while (left) {
+        uint32_t S = 0;
+        std::vector<int> members;
+        while ((int)members.size() < kStageMaxOps) {
+            int best = -1, bestnew = 99;
+            for (int i = 0; i < nf; ++i) {
+                if (placed[i])
+                    continue;
+                bool rdy = true;
+                for (int j = 0; j < i && rdy; ++j)
+                    if (!placed[j] && (posmask[j] & posmask[i]))
+                        rdy = false;
+                if (!rdy)
+                    continue;
+                const int nw = __builtin_popcount(posmask[i] & ~S);
+                if (__builtin_popcount(S | posmask[i]) <= W && nw < bestnew) {
+                    best = i;
+                    bestnew = nw;
+                }
+            }
+            if (best < 0)
+                break;
+            placed[best] = 1;
+            --left;
+            S |= posmask[best];
+            members.push_back(best);
+        }
+        for (int p = 0; __builtin_popcount(S) < W && p < b; ++p)
+            S |= 1u << p;  // pad with unused positions
+        BlkStage stg{};
+        int j = 0;
+        for (int p = 0; p < b; ++p)
+            if ((S >> p) & 1)
+                stg.pos[j++] = p;
+        // group-counter bit order over the other positions: one position of each residue class mod 4 first
+        {
+            std::vector<int> rest;
+            for (int p = 0; p < b; ++p)
+                if (!((S >> p) & 1))
+                    rest.push_back(p);
+            std::vector<int> ord;
+            for (int cls = 0; cls < 4; ++cls)
+                for (size_t r = 0; r < rest.size(); ++r)
+                    if (rest[r] % 4 == cls) {
+                        ord.push_back(rest[r]);
+                        rest.erase(rest.begin() + r);
+                        break;
+                    }
+            ord.insert(ord.end(), rest.begin(), rest.end());
+            for (int t = 0; t < b - W; ++t)
+                stg.order[t] = ord[t];
+        }
+        for (int a = 0; a < (1 << W); ++a) {
+            uint32_t o = 0;
+            for (int jj = 0; jj < W; ++jj)
+                o |= ((uint32_t)(a >> jj) & 1u) << stg.pos[jj];
+            stg.soff[a] = blk_swz(o) * (uint32_t)amp_bytes(P->dtype);
+        }
+        stage_members.push_back(members);
+        stg.op_begin = (int)P->sops.size();
+        stg.nops = (int)members.size();
+        stg.mat_base = (uint32_t)P->pool.size();
+        for (size_t o = 0; o < members.size(); ++o) {
+            const int i = members[o];
+            BlkStageOp so{};
+            for (int t = 0; t < W; ++t)
+                if ((posmask[i] >> stg.pos[t]) & 1)
+                    so.mask |= 1 << t;
+            so.mat_off = (uint32_t)P->pool.size();
+            push_matrix(P->pool, sorted_ops[i].m);
+            P->sops.push_back(so);
+            stg.masks |= (uint32_t)so.mask << (4 * o);
+        }
+        stg.mfma = -1;
+        P->stages.push_back(stg);
+    }
+    pp.nstages = (int)P->stages.size() - pp.stage_begin;
+    for (const std::vector<int> &members : stage_members)
+        for (int i : members)
+            for (int gi : fused[i].members)
+                pp.order.push_back(c->gates[gi].raw);
+    // complex64: the pass's stages with the most arithmetic (at least that of mfma_stage_ops 2-qubit ops; up to
+    // kMaxMfmaStages, the LDS they may take) become dense 16 x 16 products on the matrix cores. Op by op a
+    // k-qubit op costs 2^(k+2) FMAs per amplitude; the dense product costs 64, but FP32 MFMA runs at twice the
+    // FP32 FMA rate, so it pays from about three 2-qubit ops' worth on. The product of the stage's ops is formed
+    // here in FP64 (op o first), with stage index bit j <-> pos[j] as in the per-op masks.
+    const int mfma_ops = qs_tunables().mfma_stage_ops;
+    if (P->dtype == QS_C64 && W == 4 && mfma_ops > 0) {
+        auto weight = [&](int t) {  // FMAs per amplitude of stage t, op by op
+            const BlkStage &st = P->stages[pp.stage_begin + t];
+            int w = 0;
+            for (int o = 0; o < st.nops; ++o)
+                w += 4 << __builtin_popcount((st.masks >> (4 * o)) & 15u);
+            return w;
+        };
+        std::vector<int> pick;
+        for (int t = 0; t < pp.nstages; ++t)
+            if (weight(t) >= 16 * mfma_ops)
+                pick.push_back(t);
+        std::stable_sort(pick.begin(), pick.end(), [&](int x, int y) { return weight(x) > weight(y); });
+        if ((int)pick.size() > kMaxMfmaStages)
+            pick.resize(kMaxMfmaStages);
+        std::sort(pick.begin(), pick.end());
+        for (int t : pick) {
+            BlkStage &st = P->stages[pp.stage_begin + t];
+            std::vector<cd> M(256, cd(0, 0));
+            for (int r = 0; r < 16; ++r)
+                M[r * 16 + r] = 1;
+            for (int o = 0; o < st.nops; ++o) {
+                const int mk = (int)((st.masks >> (4 * o)) & 15u);
+                const std::vector<cd> &U = sorted_ops[stage_members[t][o]].m;
+                const int D = 1 << __builtin_popcount(mk);
+                auto sub = [mk](int x) {  // bits of x at the op's positions, packed (j-th set bit -> bit j)
+                    int v = 0, jj = 0;
+                    for (int q = 0; q < 4; ++q)
+                        if ((mk >> q) & 1)
+                            v |= ((x >> q) & 1) << jj++;
+                    return v;
+                };
+                std::vector<cd> E(256, cd(0, 0));
+                for (int r = 0; r < 16; ++r)
+                    for (int c2 = 0; c2 < 16; ++c2)
+                        if ((r & ~mk) == (c2 & ~mk))
+                            E[r * 16 + c2] = U[sub(r) * D + sub(c2)];
+                M = matmul(E, M, 16);
+            }
+            st.mfma = pp.mf.n;
+            pp.mf.off[pp.mf.n++] = (uint32_t)P->pool.size();
+            push_matrix(P->pool, M);
+        }
+    }
+    P->nfused_ops += pp.nops;
+    P->passes.push_back(std::move(pp));
+    return QS_OK;
+}
+
+int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, int stage_width,
+                const qs_plan_model *model)
+{
+    if (model && c && c->n < 8)
+        return qs_fail(QS_EINVAL, "qs_plan_create_learned: block passes need at least 8 qubits");
     if (!out || !c || !opts)
         return qs_fail(QS_EINVAL, "qs_plan_create: NULL argument");
     *out = nullptr;
@@ -682,213 +1065,25 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
     P->mode = mode;
     P->raw = c->raw;
     const int maxq = mode == QS_PLAN_BLOCK ? kMaxBlockOpK : b;
-    Former F(*c, b, w, maxq, qs_tunables().plan_beam);
-    std::vector<std::pair<std::vector<int>, std::vector<int>>> passes;
-    std::vector<int> singles;
-    F.run(passes, singles);
-    for (auto &pr : passes) {
-        const std::vector<int> &L = pr.first;
-        const std::vector<int> &gs = pr.second;
-        PlanPass pp;
-        pp.ngates = (int)gs.size();
-        if (L.empty()) {  // a single non-blockable gate
-            const PG &g = c->gates[gs[0]];
-            pp.order.assign(1, g.raw);
-            if (g.kind == 1) {
-                pp.type = 2;
-                const RawOp &r = c->raw[g.raw];
-                pp.p = std::min(r.p, r.q);
-                pp.q = std::max(r.p, r.q);
-                pp.s = r.s;
-            } else if (g.kind == 2 || (int)g.q.size() > QS_MAX_K) {
-                pp.type = 3;
-                pp.raw = g.raw;
-            } else {
-                make_dense_pass(P, g, pp);
-            }
-            P->passes.push_back(std::move(pp));
-            continue;
+    std::vector<PassSpec> passes;
+    if (model) {
+        if (int rc = learned_passes(*c, P->dtype, *model, stage_width, passes)) {
+            delete P;
+            return rc;
         }
-        if (mode == QS_PLAN_FUSE) {
-            PG blk;
-            blk.q = L;
-            const int D = 1 << L.size();
-            blk.m.assign((size_t)D * D, cd(0, 0));
-            for (int a = 0; a < D; ++a)
-                blk.m[(size_t)a * D + a] = cd(1, 0);
-            for (int gi : gs) {
-                blk.m = matmul(embed(c->gates[gi], L), blk.m, D);
-                pp.order.push_back(c->gates[gi].raw);
-            }
-            make_dense_pass(P, blk, pp);
-            P->nfused_ops += 1;
-            P->passes.push_back(std::move(pp));
-            continue;
-        }
-        // LDS block pass
-        pp.type = 0;
-        pp.b = b;
-        // pad L to b qubits with unused low qubits (any qubits work; low ones keep segments long)
-        std::vector<int> LL = L;
-        for (int q = 0; (int)LL.size() < b && q < c->n; ++q)
-            if (std::find(LL.begin(), LL.end(), q) == LL.end())
-                LL.push_back(q);
-        std::sort(LL.begin(), LL.end());
-        pp.lmask = 0;
-        pp.bm.b = b;
-        for (int t = 0; t < b; ++t) {
-            pp.bm.lpos[t] = LL[t];
-            pp.lmask |= (uint64_t)1 << LL[t];
-        }
-        std::vector<PG> fused = fuse_pass(*c, gs);
-        pp.nops = (int)fused.size();
-        // local positions of every fused op (ascending, as its sorted matrix expects)
-        std::vector<PG> sorted_ops;
-        std::vector<uint32_t> posmask;
-        for (const PG &f : fused) {
-            sorted_ops.push_back(sorted_gate(f));
-            uint32_t pm = 0;
-            for (int q : sorted_ops.back().q)
-                pm |= 1u << (int)(std::find(LL.begin(), LL.end(), q) - LL.begin());
-            posmask.push_back(pm);
-        }
-        // stages of at most W positions (W = 3 only where a 512-thread kernel exists): repeatedly take ready ops
-        // (every earlier op sharing a position placed) that keep the stage within W positions, fewest new first
-        const int W = (stage_width == 3 && (b == 12 || b == 13)) ? 3 : 4;
-        pp.sw = W;
-        const int nf = (int)fused.size();
-        std::vector<char> placed(nf, 0);
-        int left = nf;
-        pp.stage_begin = (int)P->stages.size();
-        std::vector<std::vector<int>> stage_members;  // fused-op indices of each stage of this pass, in order
-        while (left) {
-            uint32_t S = 0;
-            std::vector<int> members;
-            while ((int)members.size() < kStageMaxOps) {
-                int best = -1, bestnew = 99;
-                for (int i = 0; i < nf; ++i) {
-                    if (placed[i])
-                        continue;
-                    bool rdy = true;
-                    for (int j = 0; j < i && rdy; ++j)
-                        if (!placed[j] && (posmask[j] & posmask[i]))
-                            rdy = false;
-                    if (!rdy)
-                        continue;
-                    const int nw = __builtin_popcount(posmask[i] & ~S);
-                    if (__builtin_popcount(S | posmask[i]) <= W && nw < bestnew) {
-                        best = i;
-                        bestnew = nw;
-                    }
-                }
-                if (best < 0)
-                    break;
-                placed[best] = 1;
-                --left;
-                S |= posmask[best];
-                members.push_back(best);
-            }
-            for (int p = 0; __builtin_popcount(S) < W && p < b; ++p)
-                S |= 1u << p;  // pad with unused positions
-            BlkStage stg{};
-            int j = 0;
-            for (int p = 0; p < b; ++p)
-                if ((S >> p) & 1)
-                    stg.pos[j++] = p;
-            // group-counter bit order over the other positions: one position of each residue class mod 4 first
-            {
-                std::vector<int> rest;
-                for (int p = 0; p < b; ++p)
-                    if (!((S >> p) & 1))
-                        rest.push_back(p);
-                std::vector<int> ord;
-                for (int cls = 0; cls < 4; ++cls)
-                    for (size_t r = 0; r < rest.size(); ++r)
-                        if (rest[r] % 4 == cls) {
-                            ord.push_back(rest[r]);
-                            rest.erase(rest.begin() + r);
-                            break;
-                        }
-                ord.insert(ord.end(), rest.begin(), rest.end());
-                for (int t = 0; t < b - W; ++t)
-                    stg.order[t] = ord[t];
-            }
-            stage_members.push_back(members);
-            stg.op_begin = (int)P->sops.size();
-            stg.nops = (int)members.size();
-            stg.mat_base = (uint32_t)P->pool.size();
-            for (size_t o = 0; o < members.size(); ++o) {
-                const int i = members[o];
-                BlkStageOp so{};
-                for (int t = 0; t < W; ++t)
-                    if ((posmask[i] >> stg.pos[t]) & 1)
-                        so.mask |= 1 << t;
-                so.mat_off = (uint32_t)P->pool.size();
-                push_matrix(P->pool, sorted_ops[i].m);
-                P->sops.push_back(so);
-                stg.masks |= (uint32_t)so.mask << (4 * o);
-            }
-            stg.mfma = -1;
-            P->stages.push_back(stg);
-        }
-        pp.nstages = (int)P->stages.size() - pp.stage_begin;
-        for (const std::vector<int> &members : stage_members)
-            for (int i : members)
-                for (int gi : fused[i].members)
-                    pp.order.push_back(c->gates[gi].raw);
-        // complex64: the pass's stages with the most arithmetic (at least that of mfma_stage_ops 2-qubit ops; up to
-        // kMaxMfmaStages, the LDS they may take) become dense 16 x 16 products on the matrix cores. Op by op a
-        // k-qubit op costs 2^(k+2) FMAs per amplitude; the dense product costs 64, but FP32 MFMA runs at twice the
-        // FP32 FMA rate, so it pays from about three 2-qubit ops' worth on. The product of the stage's ops is formed
-        // here in FP64 (op o first), with stage index bit j <-> pos[j] as in the per-op masks.
-        const int mfma_ops = qs_tunables().mfma_stage_ops;
-        if (P->dtype == QS_C64 && W == 4 && mfma_ops > 0) {
-            auto weight = [&](int t) {  // FMAs per amplitude of stage t, op by op
-                const BlkStage &st = P->stages[pp.stage_begin + t];
-                int w = 0;
-                for (int o = 0; o < st.nops; ++o)
-                    w += 4 << __builtin_popcount((st.masks >> (4 * o)) & 15u);
-                return w;
-            };
-            std::vector<int> pick;
-            for (int t = 0; t < pp.nstages; ++t)
-                if (weight(t) >= 16 * mfma_ops)
-                    pick.push_back(t);
-            std::stable_sort(pick.begin(), pick.end(), [&](int x, int y) { return weight(x) > weight(y); });
-            if ((int)pick.size() > kMaxMfmaStages)
-                pick.resize(kMaxMfmaStages);
-            std::sort(pick.begin(), pick.end());
-            for (int t : pick) {
-                BlkStage &st = P->stages[pp.stage_begin + t];
-                std::vector<cd> M(256, cd(0, 0));
-                for (int r = 0; r < 16; ++r)
-                    M[r * 16 + r] = 1;
-                for (int o = 0; o < st.nops; ++o) {
-                    const int mk = (int)((st.masks >> (4 * o)) & 15u);
-                    const std::vector<cd> &U = sorted_ops[stage_members[t][o]].m;
-                    const int D = 1 << __builtin_popcount(mk);
-                    auto sub = [mk](int x) {  // bits of x at the op's positions, packed (j-th set bit -> bit j)
-                        int v = 0, jj = 0;
-                        for (int q = 0; q < 4; ++q)
-                            if ((mk >> q) & 1)
-                                v |= ((x >> q) & 1) << jj++;
-                        return v;
-                    };
-                    std::vector<cd> E(256, cd(0, 0));
-                    for (int r = 0; r < 16; ++r)
-                        for (int c2 = 0; c2 < 16; ++c2)
-                            if ((r & ~mk) == (c2 & ~mk))
-                                E[r * 16 + c2] = U[sub(r) * D + sub(c2)];
-                    M = matmul(E, M, 16);
-                }
-                st.mfma = pp.mf.n;
-                pp.mf.off[pp.mf.n++] = (uint32_t)P->pool.size();
-                push_matrix(P->pool, M);
-            }
-        }
-        P->nfused_ops += pp.nops;
-        P->passes.push_back(std::move(pp));
+    } else {
+        Former F(*c, b, w, maxq, qs_tunables().plan_beam);
+        std::vector<std::pair<std::vector<int>, std::vector<int>>> fp;
+        std::vector<int> singles;
+        F.run(fp, singles);
+        for (auto &pr : fp)
+            passes.push_back({pr.first, pr.second, b});
     }
+    for (const PassSpec &ps : passes)
+        if (int rc = append_pass(P, c, mode, ps.L, ps.gates, ps.b, stage_width)) {
+            delete P;
+            return rc;
+        }
     *out = P;
     return QS_OK;
 }
@@ -1254,13 +1449,14 @@ QS_API int qs_batch_add(qs_batch *Bt, const qs_circuit *c)
     const int bb = std::min(c->n, Bt->b);
     qs_plan_opts o{QS_PLAN_BLOCK, bb, std::min(Bt->low, bb), Bt->dtype};
     qs_plan *P = nullptr;
-    if (int rc = plan_create(&P, c, &o, 4))  // the batch kernel runs 4-position stages
+    if (int rc = plan_create(&P, c, &o, 4, nullptr))  // the batch kernel runs 4-position stages
         return rc;
     for (const PlanPass &pp : P->passes)
         if (pp.type != 0) {
+            const int type = pp.type;  // pp lives in P, which is released first
             qs_plan_free(P);
             return qs_fail(QS_EUNSUPPORTED, "qs_batch_add: batched circuits may hold gates on at most 3 qubits and "
-                                            "no fused-swaps (pass of type %d)", pp.type);
+                                            "no fused-swaps (pass of type %d)", type);
         }
     BatchCirc bc{};
     bc.n = c->n;

@@ -115,8 +115,8 @@ def _product_pair_circuit(n, seed, layers):
 
 
 def _learned_shape():
-    """The block shape the benchmark runs: the learned cost model's choice for its 32-qubit circuit (greedy 12/4
-    without weights)."""
+    """What the benchmark runs: the learned cost model's choice for its 32-qubit circuit, a (mode, bits, low) shape or
+    costmodel.LEARNED (every pass chosen by the model); greedy 12/4 without weights."""
     import os
     from paper_2203_16044_amd import costmodel as CM
     if not os.path.exists(CM.WEIGHTS):
@@ -131,16 +131,27 @@ def _learned_shape():
     return learned or ("block", 12, 4)
 
 
+def _plan_for(c, shape):
+    """A plan of circuit c in the given shape; costmodel.LEARNED: the model chooses every pass of c."""
+    from paper_2203_16044_amd import costmodel as CM
+    if shape == CM.LEARNED:
+        model = CM.CostModel.load()
+        p = CM.learned_plan(c, "c128", model)
+        model.close()
+        return p
+    return Plan(c, *shape)
+
+
 @pytest.mark.parametrize("shape", [("block", 12, 3), ("block", 12, 4), ("block", 13, 3), "learned"])
 def test_benchmark_structured_product_circuit_sampled_amplitudes(gpu, big_state, shape):
     """40 layers of the benchmark's pairing structure at 32 qubits through the benchmark's plan shapes (the persistent
     block pipeline walks 32 blocks per workgroup per pass): 4,096 sampled amplitudes against the closed form."""
-    mode, bits, low = _learned_shape() if shape == "learned" else shape
+    shape = _learned_shape() if shape == "learned" else shape
     circ, fac = _product_pair_circuit(N, 3200, 40)
     st = big_state
     st.init_zero()
     c = Circuit.from_ops(N, circ.ops)
-    p = Plan(c, mode, bits, low)
+    p = _plan_for(c, shape)
     assert p.info()["passes"] >= 20
     p.run(st)
     p.close()
@@ -180,17 +191,17 @@ def test_ghz_at_32_qubits(gpu, big_state):
 def test_random_circuit_norm_and_echo_block_plan(gpu, big_state, shape):
     """The benchmark's 32-qubit random circuit (40 layers) through the greedy block plan and through the plan the
     benchmark runs preserves the norm, and running its inverse afterwards returns to |0..0>."""
-    mode, bits, low = _learned_shape() if shape == "learned" else shape
+    shape = _learned_shape() if shape == "learned" else shape
     circ = C.su4_u3_random(n=N, seed=32, layers=40)
     st = big_state
     st.init_zero()
     c = Circuit.from_ops(N, circ.ops)
-    p = Plan(c, mode, bits, low)
+    p = _plan_for(c, shape)
     p.run(st)
     assert abs(st.norm() - 1.0) <= 1e-12
     inv = C.inverse_circuit(circ)
     ci = Circuit.from_ops(N, inv.ops)
-    pi = Plan(ci, mode, bits, low)
+    pi = _plan_for(ci, shape)
     pi.run(st)
     a0 = _amps(st, np.array([0]))[0]
     assert abs(a0 - 1.0) <= 1e-12
