@@ -91,8 +91,10 @@ QS_API int qs_apply_gate(qs_state *st, const int *targets, int k, const double *
  * qs_apply_diag -- diagonal gate: a_i <- d[a(i)] a_i, a(i) = the target bits of i in targets order
  * (Eq. 4 with a diagonal U; RZ, CZ, controlled phases). 1 <= k <= QS_MAX_DIAG_K.
  *   d  2^k complex FP64, interleaved. Entries exactly 1 leave their amplitudes' values bit-identical; entries
- *      exactly -1 are a sign flip (exact). For complex128 states, amplitudes whose entry is exactly 1 are not
- *      accessed at all. For complex64 states with k <= 2, memory is accessed in 16-byte pairs of adjacent
+ *      exactly -1 are a sign flip (exact). Entries all in {1, -1, i, -i}, not all 1, with a target inside a
+ *      128-byte line (bit < 3 for complex128, < 4 for complex64): every amplitude is read and rewritten, the
+ *      entry-1 ones unchanged. Otherwise, for complex128 states, amplitudes whose entry is exactly 1 are not
+ *      accessed at all; for complex64 states with k <= 2, memory is accessed in 16-byte pairs of adjacent
  *      amplitudes: a pair with one non-unit entry is read and both amplitudes are rewritten, the one with entry 1
  *      unchanged; a pair whose two entries are 1 is not accessed.
  * Errors: as qs_apply_gate.
@@ -102,7 +104,9 @@ QS_API int qs_apply_diag(qs_state *st, const int *targets, int k, const double *
 /*
  * qs_apply_controlled -- U on the targets, restricted to the amplitudes whose control bits are all 1
  * (CNOT, Toffoli, controlled-U). 1 <= c <= QS_MAX_CONTROLS, 1 <= k <= QS_MAX_K, c + k <= n. Permutation
- * matrices (see qs_apply_gate) are pure moves, bit-exact.
+ * matrices (see qs_apply_gate) are pure moves, bit-exact; when c + k <= QS_MAX_K and a control or target lies
+ * inside a 128-byte line (bit < 3 for complex128, < 4 for complex64) every amplitude is read and the unchanged
+ * ones are written back bit-identical, so that whole lines stream; otherwise unchanged amplitudes are not accessed.
  * Errors: QS_EINVAL (null pointers, counts out of range, qubits out of range, repeated, or a control that
  * is also a target).
  */
@@ -262,7 +266,9 @@ QS_API int qs_plan_features(const qs_plan *p, int i, float *features);
  * to `per_shape` per shape (the local sets its beam search ends with, most gates first), describes each candidate by
  * its QS_PLAN_NFEAT features (qs_plan_features), lets `model` predict log(pass milliseconds) from the features
  * standardised as (f - mean) / std, and keeps the candidate with the lowest predicted time per circuit gate carried
- * among those that carry at least (the most gates any candidate carries) - gate_slack gates.
+ * among those that carry at least (the most gates any candidate carries) - gate_slack gates. With lookahead != 0 a
+ * candidate is scored together with the pass that would follow it (formed with the first shape): their predicted
+ * time over the gates both carry.
  * Passes of a plan may therefore differ in block size and low bits. Gates that no block pass can carry run as their
  * own passes, as in qs_plan_create. opts->mode must be QS_PLAN_BLOCK; opts->block_bits / low_bits are ignored.
  * The model runs on its own stream (one synchronising prediction per pass). Host arrays are read during the call.
@@ -278,6 +284,7 @@ typedef struct {
     const int *shape_bits, *shape_low;
     int per_shape;
     int gate_slack;
+    int lookahead;
 } qs_plan_model;
 QS_API int qs_plan_create_learned(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts,
                                   const qs_plan_model *model);

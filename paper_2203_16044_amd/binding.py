@@ -32,7 +32,7 @@ class qs_plan_model(ctypes.Structure):
     _fields_ = [("model", ctypes.c_void_p), ("mean", ctypes.POINTER(ctypes.c_float)),
                 ("std", ctypes.POINTER(ctypes.c_float)), ("nshapes", ctypes.c_int),
                 ("shape_bits", ctypes.POINTER(ctypes.c_int)), ("shape_low", ctypes.POINTER(ctypes.c_int)),
-                ("per_shape", ctypes.c_int), ("gate_slack", ctypes.c_int)]
+                ("per_shape", ctypes.c_int), ("gate_slack", ctypes.c_int), ("lookahead", ctypes.c_int)]
 
 
 _lib = None
@@ -328,7 +328,7 @@ def qs_plan_create(c: int, mode: int, block_bits: int, low_bits: int = 0, dtype:
 
 
 def qs_plan_create_learned(c: int, dtype: int, model: int, mean, std, shapes, per_shape: int,
-                           gate_slack: int = 0) -> int:
+                           gate_slack: int = 0, lookahead: int = 0) -> int:
     """shapes: sequence of (block_bits, low_bits); mean / std: QS_PLAN_NFEAT floats each."""
     mean = np.ascontiguousarray(mean, dtype=np.float32)
     std = np.ascontiguousarray(std, dtype=np.float32)
@@ -338,7 +338,7 @@ def qs_plan_create_learned(c: int, dtype: int, model: int, mean, std, shapes, pe
     low = (ctypes.c_int * len(shapes))(*[int(w) for _, w in shapes])
     fp = ctypes.POINTER(ctypes.c_float)
     m = qs_plan_model(model, mean.ctypes.data_as(fp), std.ctypes.data_as(fp), len(shapes), bits, low, int(per_shape),
-                      int(gate_slack))
+                      int(gate_slack), int(lookahead))
     o = qs_plan_opts(QS_PLAN_BLOCK, 0, 0, int(dtype))
     h = _P()
     _check(lib().qs_plan_create_learned(ctypes.byref(h), c, ctypes.byref(o), ctypes.byref(m)),

@@ -55,13 +55,15 @@ def time_plan_passes(state, plan, reps: int = 2) -> np.ndarray:
 
 
 def training_circuits(seed: int = 1000, nmax: int = 32):
-    """The circuit families the model is trained on (20..nmax qubits), kept short: pass times do not depend on depth."""
+    """The circuit families the model is trained on (20..nmax qubits). They are deep enough (8 SU(4)+U3 layers, 6 mixed
+    layers, 150 random gates) that passes carry as many fused ops as passes in the middle of long circuits do: a pass's
+    time depends on its ops, and a model trained on shallow circuits only under-predicts deep circuits' passes."""
     import circuits as C
     out = []
     for n in range(20, nmax + 1):
-        out.append(C.su4_u3_random(n=n, seed=seed + n, layers=3))
-        out.append(C.mixed_layers(n=n, seed=seed + 100 + n, layers=3, toffolis=8, swap_s=min(6, n // 4)))
-        out.append(C.random_circuit(n, seed=seed + 200 + n, num_ops=60, kmax=3,
+        out.append(C.su4_u3_random(n=n, seed=seed + n, layers=8))
+        out.append(C.mixed_layers(n=n, seed=seed + 100 + n, layers=6, toffolis=8, swap_s=min(6, n // 4)))
+        out.append(C.random_circuit(n, seed=seed + 200 + n, num_ops=150, kmax=3,
                                     kinds=("dense", "diag", "ctrl")))
     return out
 
@@ -220,27 +222,30 @@ MARGIN = 0.03  # switch away from the greedy plan only for a predicted saving ab
 # block shapes (block bits, always-local low bits) among which the learned planner chooses each pass
 PASS_SHAPES = ((12, 3), (12, 4), (13, 3), (11, 3))
 PER_SHAPE = 4  # candidate local sets per shape and pass
-GATE_SLACK = 0  # a candidate pass must carry at least the largest candidate's gate count minus this
+GATE_SLACK = 1 << 20  # a candidate pass must carry at least the largest candidate's gate count minus this
+LOOKAHEAD = 1  # score a candidate pass together with the pass that would follow it
 LEARNED = ("learned", 0, 0)
 
 
 def learned_plan(circuit, dtype: str, model: CostModel, shapes=PASS_SHAPES, per_shape: int = PER_SHAPE,
-                 gate_slack: int = GATE_SLACK):
+                 gate_slack: int = GATE_SLACK, lookahead: int = LOOKAHEAD):
     """The plan whose every pass the model chooses (qs_plan_create_learned), or None for circuits too small for the
     shapes."""
     from .plan import Plan
     shapes = [s for s in shapes if s[0] <= circuit.n]
     if not shapes:
         return None
-    return Plan.learned(circuit, model, shapes, per_shape, dtype, gate_slack)
+    return Plan.learned(circuit, model, shapes, per_shape, dtype, gate_slack, lookahead)
 
 
 def choose_plan(circuit, dtype: str = "c128", model: Optional[CostModel] = None,
                 cands: Optional[Sequence[Tuple[str, int, int]]] = None, margin: float = MARGIN,
-                per_pass: bool = True):
+                per_pass: bool = False):
     """The candidate with the lowest predicted time, if it beats the greedy plan's prediction by more than `margin`;
     otherwise (and without a model) the greedy plan. Candidates: whole plans of one shape each (`cands`, default
-    candidates(n)) and, with per_pass, the plan whose passes the model chooses one by one (LEARNED). Returns
+    candidates(n)) and, with per_pass, the plan whose passes the model chooses one by one (LEARNED). Per-pass
+    choice is off by default: on held-out circuits it measured no faster than the best whole plan, and its
+    predictions run low (the model is scored on the very passes it picked as cheapest). Returns
     (plan, (mode, bits, low), predicted ms)."""
     from .plan import Plan
     n = circuit.n

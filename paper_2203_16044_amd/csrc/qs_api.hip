@@ -255,6 +255,55 @@ bool is_diagonal(const double *U, int k)
 
 int diag_impl(qs_state *st, const int *targets, int k, const double *d);
 
+// Bits of the amplitude index inside one 128-byte line (8 complex128 / 16 complex64 amplitudes).
+inline int line_bits(int dtype) { return dtype == QS_C128 ? 3 : 4; }
+
+// Whole-line form of a monomial operation whose changed amplitudes are a strided part of every cache line (a
+// target or control inside the 128-byte line): every amplitude is read and written once, the unchanged ones copied
+// bit for bit, so each line streams once instead of being fetched and partly written. The group runs over the
+// qubits of `qmask` (targets and controls, at most QS_MAX_K); member bit u <-> the u-th lowest qubit of qmask. pt
+// maps target members (bit j <-> the j-th lowest target) and applies where every control bit is 1.
+int launch_perm_whole_lines(qs_state *st, uint64_t tmask, uint64_t cmask, const PermTable &pt)
+{
+    const uint64_t qmask = tmask | cmask;
+    const int K2 = __builtin_popcountll(qmask);
+    TPos up{};
+    int ut[QS_MAX_K];  // member bit u -> target index (or -1 for a control)
+    for (int p = 0, u = 0, j = 0; p < 64; ++p) {
+        if (!((qmask >> p) & 1))
+            continue;
+        up.tpos[u] = p;
+        ut[u] = ((tmask >> p) & 1) ? j++ : -1;
+        ++u;
+    }
+    PermTable pu{};
+    for (int a = 0; a < (1 << K2); ++a) {
+        bool on = true;
+        int ta = 0;
+        for (int u = 0; u < K2; ++u) {
+            const int bit = (a >> u) & 1;
+            if (ut[u] < 0)
+                on = on && bit;
+            else
+                ta |= bit << ut[u];
+        }
+        int src = a, ph = 0;
+        if (on) {
+            const int st_ = pt.src[ta];
+            ph = pt.phase[ta];
+            src = 0;
+            for (int u = 0; u < K2; ++u)
+                src |= (ut[u] < 0 ? (a >> u) & 1 : (st_ >> ut[u]) & 1) << u;
+        }
+        pu.src[a] = (uint8_t)src;
+        pu.phase[a] = (uint8_t)ph;
+        pu.moving |= (uint64_t)1 << a;  // every member is read and written
+    }
+    const InsBits ins = qs_make_ins(qmask, 0);
+    QS_HIP(launch_perm(st->dtype, K2, st->psi, (uint64_t)1 << (st->n - K2), ins, up, pu, st->stream));
+    return QS_OK;
+}
+
 // Dense / monomial gate on `targets`, restricted to indices whose `cmask` bits are all 1.
 int matrix_impl(qs_state *st, const int *targets, int k, uint64_t tmask, uint64_t cmask, const double *U)
 {
@@ -271,6 +320,10 @@ int matrix_impl(qs_state *st, const int *targets, int k, uint64_t tmask, uint64_
     if (monomial_table(Us, k, pt)) {
         if (!pt.moving)
             return QS_OK;  // identity
+        const uint64_t line = ((uint64_t)1 << line_bits(st->dtype)) - 1;
+        const bool partial = cmask != 0 || pt.moving != (k >= 6 ? ~(uint64_t)0 : ((uint64_t)1 << (1 << k)) - 1);
+        if (partial && ((tmask | cmask) & line) && nins <= QS_MAX_K)
+            return launch_perm_whole_lines(st, tmask, cmask, pt);
         QS_HIP(launch_perm(st->dtype, k, st->psi, ngroups, ins, tp, pt, st->stream));
         return QS_OK;
     }
@@ -304,6 +357,42 @@ int diag_impl(qs_state *st, const int *targets, int k, const double *d)
     uint64_t tmask = 0;
     for (int j = 0; j < k; ++j)
         tmask |= (uint64_t)1 << targets[j];
+    // a diagonal of phases 1, -1, i, -i that changes only part of each 128-byte line (a target inside the line): the
+    // whole-line move form (exact, every amplitude streamed once) instead of a strided sparse pass
+    if (m < D && k <= QS_MAX_K && (tmask & (((uint64_t)1 << line_bits(st->dtype)) - 1))) {
+        PermTable pt{};
+        bool mono = true;
+        for (int a = 0; a < D && mono; ++a) {
+            const double re = d[2 * a], im = d[2 * a + 1];
+            pt.src[a] = (uint8_t)a;
+            if (re == 1.0 && im == 0.0)
+                pt.phase[a] = 0;
+            else if (re == 0.0 && im == 1.0)
+                pt.phase[a] = 1;
+            else if (re == -1.0 && im == 0.0)
+                pt.phase[a] = 2;
+            else if (re == 0.0 && im == -1.0)
+                pt.phase[a] = 3;
+            else
+                mono = false;
+        }
+        if (mono) {
+            // member bit j <-> the j-th lowest target; d is indexed in the caller's target order
+            int order[QS_MAX_DIAG_K];
+            for (int j = 0; j < k; ++j)
+                order[j] = j;
+            std::sort(order, order + k, [&](int x, int y) { return targets[x] < targets[y]; });
+            PermTable ps{};
+            for (int as = 0; as < D; ++as) {
+                int a = 0;
+                for (int j = 0; j < k; ++j)
+                    a |= ((as >> j) & 1) << order[j];
+                ps.src[as] = (uint8_t)as;
+                ps.phase[as] = pt.phase[a];
+            }
+            return launch_perm_whole_lines(st, tmask, 0, ps);
+        }
+    }
     if (m <= D / 2 && m <= kMaxSparseDiag) {
         // visit only the subspaces of the non-unit patterns: 2^(n-k) amplitudes each
         DiagSparseEntry ent[kMaxSparseDiag];

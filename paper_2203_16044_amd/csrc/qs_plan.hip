@@ -685,9 +685,11 @@ extern "C" QS_API int qs_plan_create_learned(qs_plan **out, const qs_circuit *c,
     *out = nullptr;
     if (opts->mode != QS_PLAN_BLOCK)
         return qs_fail(QS_EINVAL, "qs_plan_create_learned: mode must be QS_PLAN_BLOCK");
-    if (m->nshapes < 1 || m->nshapes > 16 || m->per_shape < 1 || m->per_shape > 8 || m->gate_slack < 0)
-        return qs_fail(QS_EINVAL, "qs_plan_create_learned: nshapes = %d, per_shape = %d or gate_slack = %d out of range",
-                       m->nshapes, m->per_shape, m->gate_slack);
+    if (m->nshapes < 1 || m->nshapes > 16 || m->per_shape < 1 || m->per_shape > 8 || m->gate_slack < 0 ||
+        m->lookahead < 0 || m->lookahead > 1)
+        return qs_fail(QS_EINVAL,
+                       "qs_plan_create_learned: nshapes = %d, per_shape = %d, gate_slack = %d or lookahead = %d invalid",
+                       m->nshapes, m->per_shape, m->gate_slack, m->lookahead);
     for (int i = 0; i < m->nshapes; ++i)
         if (m->shape_bits[i] < 10 || m->shape_bits[i] > kMaxBlockBits || m->shape_bits[i] > c->n ||
             m->shape_low[i] < 0 || m->shape_low[i] > m->shape_bits[i])
@@ -775,16 +777,28 @@ int learned_passes(const qs_circuit &c, int dtype, const qs_plan_model &M, int s
         int pick = 0;
         if (cands.size() > 1) {
             const int nc = (int)cands.size();
-            X.assign((size_t)nc * QS_PLAN_NFEAT, 0.0f);
-            Y.assign(nc, 0.0f);
-            for (int k = 0; k < nc; ++k) {
-                std::vector<int> L = cands[k].L;
+            // rows 0..nc-1: the candidates; with lookahead, rows nc..2nc-1: the pass that would follow each
+            std::vector<Former::Cand> follow(M.lookahead ? nc : 0);
+            std::vector<int> follow_b(follow.size(), M.shape_bits[0]);
+            for (int k = 0; k < (int)follow.size(); ++k) {
+                F[0].head = cands[k].h;
+                follow[k] = F[0].form_pass();
+            }
+            const int rows = nc + (int)follow.size();
+            X.assign((size_t)rows * QS_PLAN_NFEAT, 0.0f);
+            Y.assign(rows, 0.0f);
+            for (int k = 0; k < rows; ++k) {
+                const Former::Cand &cd = k < nc ? cands[k] : follow[k - nc];
+                if (cd.gates.empty())
+                    continue;  // nothing blockable follows: no time added
+                std::vector<int> L = cd.L;
                 std::sort(L.begin(), L.end());
                 tmp.passes.clear();
                 tmp.stages.clear();
                 tmp.sops.clear();
                 tmp.pool.clear();
-                if (int rc = append_pass(&tmp, &c, QS_PLAN_BLOCK, L, cands[k].gates, cand_b[k], stage_width))
+                if (int rc = append_pass(&tmp, &c, QS_PLAN_BLOCK, L, cd.gates, k < nc ? cand_b[k] : follow_b[k - nc],
+                                         stage_width))
                     return rc;
                 float *x = &X[(size_t)k * QS_PLAN_NFEAT];
                 if (int rc = qs_plan_features(&tmp, 0, x))
@@ -792,14 +806,18 @@ int learned_passes(const qs_circuit &c, int dtype, const qs_plan_model &M, int s
                 for (int j = 0; j < QS_PLAN_NFEAT; ++j)
                     x[j] = (x[j] - M.mean[j]) / M.std[j];
             }
-            for (int k0 = 0; k0 < nc; k0 += 4096)
-                if (int rc = qs_mlp_predict(M.model, &X[(size_t)k0 * QS_PLAN_NFEAT], std::min(4096, nc - k0), &Y[k0]))
+            for (int k0 = 0; k0 < rows; k0 += 4096)
+                if (int rc = qs_mlp_predict(M.model, &X[(size_t)k0 * QS_PLAN_NFEAT], std::min(4096, rows - k0), &Y[k0]))
                     return rc;
             double best = 0.0;
             for (int k = 0; k < nc; ++k) {
-                const double per_gate = std::exp((double)Y[k]) / (double)cands[k].gates.size();
-                if (k == 0 || per_gate < best) {
-                    best = per_gate;
+                double t = std::exp((double)Y[k]), g = (double)cands[k].gates.size();
+                if (!follow.empty() && !follow[k].gates.empty()) {
+                    t += std::exp((double)Y[nc + k]);
+                    g += (double)follow[k].gates.size();
+                }
+                if (k == 0 || t / g < best) {
+                    best = t / g;
                     pick = k;
                 }
             }

@@ -63,14 +63,14 @@ class Plan:
 
     @classmethod
     def learned(cls, circuit: Circuit, model, shapes, per_shape: int = 4, dtype: str = "c128",
-                gate_slack: int = 0) -> "Plan":
+                gate_slack: int = 1 << 20, lookahead: int = 0) -> "Plan":
         """A plan whose every pass is chosen by the cost model `model` (a costmodel.CostModel) among candidate passes
         of the given (block_bits, low_bits) shapes (qs_plan_create_learned)."""
         self = cls.__new__(cls)
         self.n = circuit.n
         self.mode, self.block_bits, self.low_bits, self.dtype = "learned", 0, 0, dtype
         self.h = B.qs_plan_create_learned(circuit.h, B.QS_C128 if dtype == "c128" else B.QS_C64, model.h, model.mean,
-                                          model.std, shapes, per_shape, gate_slack)
+                                          model.std, shapes, per_shape, gate_slack, lookahead)
         return self
 
     def info(self) -> dict:

@@ -76,6 +76,19 @@ def test_block_pass_many_blocks_per_workgroup(gpu, tunables, n, layers, dtype, l
     _check(np.asarray(got, np.complex128), oracle.run(circ, psi0), dtype)
 
 
+def test_block_passes_with_three_position_ops(gpu):
+    """A circuit with Toffolis, random 3-qubit gates and fused-swaps at 20 qubits: block passes whose stages hold
+    3-position ops (8 x 8 matrices) beside 1- and 2-position ones, and fused-swap passes, in one plan."""
+    n = 20
+    circ = C.mixed_layers(n=n, seed=960, layers=6, toffolis=12, swap_s=4)
+    extra = C.random_circuit(n, seed=961, num_ops=40, kmax=3, kinds=("dense", "diag", "ctrl"))
+    circ = C.Circuit(n, list(circ.ops) + list(extra.ops), name="mixed+random3")
+    psi0 = C.random_state(n, 962)
+    got, info = _plan_run(gpu, circ, 12, 3, psi0, "c128")
+    assert info["block"] >= 2
+    _check(got, oracle.run(circ, psi0), "c128")
+
+
 @pytest.mark.parametrize("n", [22, 24])
 def test_double_buffered_block_pass_many_blocks_per_workgroup(gpu, tunables, n):
     """The direct-to-LDS double-buffered variant (complex128, 12-qubit blocks) with 256 workgroups: its explicit

@@ -89,33 +89,57 @@ def test_mlp_rejects_bad_batches(gpu):
     B.qs_mlp_free(m)
 
 
+def _step_ms(st, plan, torch):
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    st.init_zero()
+    a.record(st.stream)
+    plan.run(st)
+    b.record(st.stream)
+    b.synchronize()
+    return a.elapsed_time(b)
+
+
 def test_learned_planner_against_greedy(gpu):
-    """On held-out circuits (other seeds and sizes than the training runs), the plan the trained model picks is
-    measured against the greedy plan; the model must not lose (beyond timing noise) and its gain is reported."""
+    """Held-out circuits (a family the model never saw, and seeds and depths outside its training runs): quantum
+    volume at 28 qubits (depth 10), the 28-qubit mixed family (20 layers) and SU(4)+U3 at 26 and 30 qubits (20
+    layers). The plan the trained model picks among whole plans and the greedy plan are timed alternately, three
+    times each. Per circuit the choice may not lose beyond its measured spread plus 1 %; over the circuits where it
+    differs from greedy, its mean relative gain must exceed the largest spread measured on them. The per-circuit
+    report is printed."""
+    import torch
+
     from paper_2203_16044_amd import costmodel as CM
     from paper_2203_16044_amd.plan import Circuit
-    if os.path.exists(CM.WEIGHTS):
-        model = CM.CostModel.load()
-    else:  # train a small model here from 16-22 qubit timings
-        circs = [C.su4_u3_random(n=n, seed=5 + n, layers=2) for n in (16, 18, 20, 22)]
-        X, y = CM.collect(circs, dtypes=("c128",), log=lambda m: None)
-        model = CM.CostModel()
-        model.fit(X, y, epochs=150)
-    held = [(C.su4_u3_random(n=25, seed=901, layers=6), "c128"), (C.su4_u3_random(n=27, seed=902, layers=6), "c128"),
-            (C.su4_u3_renorm(n=27, seed=903, layers=6), "c64")]
-    report = []
-    for circ, dt in held:
-        st = gpu.State(circ.n, dt)
+    if not os.path.exists(CM.WEIGHTS):
+        pytest.skip("no trained cost model in the package")
+    model = CM.CostModel.load()
+    held = [("qv28", C.quantum_volume(28, seed=501, depth=10)), ("mixed28", C.mixed_layers(n=28, seed=777, layers=20)),
+            ("su4u3_26", C.su4_u3_random(n=26, seed=3026, layers=20)),
+            ("su4u3_30", C.su4_u3_random(n=30, seed=3030, layers=20))]
+    report, gains, spreads = [], [], []
+    for name, circ in held:
         c = Circuit.from_ops(circ.n, circ.ops)
-        lp, cand, pred = CM.choose_plan(c, dt, model)
-        gp, gcand, _ = CM.choose_plan(c, dt, None)
-        t_l = min(CM.time_plan_passes(st, lp).sum() for _ in range(2))
-        t_g = min(CM.time_plan_passes(st, gp).sum() for _ in range(2))
-        report.append((circ.name, dt, cand, gcand, t_l, t_g))
-        for x in (lp, gp, c):
+        cp, cand, _ = CM.choose_plan(c, "c128", model)
+        gp, gcand, _ = CM.choose_plan(c, "c128", None)
+        st = gpu.State(circ.n, "c128")
+        cp.run(st)
+        gp.run(st)
+        tc, tg = [], []
+        for _ in range(3):
+            tc.append(_step_ms(st, cp, torch))
+            tg.append(_step_ms(st, gp, torch))
+        spread = max((max(tc) - min(tc)) / min(tc), (max(tg) - min(tg)) / min(tg))
+        report.append((name, cand, gcand, round(min(tc), 2), round(min(tg), 2), round(100 * spread, 2)))
+        assert min(tc) <= min(tg) * (1.0 + spread + 0.01), report
+        if cand != gcand:
+            gains.append(1.0 - min(tc) / min(tg))
+            spreads.append(spread)
+        for x in (cp, gp, c):
             x.close()
         st.close()
-    print("learned vs greedy:", report)
-    tl = sum(r[4] for r in report)
-    tg = sum(r[5] for r in report)
-    assert tl <= 1.05 * tg, report
+        del st
+        torch.cuda.empty_cache()
+    gain = float(np.mean(gains)) if gains else 0.0
+    print(f"learned choice vs greedy (name, choice, greedy, ms choice, ms greedy, spread %): {report}; "
+          f"mean gain where the choice differs {100 * gain:.2f} %")
+    assert gains and gain > max(spreads), (gain, spreads, report)

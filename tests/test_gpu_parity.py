@@ -157,6 +157,43 @@ def test_permutation_gates_bit_exact(gpu, n):
     assert got.tobytes() == ref.tobytes()
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [3, 6, 11, 15])
+def test_whole_line_monomials_bit_exact(gpu, dtype, n):
+    """Monomial diagonals and controlled moves with a target or control inside a 128-byte line (bits 0-2 for
+    complex128, 0-3 for complex64) stream whole lines, rewriting unchanged amplitudes: bit-exact, signed zeros
+    kept; n = 3 leaves a single group (all qubits involved)."""
+    rng = _rng(1100 + n)
+    X = C.x_gate()
+    ph = np.array([1, -1, 1j, -1j], dtype=complex)
+    ops = [C.Op("diag", (0, 1), mat=C.CZ_DIAG), C.Op("diag", (n - 1, 0), mat=C.CZ_DIAG),
+           C.Op("diag", (2,), mat=np.array([1, 1j], dtype=complex)),
+           C.Op("ctrl", (0,), (n - 1,), mat=X), C.Op("ctrl", (n - 1,), (1,), mat=X),  # targets, then controls
+           C.Op("ctrl", (2,), (0, 1), mat=X), C.Op("ctrl", (0,), (1, n - 1), mat=X),  # Toffolis
+           C.Op("dense", (1, n - 1), mat=np.eye(4)[[0, 1, 3, 2]])]  # CNOT as a 2-qubit gate: fixed points
+    for k in range(1, min(6, n) + 1):
+        t = [0] + [int(v) for v in rng.choice(np.arange(1, n), size=k - 1, replace=False)]
+        rng.shuffle(t)
+        d = rng.choice(ph, size=1 << k)
+        d[0] = 1.0
+        ops.append(C.Op("diag", tuple(t), mat=d))
+        if k + 1 <= min(6, n):
+            rest = [q for q in range(n) if q not in t]
+            ops.append(C.Op("ctrl", tuple(t), (int(rng.choice(rest)),), mat=_monomial(rng, k)))
+            low = [q for q in range(4) if q < n and q not in t]
+            if low:
+                ops.append(C.Op("ctrl", tuple(t), (low[-1],), mat=_monomial(rng, k)))
+    psi = C.random_state(n, 1200 + n)
+    if dtype == "c64":
+        psi = psi.astype(np.complex64).astype(np.complex128)
+    psi = _with_signed_zeros(psi, n)
+    got, ref = _run_both(gpu, n, ops, psi, dtype=dtype)
+    if dtype == "c64":
+        assert got.tobytes() == ref.astype(np.complex64).tobytes()
+    else:
+        assert got.tobytes() == ref.tobytes()
+
+
 # ------------------------------------------------------------------------------------------------ fused-swap
 
 FSWAP_CASES = [
