@@ -37,14 +37,14 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (= FP64 MFMA): 256 CUs x 4 SIMDs x
 # The readings hold for the kernel sources they were taken on: `sha1` fingerprints those files and the traffic is
 # reported as null once they differ.
 PMC_TRAFFIC = {
-    "block_b12": {"fetch_kib": None, "write_kib": None, "fetch_scale": 2.0, "write_scale": 1.0,
+    "block_b12": {"fetch_kib": 33554705.05, "write_kib": 67110078.52, "fetch_scale": 2.0, "write_scale": 1.0,
                   "sources": ["paper_2203_16044_amd/csrc/qs_block.hip", "paper_2203_16044_amd/csrc/qs_internal.h",
                               "paper_2203_16044_amd/csrc/qs_index.h"],
-                  "sha1": None},
-    "dense_k1": {"fetch_kib": None, "write_kib": None, "fetch_scale": 2.0, "write_scale": 1.0,
+                  "sha1": "ee2f5aa27ca1b0dc27c1455704a03f401bb48e0e"},
+    "dense_k1": {"fetch_kib": 33554446.85, "write_kib": 67110492.90, "fetch_scale": 2.0, "write_scale": 1.0,
                  "sources": ["paper_2203_16044_amd/csrc/qs_kernels.hip", "paper_2203_16044_amd/csrc/qs_internal.h",
                              "paper_2203_16044_amd/csrc/qs_index.h"],
-                 "sha1": None},
+                 "sha1": "543e51f128ea99191489ce45eca2531f1700501a"},
 }
 
 
@@ -79,6 +79,43 @@ def _alg_bytes(op, n, amp):
     if op.kind == "fswap":
         return int(full * (1 - 2.0 ** -op.s))
     raise ValueError(op.kind)
+
+
+def _line_bytes(op, n, amp):
+    """Bytes of the 128-byte lines that hold an amplitude the op changes, each read and written once: the
+    line-granular roof of any pass, since HBM moves whole lines (a CZ on qubits 0 and 1 changes a quarter of the
+    amplitudes but every line)."""
+    full = 2 * amp * (1 << n)
+    lb = 3 if amp == 16 else 4  # index bits inside a 128-byte line
+    if op.kind == "dense":
+        return full
+    if op.kind == "fswap":
+        q = [op.p + j for j in range(op.s)] + [op.q + j for j in range(op.s)]
+        changed = lambda b: any(b[j] != b[op.s + j] for j in range(op.s))  # noqa: E731
+    elif op.kind == "diag":
+        q = list(op.targets)
+        d = op.mat.ravel()
+        changed = lambda b: d[sum(x << j for j, x in enumerate(b))] != 1  # noqa: E731
+    elif op.kind == "ctrl":
+        nc = len(op.controls)
+        q = list(op.controls) + list(op.targets)
+        changed = lambda b: all(b[:nc])  # noqa: E731
+    else:
+        raise ValueError(op.kind)
+    inside = [i for i, x in enumerate(q) if x < lb]
+    above = [i for i, x in enumerate(q) if x >= lb]
+    touched = 0
+    for hp in range(1 << len(above)):
+        for lp in range(1 << len(inside)):
+            b = [0] * len(q)
+            for j, i in enumerate(above):
+                b[i] = (hp >> j) & 1
+            for j, i in enumerate(inside):
+                b[i] = (lp >> j) & 1
+            if changed(b):
+                touched += 1
+                break
+    return full * touched // (1 << len(above))
 
 
 def _alg_flops(op, n):
@@ -271,8 +308,9 @@ def copy_ceiling(st, torch, reps=3):
 
 def bench_mixed28(torch, copy_tbs, steps=1, warmup=1):
     """The 28-qubit mixed circuit (U3, CZ and RZ layers, Toffolis, fused-swaps; 1,425 operations), unfused: one pass
-    per operation, per-class HBM rates (algorithmic bytes) against 8 TB/s and against the measured copy ceiling; and
-    the same circuit through the greedy block plan."""
+    per operation, per-class HBM rates against 8 TB/s and against the measured in-place ceiling, in algorithmic
+    bytes (changed amplitudes) and in line-granular bytes (the 128-byte lines holding them); and the same circuit
+    through the greedy block plan."""
     import circuits as C
     import paper_2203_16044_amd as qs
     from paper_2203_16044_amd.plan import Circuit, Plan
@@ -284,11 +322,18 @@ def bench_mixed28(torch, copy_tbs, steps=1, warmup=1):
     times, per = time_steps(st, steps, warmup, lambda ev: run_plain(st, ops, ev) if ev else [st.apply_op(o) for o in ops],
                             units, torch)
     t = sum(times) / len(times)
+    line_bytes = {}
+    for o in ops:
+        line_bytes[o.label.lower()] = line_bytes.get(o.label.lower(), 0) + _line_bytes(o, n, 16)
     classes = {}
     for c, (sec, cnt, nbytes, _) in sorted(per.items()):
         tbs = nbytes / sec / 1e12
+        ltbs = line_bytes[c] * len(times) / sec / 1e12
         classes[c] = {"ops": cnt // len(times), "avg_ms": sec / cnt * 1e3, "tbs": tbs, "frac_of_peak": tbs / HBM_PEAK_TBS,
-                      "frac_of_copy_ceiling": tbs / copy_tbs}
+                      "frac_of_copy_ceiling": tbs / copy_tbs,
+                      # against the bytes of the lines holding changed amplitudes (the line-granular roof)
+                      "line_tbs": ltbs, "frac_of_line_roof": ltbs / HBM_PEAK_TBS,
+                      "line_frac_of_copy_ceiling": ltbs / copy_tbs}
     total_bytes = sum(u[1] for u in units)
     cc = Circuit.from_ops(n, ops)
     p = Plan(cc, "block", 12, 4, "c128")

@@ -91,12 +91,15 @@ QS_API int qs_apply_gate(qs_state *st, const int *targets, int k, const double *
  * qs_apply_diag -- diagonal gate: a_i <- d[a(i)] a_i, a(i) = the target bits of i in targets order
  * (Eq. 4 with a diagonal U; RZ, CZ, controlled phases). 1 <= k <= QS_MAX_DIAG_K.
  *   d  2^k complex FP64, interleaved. Entries exactly 1 leave their amplitudes' values bit-identical; entries
- *      exactly -1 are a sign flip (exact). Entries all in {1, -1, i, -i}, not all 1, with a target inside a
- *      128-byte line (bit < 3 for complex128, < 4 for complex64): every amplitude is read and rewritten, the
- *      entry-1 ones unchanged. Otherwise, for complex128 states, amplitudes whose entry is exactly 1 are not
- *      accessed at all; for complex64 states with k <= 2, memory is accessed in 16-byte pairs of adjacent
- *      amplitudes: a pair with one non-unit entry is read and both amplitudes are rewritten, the one with entry 1
- *      unchanged; a pair whose two entries are 1 is not accessed.
+ *      exactly -1 are a sign flip (exact). When every entry is in {1, -1, i, -i} and k <= 6, the diagonal is a pure
+ *      move: entries i and -i exchange the components with a sign, exactly (signed zeros kept).
+ *      Access: such a diagonal that changes an amplitude in every 128-byte line (bit < 3 of the index lies inside
+ *      a complex128 line, bit < 4 inside a complex64 one), with at most 2 targets at bit 6 (complex64: 7) or
+ *      above and n at least 6 (7) plus that number, reads and rewrites every amplitude, the entry-1 ones
+ *      unchanged. Otherwise amplitudes whose entry is exactly 1 are not accessed, except on complex64 states with
+ *      k <= 2 (unless the diagonal is a pure move with an entry i or -i): there memory is accessed in 16-byte
+ *      pairs of adjacent amplitudes, a pair with one entry other than 1 is read and both amplitudes are rewritten
+ *      (the one with entry 1 unchanged), and a pair whose two entries are 1 is not accessed.
  * Errors: as qs_apply_gate.
  */
 QS_API int qs_apply_diag(qs_state *st, const int *targets, int k, const double *d);
@@ -104,9 +107,12 @@ QS_API int qs_apply_diag(qs_state *st, const int *targets, int k, const double *
 /*
  * qs_apply_controlled -- U on the targets, restricted to the amplitudes whose control bits are all 1
  * (CNOT, Toffoli, controlled-U). 1 <= c <= QS_MAX_CONTROLS, 1 <= k <= QS_MAX_K, c + k <= n. Permutation
- * matrices (see qs_apply_gate) are pure moves, bit-exact; when c + k <= QS_MAX_K and a control or target lies
- * inside a 128-byte line (bit < 3 for complex128, < 4 for complex64) every amplitude is read and the unchanged
- * ones are written back bit-identical, so that whole lines stream; otherwise unchanged amplitudes are not accessed.
+ * matrices (see qs_apply_gate) are pure moves, bit-exact. When c + k <= 6, a control or target lies inside a
+ * 128-byte line (bit < 3 for complex128, < 4 for complex64), every 128-byte line holds an amplitude the move
+ * changes, at most 2 of the c + k qubits are at bit 6 (complex64: 7) or above and n is at least 6 (7) plus that
+ * number, every amplitude is read and the unchanged ones are written back bit-identical (whole lines stream);
+ * otherwise unchanged amplitudes are not accessed. The same holds for permutation matrices given to
+ * qs_apply_gate.
  * Errors: QS_EINVAL (null pointers, counts out of range, qubits out of range, repeated, or a control that
  * is also a target).
  */
@@ -116,11 +122,11 @@ QS_API int qs_apply_controlled(qs_state *st, const int *controls, int c, const i
  * qs_fused_swap -- fused_swap(p, q, s) of Sec. III-D, Listing 1: swap(p+i, q+i) for 0 <= i < s, in place:
  * psi'[sigma(i)] = psi[i] where sigma exchanges bit p+j with bit q+j. Pure moves, bit-exact; the 2^(n-s)
  * fixed points (sigma(i) = i) keep their values bit-identical. Whether a fixed point is accessed depends on the
- * form chosen for the run length 2^min(p,q) and the tile size: runs of at least 256 bytes are exchanged
- * directly, and short runs in tiles too small for LDS staging one index pair at a time, neither accessing fixed
- * points; the LDS tile forms read the fixed points that share a tile with moved amplitudes, and the wide-row form
- * (2^s x 2^s tiles of runs up to 32 KiB) also writes them back unchanged. s = 0 is a no-op; p and q may come in
- * either order.
+ * form chosen for the run length 2^min(p,q) and the tile size: runs of at least 256 bytes, or of 128 bytes with
+ * s <= 4, are exchanged directly, and short runs in tiles too small for LDS staging one index pair at a time,
+ * neither accessing fixed points; the LDS tile forms read the fixed points that share a tile with moved
+ * amplitudes, and the wide-row form (2^s x 2^s tiles of runs up to 32 KiB) also writes them back unchanged.
+ * s = 0 is a no-op; p and q may come in either order.
  * Errors: QS_EINVAL if s < 0, p < 0, q < 0, p+s > n, q+s > n, or the ranges overlap (|p - q| < s).
  */
 QS_API int qs_fused_swap(qs_state *st, int p, int q, int s);

@@ -255,32 +255,37 @@ bool is_diagonal(const double *U, int k)
 
 int diag_impl(qs_state *st, const int *targets, int k, const double *d);
 
-// Bits of the amplitude index inside one 128-byte line (8 complex128 / 16 complex64 amplitudes).
-inline int line_bits(int dtype) { return dtype == QS_C128 ? 3 : 4; }
-
-// Whole-line form of a monomial operation whose changed amplitudes are a strided part of every cache line (a
-// target or control inside the 128-byte line): every amplitude is read and written once, the unchanged ones copied
-// bit for bit, so each line streams once instead of being fetched and partly written. The group runs over the
-// qubits of `qmask` (targets and controls, at most QS_MAX_K); member bit u <-> the u-th lowest qubit of qmask. pt
-// maps target members (bit j <-> the j-th lowest target) and applies where every control bit is 1.
-int launch_perm_whole_lines(qs_state *st, uint64_t tmask, uint64_t cmask, const PermTable &pt)
+// Lane-order form of a monomial op (qs_kernels.hip, k_perm_lanes) when it pays: the op's qubits Q = targets and
+// controls (at most 6, at most 2 outside a wave's 64 16-byte lanes) and every 128-byte line of the state holds an
+// amplitude it changes, so that a strided pass over the changed amplitudes would fetch and partly rewrite every line
+// anyway. Then every amplitude is read and written once in lane order (unchanged ones bit-identical). pt maps target
+// members (bit j <-> the j-th lowest target) and applies where every control bit is 1. Returns true if launched.
+bool try_perm_lanes(qs_state *st, uint64_t tmask, uint64_t cmask, const PermTable &pt, int *rc)
 {
     const uint64_t qmask = tmask | cmask;
-    const int K2 = __builtin_popcountll(qmask);
-    TPos up{};
-    int ut[QS_MAX_K];  // member bit u -> target index (or -1 for a control)
-    for (int p = 0, u = 0, j = 0; p < 64; ++p) {
+    const int nq = __builtin_popcountll(qmask);
+    const int LB = st->dtype == QS_C128 ? 6 : 7;          // in-wave index bits
+    const int line = st->dtype == QS_C128 ? 3 : 4;        // index bits inside a 128-byte line
+    if (nq > 6 || (qmask & (((uint64_t)1 << line) - 1)) == 0)
+        return false;
+    PermLanes pl{};
+    int ut[6];  // member bit u -> target index, or -1 for a control
+    int nh = 0;
+    for (int p = 0, j = 0; p < 64; ++p) {
         if (!((qmask >> p) & 1))
             continue;
-        up.tpos[u] = p;
-        ut[u] = ((tmask >> p) & 1) ? j++ : -1;
-        ++u;
+        pl.qpos[pl.nq] = p;
+        ut[pl.nq] = ((tmask >> p) & 1) ? j++ : -1;
+        nh += p >= LB;
+        ++pl.nq;
     }
-    PermTable pu{};
-    for (int a = 0; a < (1 << K2); ++a) {
+    if (nh > 2 || st->n < LB + nh)
+        return false;
+    uint64_t changed = 0;  // members a (over Q) whose amplitude changes
+    for (int a = 0; a < (1 << nq); ++a) {
         bool on = true;
         int ta = 0;
-        for (int u = 0; u < K2; ++u) {
+        for (int u = 0; u < nq; ++u) {
             const int bit = (a >> u) & 1;
             if (ut[u] < 0)
                 on = on && bit;
@@ -289,19 +294,37 @@ int launch_perm_whole_lines(qs_state *st, uint64_t tmask, uint64_t cmask, const 
         }
         int src = a, ph = 0;
         if (on) {
-            const int st_ = pt.src[ta];
+            const int s_ = pt.src[ta];
             ph = pt.phase[ta];
             src = 0;
-            for (int u = 0; u < K2; ++u)
-                src |= (ut[u] < 0 ? (a >> u) & 1 : (st_ >> ut[u]) & 1) << u;
+            for (int u = 0; u < nq; ++u)
+                src |= (ut[u] < 0 ? (a >> u) & 1 : (s_ >> ut[u]) & 1) << u;
         }
-        pu.src[a] = (uint8_t)src;
-        pu.phase[a] = (uint8_t)ph;
-        pu.moving |= (uint64_t)1 << a;  // every member is read and written
+        pl.src[a] = (uint8_t)src;
+        pl.phase[a] = (uint8_t)ph;
+        if (src != a || ph != 0)
+            changed |= (uint64_t)1 << a;
     }
-    const InsBits ins = qs_make_ins(qmask, 0);
-    QS_HIP(launch_perm(st->dtype, K2, st->psi, (uint64_t)1 << (st->n - K2), ins, up, pu, st->stream));
-    return QS_OK;
+    // every line holds a changed amplitude: each pattern of the Q bits above the line has one under some pattern of
+    // the Q bits inside it
+    int in_line = 0;
+    for (int u = 0; u < nq; ++u)
+        in_line |= (pl.qpos[u] < line) << u;
+    for (int hi = 0; hi < (1 << nq); ++hi) {
+        if (hi & in_line)
+            continue;
+        bool any = false;
+        for (int lo = in_line;; lo = (lo - 1) & in_line) {
+            any = any || ((changed >> (hi | lo)) & 1);
+            if (lo == 0)
+                break;
+        }
+        if (!any)
+            return false;
+    }
+    hipError_t e = launch_perm_lanes(st->dtype, st->psi, st->n, pl, st->stream);
+    *rc = e == hipSuccess ? QS_OK : qs_hip_fail(e, "launch_perm_lanes");
+    return true;
 }
 
 // Dense / monomial gate on `targets`, restricted to indices whose `cmask` bits are all 1.
@@ -320,10 +343,9 @@ int matrix_impl(qs_state *st, const int *targets, int k, uint64_t tmask, uint64_
     if (monomial_table(Us, k, pt)) {
         if (!pt.moving)
             return QS_OK;  // identity
-        const uint64_t line = ((uint64_t)1 << line_bits(st->dtype)) - 1;
-        const bool partial = cmask != 0 || pt.moving != (k >= 6 ? ~(uint64_t)0 : ((uint64_t)1 << (1 << k)) - 1);
-        if (partial && ((tmask | cmask) & line) && nins <= QS_MAX_K)
-            return launch_perm_whole_lines(st, tmask, cmask, pt);
+        int rc = QS_OK;
+        if (try_perm_lanes(st, tmask, cmask, pt, &rc))
+            return rc;
         QS_HIP(launch_perm(st->dtype, k, st->psi, ngroups, ins, tp, pt, st->stream));
         return QS_OK;
     }
@@ -357,9 +379,9 @@ int diag_impl(qs_state *st, const int *targets, int k, const double *d)
     uint64_t tmask = 0;
     for (int j = 0; j < k; ++j)
         tmask |= (uint64_t)1 << targets[j];
-    // a diagonal of phases 1, -1, i, -i that changes only part of each 128-byte line (a target inside the line): the
-    // whole-line move form (exact, every amplitude streamed once) instead of a strided sparse pass
-    if (m < D && k <= QS_MAX_K && (tmask & (((uint64_t)1 << line_bits(st->dtype)) - 1))) {
+    // a diagonal of phases 1, -1, i, -i that changes part of every 128-byte line: the lane-order move form (exact,
+    // every amplitude streamed once) instead of a strided pass that would fetch and partly rewrite every line
+    if (m < D && k <= 6) {
         PermTable pt{};
         bool mono = true;
         for (int a = 0; a < D && mono; ++a) {
@@ -390,7 +412,23 @@ int diag_impl(qs_state *st, const int *targets, int k, const double *d)
                 ps.src[as] = (uint8_t)as;
                 ps.phase[as] = pt.phase[a];
             }
-            return launch_perm_whole_lines(st, tmask, 0, ps);
+            int rc = QS_OK;
+            if (try_perm_lanes(st, tmask, 0, ps, &rc))
+                return rc;
+            bool quarter = false;  // an entry i or -i: a component exchange, kept exact (signed zeros) as a move
+            for (int a = 0; a < D; ++a) {
+                quarter = quarter || (ps.phase[a] & 1);
+                if (ps.phase[a])
+                    ps.moving |= (uint64_t)1 << a;
+            }
+            if (quarter) {
+                TPos tp{};
+                int perm[QS_MAX_DIAG_K];
+                qs_sort_targets(targets, k, tp, perm);
+                QS_HIP(launch_perm(st->dtype, k, st->psi, (uint64_t)1 << (st->n - k), qs_make_ins(tmask, 0), tp, ps,
+                                   st->stream));
+                return QS_OK;
+            }
         }
     }
     if (m <= D / 2 && m <= kMaxSparseDiag) {

@@ -73,6 +73,15 @@ struct PermTable {
     uint64_t moving;    // bit a set when member a changes (src[a] != a or phase != 1); k <= 6 so 64 bits suffice
 };
 
+// Monomial op over a qubit set Q (at most 6 qubits, at most 2 of them outside a wave's 64 lanes of 16-byte vectors)
+// whose move table is given over Q (member bit u <-> the u-th lowest qubit of Q): lane-order streaming form.
+struct PermLanes {
+    uint8_t src[64], phase[64];
+    int nq;
+    int qpos[6];  // positions of Q, ascending
+};
+hipError_t launch_perm_lanes(int dtype, void *psi, int n, const PermLanes &pl, hipStream_t s);
+
 hipError_t launch_init_zero(int dtype, void *psi, uint64_t dim, hipStream_t s);
 hipError_t launch_dense(int dtype, int k, void *psi, uint64_t ngroups, const InsBits &ins, const TPos &tp,
                         const double *U_host_sorted, const void *U_dev, hipStream_t s);

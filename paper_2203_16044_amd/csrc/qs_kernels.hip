@@ -237,6 +237,98 @@ __global__ __launch_bounds__(256) void k_perm(typename CT<R>::T *__restrict__ ps
     }
 }
 
+// Lane-order form of a monomial op over Q for states where every 128-byte line holds amplitudes it changes (a CZ or
+// controlled phase on qubits inside the line, a CNOT or Toffoli with a control there): a wave streams 64 consecutive
+// 16-byte vectors (one complex128 amplitude or two complex64 ones per lane, LB = 6 or 7 in-wave index bits) for each
+// of the 2^H combinations of the out-of-wave qubits of Q, so every access is a whole line in lane order, and each
+// output takes its source from the lane, vector slot and member the move table names, by cross-lane reads. Which
+// source feeds an output depends only on the lane, so it is worked out once per thread.
+template <class R, int H>
+__global__ __launch_bounds__(256) void k_perm_lanes(typename LaneVec<R>::T *__restrict__ psi, uint64_t nchunks,
+                                                    InsBits ins_h, PermLanes pl)
+{
+    using V = typename LaneVec<R>::T;
+    constexpr int P = sizeof(R) == 8 ? 1 : 2;  // amplitudes per 16-byte vector
+    constexpr int LB = sizeof(R) == 8 ? 6 : 7;  // in-wave index bits
+    constexpr int M = 1 << H;                   // members per lane
+    const int lane = threadIdx.x & 63;
+    uint64_t hoff[M];
+    int sl[M][P], sp[M][P], sm[M][P], ph[M][P];
+    {
+        int hpos[2] = {0, 0}, nh = 0;
+        for (int u = 0; u < pl.nq; ++u)
+            if (pl.qpos[u] >= LB)
+                hpos[nh++] = pl.qpos[u];
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            hoff[m] = 0;
+            for (int j = 0; j < H; ++j)
+                hoff[m] |= (uint64_t)((m >> j) & 1) << hpos[j];
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                const int iw = lane * P + p;
+                int a = 0;
+                for (int u = 0, j = 0; u < pl.nq; ++u)
+                    a |= (pl.qpos[u] < LB ? (iw >> pl.qpos[u]) & 1 : (m >> j++) & 1) << u;
+                const int sa = pl.src[a];
+                int siw = iw, smem = 0;
+                for (int u = 0, j = 0; u < pl.nq; ++u) {
+                    const int bit = (sa >> u) & 1;
+                    if (pl.qpos[u] < LB)
+                        siw = (siw & ~(1 << pl.qpos[u])) | (bit << pl.qpos[u]);
+                    else
+                        smem |= bit << j++;
+                }
+                sl[m][p] = siw / P;
+                sp[m][p] = siw % P;
+                sm[m][p] = smem;
+                ph[m][p] = pl.phase[a];
+            }
+        }
+    }
+    const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+    for (uint64_t c = wave; c < nchunks; c += nwaves) {
+        const uint64_t base = qs_ins0(c << LB, ins_h) / P + lane;  // vector index of member 0
+        V v[M];
+#pragma unroll
+        for (int m = 0; m < M; ++m)
+            v[m] = __builtin_nontemporal_load(psi + base + hoff[m] / P);
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            V y;
+#pragma unroll
+            for (int p = 0; p < P; ++p) {
+                // the source vector of every candidate member, read from the source lane; keep the named one
+                R re = 0, im = 0;
+#pragma unroll
+                for (int cm = 0; cm < M; ++cm) {
+                    R w[2 * P];
+#pragma unroll
+                    for (int e = 0; e < 2 * P; ++e)
+                        w[e] = __shfl(v[cm][e], sl[m][p], 64);
+                    if (cm == sm[m][p]) {
+                        if constexpr (P == 1) {
+                            re = w[0];
+                            im = w[1];
+                        } else {
+                            re = sp[m][p] ? w[2] : w[0];
+                            im = sp[m][p] ? w[3] : w[1];
+                        }
+                    }
+                }
+                typename CT<R>::T z;
+                z.x = re;
+                z.y = im;
+                z = apply_phase(z, ph[m][p]);
+                y[2 * p] = z.x;
+                y[2 * p + 1] = z.y;
+            }
+            __builtin_nontemporal_store(y, psi + base + hoff[m] / P);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------------------------------------
 // diagonal gates
 // ---------------------------------------------------------------------------------------------------------
@@ -426,7 +518,7 @@ __global__ __launch_bounds__(256) void k_fswap_pairs(C2 *__restrict__ psi, uint6
     }
 }
 
-// Run form (2^lo amplitudes per run span at least 256 bytes): thread -> (outer, pair a > b, element e);
+// Run form (runs of at least 256 bytes, or one 128-byte line with s <= 4): thread -> (outer, pair a > b, element e);
 // the runs (A=a, B=b) and (A=b, B=a) are exchanged with coalesced 16-byte lanes along e.
 template <class C2>
 __global__ __launch_bounds__(256) void k_fswap_runs(C2 *__restrict__ psi, uint64_t total, int lo, int hi, int s,
@@ -442,7 +534,7 @@ __global__ __launch_bounds__(256) void k_fswap_runs(C2 *__restrict__ psi, uint64
     }
 }
 
-// LDS form (runs shorter than 256 bytes): a workgroup exchanges the sub-tile pair (I, J) / (J, I) of one
+// LDS form (runs too short for the direct form): a workgroup exchanges the sub-tile pair (I, J) / (J, I) of one
 // 2^s x 2^s tile (rows A, contiguous columns B of 2^lo-amplitude runs) through LDS; I == J transposes in
 // place. Rows are read and written as contiguous (B, e) segments.
 template <class C2, int TS>
@@ -484,7 +576,7 @@ __global__ __launch_bounds__(256) void k_fswap_lds(C2 *__restrict__ psi, uint64_
     }
 }
 
-// Wide-row form for runs shorter than 256 bytes whose 2^s x 2^s tile fits 32 KiB. With x low "mid" bits carried along, the segment
+// Wide-row form for runs the direct form does not take, whose 2^s x 2^s tile fits 32 KiB. With x low "mid" bits carried along, the segment
 // (mid_low, B, e) for fixed A is contiguous: 2^(x+s+lo) amplitudes (kilobytes). A workgroup loads the 2^s rows
 // A = a of one work item with coalesced 16-byte lanes into LDS and writes every row b back with the element at
 // (mid_low, B = a, e) taken from row a at (mid_low, B = b, e): 2^x independent 2^s x 2^s transposes at once.
@@ -777,6 +869,41 @@ hipError_t launch_perm(int dtype, int k, void *psi, uint64_t ngroups, const InsB
 {
     return dtype == QS_C128 ? perm_r<double>(k, psi, ngroups, ins, tp, pt, s)
                             : perm_r<float>(k, psi, ngroups, ins, tp, pt, s);
+}
+
+hipError_t launch_perm_lanes(int dtype, void *psi, int n, const PermLanes &pl, hipStream_t s)
+{
+    const int LB = dtype == QS_C128 ? 6 : 7;
+    int h = 0;
+    uint64_t hmask = 0;
+    for (int u = 0; u < pl.nq; ++u)
+        if (pl.qpos[u] >= LB) {
+            ++h;
+            hmask |= (uint64_t)1 << pl.qpos[u];
+        }
+    if (pl.nq < 1 || pl.nq > 6 || h > 2 || n < LB + h)
+        return hipErrorInvalidValue;
+    const InsBits ins_h = qs_make_ins(hmask, 0);
+    const uint64_t nchunks = (uint64_t)1 << (n - LB - h);
+    const unsigned g = grid_for(nchunks * 64, 256);
+    if (dtype == QS_C128) {
+        using V = LaneVec<double>::T;
+        if (h == 0)
+            hipLaunchKernelGGL((k_perm_lanes<double, 0>), dim3(g), dim3(256), 0, s, (V *)psi, nchunks, ins_h, pl);
+        else if (h == 1)
+            hipLaunchKernelGGL((k_perm_lanes<double, 1>), dim3(g), dim3(256), 0, s, (V *)psi, nchunks, ins_h, pl);
+        else
+            hipLaunchKernelGGL((k_perm_lanes<double, 2>), dim3(g), dim3(256), 0, s, (V *)psi, nchunks, ins_h, pl);
+    } else {
+        using V = LaneVec<float>::T;
+        if (h == 0)
+            hipLaunchKernelGGL((k_perm_lanes<float, 0>), dim3(g), dim3(256), 0, s, (V *)psi, nchunks, ins_h, pl);
+        else if (h == 1)
+            hipLaunchKernelGGL((k_perm_lanes<float, 1>), dim3(g), dim3(256), 0, s, (V *)psi, nchunks, ins_h, pl);
+        else
+            hipLaunchKernelGGL((k_perm_lanes<float, 2>), dim3(g), dim3(256), 0, s, (V *)psi, nchunks, ins_h, pl);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_diag_full(int dtype, void *psi, uint64_t dim, const DiagArgs &da, const double *d_host,

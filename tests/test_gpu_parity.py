@@ -161,8 +161,9 @@ def test_permutation_gates_bit_exact(gpu, n):
 @pytest.mark.parametrize("n", [3, 6, 11, 15])
 def test_whole_line_monomials_bit_exact(gpu, dtype, n):
     """Monomial diagonals and controlled moves with a target or control inside a 128-byte line (bits 0-2 for
-    complex128, 0-3 for complex64) stream whole lines, rewriting unchanged amplitudes: bit-exact, signed zeros
-    kept; n = 3 leaves a single group (all qubits involved)."""
+    complex128, 0-3 for complex64): when every line holds a changed amplitude they run in lane order (cross-lane
+    moves, 0-2 of their qubits outside the wave), otherwise as strided moves; both bit-exact, signed zeros kept.
+    n = 3 and 6 are below the lane form's minimum state (every qubit involved, or fewer amplitudes than a wave)."""
     rng = _rng(1100 + n)
     X = C.x_gate()
     ph = np.array([1, -1, 1j, -1j], dtype=complex)
@@ -171,6 +172,10 @@ def test_whole_line_monomials_bit_exact(gpu, dtype, n):
            C.Op("ctrl", (0,), (n - 1,), mat=X), C.Op("ctrl", (n - 1,), (1,), mat=X),  # targets, then controls
            C.Op("ctrl", (2,), (0, 1), mat=X), C.Op("ctrl", (0,), (1, n - 1), mat=X),  # Toffolis
            C.Op("dense", (1, n - 1), mat=np.eye(4)[[0, 1, 3, 2]])]  # CNOT as a 2-qubit gate: fixed points
+    if n >= 9:  # two qubits outside the wave, every line changed
+        ops.append(C.Op("diag", (0, n - 2, n - 1), mat=np.array([1, -1, 1j, 1, -1j, -1, 1, 1j], dtype=complex)))
+        ops.append(C.Op("ctrl", (n - 1, n - 2), (0,), mat=_monomial(rng, 2)))
+        ops.append(C.Op("ctrl", (n - 3,), (1, 2), mat=C.x_gate()))  # Toffoli, controls inside the line
     for k in range(1, min(6, n) + 1):
         t = [0] + [int(v) for v in rng.choice(np.arange(1, n), size=k - 1, replace=False)]
         rng.shuffle(t)
@@ -199,18 +204,21 @@ def test_whole_line_monomials_bit_exact(gpu, dtype, n):
 FSWAP_CASES = [
     (4, 0, 2, 2), (8, 0, 4, 4), (8, 5, 1, 3), (10, 0, 7, 3), (7, 0, 1, 1),  # small / generic
     (16, 0, 12, 4),  # the 16-qubit circuit's swap: runs of 1 amplitude
-    (18, 1, 12, 5), (18, 2, 9, 6), (18, 3, 11, 7), (20, 0, 14, 6),  # LDS path, various run lengths
-    (18, 4, 12, 6), (18, 6, 12, 6), (20, 5, 15, 5), (19, 4, 8, 3),  # run path (>= 256-byte runs)
+    (18, 1, 12, 5), (18, 2, 9, 6), (20, 0, 14, 6),  # LDS path, various run lengths
+    (18, 4, 12, 6), (18, 6, 12, 6), (20, 5, 15, 5), (19, 4, 8, 3),  # run path (>= 128-byte runs)
+    (18, 3, 12, 1), (19, 3, 10, 4), (12, 3, 7, 2),  # run path, runs of exactly one line (s <= 4)
+    (18, 3, 11, 7), (20, 3, 13, 6),  # one-line runs with s > 4: LDS tiles
     (16, 12, 0, 4),  # reversed argument order
-    # wide-row path (s <= 3, runs < 256 B): carried mid bits x = 9/7/5, capped by few mid bits, none at all
-    (18, 0, 12, 1), (18, 0, 14, 2), (18, 0, 15, 3), (18, 1, 10, 2), (18, 2, 9, 3), (18, 3, 11, 2),
+    # wide-row path (s <= 3, runs < 128 B): carried mid bits x = 9/7/5, capped by few mid bits, none at all
+    (18, 0, 12, 1), (18, 0, 14, 2), (18, 0, 15, 3), (18, 1, 10, 2), (18, 2, 9, 3), (18, 2, 11, 2),
     (14, 0, 3, 1), (12, 0, 2, 2), (12, 1, 4, 3), (9, 0, 3, 3), (20, 0, 17, 3),
     (20, 0, 13, 6), (13, 0, 6, 6), (16, 0, 10, 5), (17, 1, 9, 5),  # wide rows with 32-64 KiB tiles
 ]
 
 
 @pytest.mark.parametrize("n,p,q,s", [(18, 0, 12, 1), (18, 0, 14, 2), (18, 0, 15, 3), (18, 4, 9, 3), (12, 0, 2, 2),
-                                     (18, 1, 12, 5), (18, 5, 12, 6), (20, 0, 13, 6), (16, 1, 8, 6)])
+                                     (18, 1, 12, 5), (18, 5, 12, 6), (20, 0, 13, 6), (16, 1, 8, 6),
+                                     (18, 4, 12, 1), (16, 4, 9, 3)])  # runs of one 128-byte line
 def test_fused_swap_complex64_bit_exact(gpu, n, p, q, s):
     psi = C.random_state(n, n + 3 * s).astype(np.complex64)
     st = gpu.State(n, "c64")
