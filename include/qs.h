@@ -363,6 +363,10 @@ QS_API int qs_probe_rmw(void *buf, size_t bytes, void *hip_stream);
  *                     3 (512-thread kernel with 8 register amplitudes per thread, for 12- and 13-qubit blocks);
  * "block_async" 0/1: 12-qubit complex128 block passes double-buffer the next block in LDS with direct-to-LDS loads
  *               (default 0: one workgroup per CU fits, measured slower than two with register prefetch);
+ * "block_lanes" 0/1: in plans created afterwards, complex128 12-qubit block passes whose ops act on one or two
+ *               register positions run a 512-thread kernel that holds each 16-amplitude register group in two
+ *               lanes (4 waves per SIMD instead of 2; default 0: measured 0.5 % slower, the chip's sustained
+ *               clock falls as VALU activity rises);
  * "mfma_stage_ops" complex64 block plans and batches created afterwards: in each pass, up to 4 of the 4-position
  *               stages whose ops amount to at least this many 2-qubit ops' arithmetic (a k-qubit op counts
  *               2^(k-2); the stages with the most) run as one fused 16 x 16 product on the FP32 matrix cores

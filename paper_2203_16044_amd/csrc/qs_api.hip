@@ -795,6 +795,10 @@ QS_API int qs_set_tunable(const char *name, int64_t value)
         if (value != 0 && value != 1)
             return qs_fail(QS_EINVAL, "block_async must be 0 or 1");
         t.block_async = (int)value;
+    } else if (!std::strcmp(name, "block_lanes")) {
+        if (value != 0 && value != 1)
+            return qs_fail(QS_EINVAL, "block_lanes must be 0 or 1");
+        t.block_lanes = (int)value;
     } else if (!std::strcmp(name, "mfma_stage_ops")) {
         if (value < 0 || value > kStageMaxOps)
             return qs_fail(QS_EINVAL, "mfma_stage_ops must be in [0, %d]", kStageMaxOps);

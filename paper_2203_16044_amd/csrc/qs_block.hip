@@ -521,6 +521,231 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, B, NT>::waves_per_eu)) void k_b
     }
 }
 
+// ---------------------------------------------------------------------------------------------------------
+// Lane-pair stages (complex128, 12-qubit blocks): a 4-position stage's 16-amplitude group is held by lanes l and
+// l + 32 of a wave, 8 amplitudes each (register index a over three of the stage positions, the lane bit over the
+// fourth), so that the 512-thread workgroups of two 64 KB blocks give a CU 16 waves (4 per SIMD) where the
+// one-lane form gives 8, with the same stages and LDS round trips. An op on the lane's position is preceded by an
+// exchange of the lane bit with a register bit it does not use (BlkStageL.swaps, chosen by the planner).
+// ---------------------------------------------------------------------------------------------------------
+
+// Exchange of the lane bit (thread bit 5) with register bit RB: for every a with bit RB clear, the upper
+// half-wave's x[a] and the lower half-wave's x[a | 2^RB] trade places, which is what v_permlane32_swap does to
+// its two operands (upper 32 lanes of the first with the lower 32 lanes of the second), one 32-bit word at a time.
+__device__ __forceinline__ void swap_halves(double &u, double &v)
+{
+    const uint64_t bu = __builtin_bit_cast(uint64_t, u), bv = __builtin_bit_cast(uint64_t, v);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)bu, (unsigned)bv, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(bu >> 32), (unsigned)(bv >> 32), false, false);
+    u = __builtin_bit_cast(double, (uint64_t)lo[0] | ((uint64_t)hi[0] << 32));
+    v = __builtin_bit_cast(double, (uint64_t)lo[1] | ((uint64_t)hi[1] << 32));
+}
+
+template <int RB>
+__device__ __forceinline__ void lane_swap_bit(double2 *x)
+{
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        if (a & (1 << RB))
+            continue;
+        swap_halves(x[a].x, x[a | 1 << RB].x);
+        swap_halves(x[a].y, x[a | 1 << RB].y);
+    }
+}
+
+// reg_op for the lane-pair stages, one group at a time: a scheduling barrier after each group's write-back keeps
+// the compiler from interleaving the groups, so only one group's outputs are live beside the 8 amplitudes and the
+// prefetched next block (the kernel has 128 registers for 4 waves per SIMD)
+template <int MASK>
+__device__ __forceinline__ void reg_op_seq(double2 *x, const double *__restrict__ U)
+{
+    constexpr int K = __builtin_popcount(MASK);
+    constexpr int D = 1 << K;
+    int bitpos[2] = {0, 0};
+    {
+        int j = 0;
+        for (int b = 0; b < 3; ++b)
+            if ((MASK >> b) & 1)
+                bitpos[j++] = b;
+    }
+#pragma unroll
+    for (int rest = 0; rest < 8; ++rest) {
+        if (rest & MASK)
+            continue;
+        double2 v[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            int r = rest;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                r |= ((a >> j) & 1) << bitpos[j];
+            v[a] = x[r];
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            double yr = 0, yi = 0;
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                const double ur = U[2 * (a * D + b)], ui = U[2 * (a * D + b) + 1];
+                yr = fma(ur, v[b].x, yr);
+                yr = fma(-ui, v[b].y, yr);
+                yi = fma(ur, v[b].y, yi);
+                yi = fma(ui, v[b].x, yi);
+            }
+            int r = rest;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                r |= ((a >> j) & 1) << bitpos[j];
+            x[r].x = yr;
+            x[r].y = yi;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+__device__ __forceinline__ void run_stage_lanes(double2 *s, const BlkStageL &stg, const double *__restrict__ mats)
+{
+    const uint32_t t = threadIdx.x;
+    const uint32_t g = (t & 31u) | ((t >> 6) << 5);  // group: lanes l and l + 32 share one
+    const bool up = (t >> 5) & 1u;                   // the lane bit
+    uint32_t m = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        m |= ((g >> j) & 1u) << stg.order[j];
+    const uint32_t sm = slot_bytes<double2>(m);
+    const uint32_t smr = sm ^ (up ? stg.rd_lane : 0u);
+    double2 x[8];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+        x[a] = lds_at(s, smr ^ stg.rd[a]);
+    uint32_t moff = stg.mat_base;
+    for (int o = 0; o < stg.nops; ++o) {
+        switch ((stg.swaps >> (2 * o)) & 3u) {
+        case 1: lane_swap_bit<0>(x); break;
+        case 2: lane_swap_bit<1>(x); break;
+        case 3: lane_swap_bit<2>(x); break;
+        default: break;
+        }
+        const int mask = (int)(stg.masks >> (4 * o)) & 7;  // one or two register bits (the planner's condition)
+        switch (mask) {
+        case 1: reg_op_seq<1>(x, mats + moff); break;
+        case 2: reg_op_seq<2>(x, mats + moff); break;
+        case 4: reg_op_seq<4>(x, mats + moff); break;
+        case 3: reg_op_seq<3>(x, mats + moff); break;
+        case 5: reg_op_seq<5>(x, mats + moff); break;
+        default: reg_op_seq<6>(x, mats + moff); break;
+        }
+        moff += 2u << (2 * __builtin_popcount(mask));
+    }
+    const uint32_t smw = sm ^ (up ? stg.wr_lane : 0u);
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+        lds_at(s, smw ^ stg.wr[a]) = x[a];
+}
+
+// The block loop of k_block (next block's loads issued into registers before the current block's stages, rotated
+// so that the wait covers only those loads), 512 threads, 8 amplitudes per thread, lane-pair stages.
+__global__ __launch_bounds__(512, 4) void k_block_lanes(double2 *__restrict__ psi, uint64_t nblocks, InsBits outer,
+                                                        BlockMap bm, const BlkStageL *__restrict__ stages,
+                                                        int nstages, const double *__restrict__ mats)
+{
+    using C2 = double2;
+    extern __shared__ __align__(16) unsigned char smem_blk[];
+    C2 *s = reinterpret_cast<C2 *>(smem_blk);
+    constexpr int B = 12, NT = 512;
+    constexpr int PER = (1 << B) / NT;
+    constexpr int LNT = 9;
+    constexpr int PB = B - LNT;
+    const uint64_t own = spread(threadIdx.x, bm);  // this thread's offset inside a block (its bits at lpos[0..8])
+    uint64_t hb[PB];
+#pragma unroll
+    for (int j = 0; j < PB; ++j)
+        hb[j] = (uint64_t)1 << bm.lpos[LNT + j];
+    const uint32_t sbase = slot_bytes<C2>(threadIdx.x);
+    auto opaque_h = [&](uint64_t *h) {
+#pragma unroll
+        for (int j = 0; j < PB; ++j) {
+            h[j] = hb[j];
+            asm volatile("" : "+s"(h[j]));
+        }
+    };
+    auto opaque_s = [&]() {
+        uint32_t sb = sbase;
+        asm volatile("" : "+v"(sb));
+        return sb;
+    };
+    using NV = typename NT2<double>::type;
+    NV pre[PER];
+    uint64_t blk = blockIdx.x;
+    if (blk >= nblocks)
+        return;
+    uint64_t base = ins0b(blk, outer);  // the block's offset (uniform); `own` is OR-ed in at each access
+    {
+        uint64_t h[PB];
+        opaque_h(h);
+        const C2 *pb = psi + (base | own);
+#pragma unroll
+        for (int it = 0; it < PER; ++it)
+            pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(pb + blk_hi<PB>(h, it)));
+        const uint32_t sb = opaque_s();
+#pragma unroll
+        for (int it = 0; it < PER; ++it) {
+            C2 v;
+            v.x = pre[it].x;
+            v.y = pre[it].y;
+            lds_at(s, blk_phase_slot(sb, it, NT, (uint32_t)sizeof(C2))) = v;
+        }
+    }
+    lds_barrier();
+    for (;;) {
+        const uint64_t nxt = blk + gridDim.x;
+        const bool more = nxt < nblocks;  // uniform
+        const uint64_t nbase = ins0b(more ? nxt : blk, outer);
+        if (more) {
+            uint64_t h[PB];
+            opaque_h(h);
+            const C2 *pb = psi + (nbase | own);
+#pragma unroll
+            for (int it = 0; it < PER; ++it)
+                pre[it] = __builtin_nontemporal_load(reinterpret_cast<const NV *>(pb + blk_hi<PB>(h, it)));
+        }
+        for (int t = 0; t < nstages; ++t) {
+            run_stage_lanes(s, stages[t], mats);
+            lds_barrier();
+        }
+        {
+            uint64_t h[PB];
+            opaque_h(h);
+            C2 *pb = psi + (base | own);
+            const uint32_t sb = opaque_s();
+#pragma unroll
+            for (int it = 0; it < PER; ++it) {
+                const C2 v = lds_at(s, blk_phase_slot(sb, it, NT, (uint32_t)sizeof(C2)));
+                NV w;
+                w.x = v.x;
+                w.y = v.y;
+                __builtin_nontemporal_store(w, reinterpret_cast<NV *>(pb + blk_hi<PB>(h, it)));
+            }
+        }
+        if (nxt >= nblocks)
+            break;
+        blk = nxt;
+        base = nbase;
+        lds_barrier();  // every thread has read its stored values out of LDS
+        {
+            const uint32_t sb = opaque_s();
+#pragma unroll
+            for (int it = 0; it < PER; ++it) {
+                C2 v;
+                v.x = pre[it].x;
+                v.y = pre[it].y;
+                lds_at(s, blk_phase_slot(sb, it, NT, (uint32_t)sizeof(C2))) = v;
+            }
+        }
+        lds_barrier();
+    }
+}
+
 // Double-buffered block pass: the next block streams from HBM straight into the other LDS buffer (direct-to-LDS
 // 16-byte loads, no registers involved) while the current block's stages run, so HBM traffic and arithmetic
 // overlap inside one workgroup. Load instruction `it` of wave w fills slots [256 it + 64 w, +64), one 16-byte slot
@@ -895,7 +1120,7 @@ hipError_t batch_r(int b, void *psi, double *probs, const BatchItem *items, int 
 
 template <class R, int B, int W>
 hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm, const BlkStage *stages,
-                   int nstages, const void *mats, const BlkMfma &mf, hipStream_t s)
+                   int nstages, const void *mats, const BlkMfma &mf, const BlkStageL *lstages, hipStream_t s)
 {
     using C2 = typename BT<R>::C2;
     constexpr int NT = BlockThreads<B, W>::value;
@@ -915,6 +1140,20 @@ hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const Bloc
         grid = cus;
     if (grid > nblocks)
         grid = nblocks;
+    if constexpr (B == 12 && W == 4 && sizeof(R) == 8) {
+        if (lstages) {
+            if (hipError_t e = qs_allow_lds((const void *)k_block_lanes, data))
+                return e;
+            uint64_t g2 = cus * qs_tunables().block_wg_per_cu / 2;  // 512-thread workgroups
+            if (g2 < cus)
+                g2 = cus;
+            if (g2 > nblocks)
+                g2 = nblocks;
+            hipLaunchKernelGGL(k_block_lanes, dim3((unsigned)g2), dim3(512), data, s, (double2 *)psi, nblocks, outer,
+                               bm, lstages, nstages, (const double *)mats);
+            return hipGetLastError();
+        }
+    }
     // complex128 only: a 16-byte direct-to-LDS load is one complex128 amplitude; for complex64 it would carry two
     // amplitudes into two adjacent slots, which the swizzle may need in the opposite order
     if constexpr (B == 12 && W == 4 && sizeof(R) == 8) {
@@ -934,24 +1173,25 @@ hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const Bloc
 
 template <class R>
 hipError_t block_r(int b, int w, void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm,
-                   const BlkStage *stages, int nstages, const void *mats, const BlkMfma &mf, hipStream_t s)
+                   const BlkStage *stages, int nstages, const void *mats, const BlkMfma &mf, const BlkStageL *lstages,
+                   hipStream_t s)
 {
     if (w == 3) {
         switch (b) {
-        case 12: return block_b<R, 12, 3>(psi, nblocks, outer, bm, stages, nstages, mats, mf, s);
-        case 13: return block_b<R, 13, 3>(psi, nblocks, outer, bm, stages, nstages, mats, mf, s);
+        case 12: return block_b<R, 12, 3>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, s);
+        case 13: return block_b<R, 13, 3>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, s);
         default: return hipErrorInvalidValue;
         }
     }
     if (w != 4)
         return hipErrorInvalidValue;
     switch (b) {
-    case 8: return block_b<R, 8, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, s);
-    case 9: return block_b<R, 9, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, s);
-    case 10: return block_b<R, 10, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, s);
-    case 11: return block_b<R, 11, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, s);
-    case 12: return block_b<R, 12, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, s);
-    case 13: return block_b<R, 13, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, s);
+    case 8: return block_b<R, 8, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, s);
+    case 9: return block_b<R, 9, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, s);
+    case 10: return block_b<R, 10, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, s);
+    case 11: return block_b<R, 11, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, s);
+    case 12: return block_b<R, 12, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, s);
+    case 13: return block_b<R, 13, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -970,9 +1210,9 @@ hipError_t launch_batch_level(int dtype, int b, void *psi, double *probs, const 
 
 hipError_t launch_block(int dtype, int b, int w, void *psi, uint64_t nblocks, const InsBits &outer,
                         const BlockMap &bm, const BlkStage *stages_dev, int nstages, const void *mats_dev,
-                        const BlkMfma &mf, hipStream_t s)
+                        const BlkMfma &mf, const BlkStageL *lstages_dev, hipStream_t s)
 {
     return dtype == QS_C128
-               ? block_r<double>(b, w, psi, nblocks, outer, bm, stages_dev, nstages, mats_dev, mf, s)
-               : block_r<float>(b, w, psi, nblocks, outer, bm, stages_dev, nstages, mats_dev, mf, s);
+               ? block_r<double>(b, w, psi, nblocks, outer, bm, stages_dev, nstages, mats_dev, mf, lstages_dev, s)
+               : block_r<float>(b, w, psi, nblocks, outer, bm, stages_dev, nstages, mats_dev, mf, nullptr, s);
 }

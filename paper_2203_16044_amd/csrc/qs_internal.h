@@ -137,6 +137,22 @@ struct BlkStage {
     uint32_t soff[16];
 };
 
+// Lane-pair form of a 4-position stage (complex128, 12-qubit blocks, 512 threads; passes whose ops act on one or
+// two positions): a 16-amplitude group is held by two lanes of a wave (thread bit 5), 8 amplitudes each; three
+// stage positions are register bits of a lane's index a (0..7), the fourth is the lane bit. An op that acts on the
+// lane's position is preceded by an exchange of the lane bit with a register bit the op does not use.
+struct BlkStageL {
+    int order[kMaxBlockBits - 4];  // group counter bit j -> local position (as in BlkStage)
+    // LDS byte offsets (slot maps are linear over XOR): member (a, l) of a group at base slot sm sits at
+    // sm ^ rd[a] ^ (l ? rd_lane : 0) in the initial placement, at sm ^ wr[a] ^ (l ? wr_lane : 0) after the last op
+    uint32_t rd[8], wr[8];
+    uint32_t rd_lane, wr_lane;
+    uint32_t masks;                // op o: register bits it acts on, bits 4o..4o+2 (its matrix in register-bit order)
+    uint32_t swaps;                // op o: 0, or 1 + the register bit exchanged with the lane bit before it, bits 2o..2o+1
+    uint32_t mat_base;             // pool offset of op 0's matrix; the others follow in order
+    int nops;
+};
+
 struct BlkStageOp {  // host-side op table (planner statistics and batch relocation)
     int mask;          // stage positions the op acts on (bit j of the mask <-> pos[j], j < W); 1..3 bits set
     uint32_t mat_off;  // offset of its 2^k x 2^k matrix (bit order of the mask's positions) in real elements
@@ -149,9 +165,11 @@ struct BlkMfma {
     int n = 0;
     uint32_t off[kMaxMfmaStages] = {0, 0, 0, 0};
 };
+// lstages_dev: the pass's stages in lane-pair form (complex128, b = 12, 4-position stages; built for plans created
+// while the tunable block_lanes is set), or null
 hipError_t launch_block(int dtype, int b, int w, void *psi, uint64_t nblocks, const InsBits &outer,
                         const BlockMap &bm, const BlkStage *stages_dev, int nstages, const void *mats_dev,
-                        const BlkMfma &mf, hipStream_t s);
+                        const BlkMfma &mf, const BlkStageL *lstages_dev, hipStream_t s);
 
 // batched circuits: one persistent launch per pass level (see qs_block.hip)
 struct BatchCirc {
@@ -211,6 +229,7 @@ struct Tunables {
     std::atomic<int> block_stage_width{4}; // register stage width of new block plans: 4, or 3 (512 threads, b = 12, 13)
     std::atomic<int> plan_beam{16};       // pass formation: beam width over local-set growth (0: fewest-new greedy)
     std::atomic<int> block_async{0};      // 12-qubit block passes: double-buffered LDS with direct-to-LDS loads
+    std::atomic<int> block_lanes{0};      // plans created afterwards: complex128 12-qubit lane-pair stages, 512 threads
     std::atomic<int> mfma_stage_ops{3};   // complex64 plans: stages of at least this many ops run fused on MFMA
 };
 Tunables &qs_tunables();

@@ -133,16 +133,19 @@ struct PlanPass {
     int raw = -1;
     int ngates = 0;          // circuit gates carried by the pass
     std::vector<int> order;  // their raw-op indices, in the order the pass applies them
+    int lstage_begin = -1;   // block: first of the pass's lane-pair stage records (-1: the pass has none)
 };
 
 struct qs_plan {
     int n = 0, dtype = QS_C128, mode = 0;
     std::vector<PlanPass> passes;
     std::vector<BlkStage> stages;
+    std::vector<BlkStageL> lstages;  // lane-pair form of the stages of eligible passes
     std::vector<BlkStageOp> sops;
     std::vector<double> pool;  // matrices, FP64 (rounded to FP32 on upload for complex64)
     std::vector<RawOp> raw;    // copy: the plan stays valid after the circuit is freed
     BlkStage *dstages = nullptr;
+    BlkStageL *dlstages = nullptr;
     void *dpool = nullptr;
     int dev = -1;
     int nfused_ops = 0;
@@ -453,6 +456,15 @@ int upload_tables(qs_plan *P)
     P->dstages = static_cast<BlkStage *>(p);
     if (!P->stages.empty())
         QS_HIP(hipMemcpy(P->dstages, P->stages.data(), P->stages.size() * sizeof(BlkStage), hipMemcpyHostToDevice));
+    if (!P->lstages.empty()) {
+        p = nullptr;
+        e = hipMalloc(&p, P->lstages.size() * sizeof(BlkStageL));
+        if (e != hipSuccess)
+            return qs_hip_fail(e, "hipMalloc(plan lane-pair stages)");
+        P->dlstages = static_cast<BlkStageL *>(p);
+        QS_HIP(hipMemcpy(P->dlstages, P->lstages.data(), P->lstages.size() * sizeof(BlkStageL),
+                         hipMemcpyHostToDevice));
+    }
     // 64 zero elements past the end: a block kernel loads 32 elements from the start of a stage's first matrix
     // whatever its size
     const size_t npool = P->pool.size() + 64;
@@ -486,9 +498,12 @@ int upload(qs_plan *P)
     if (int rc = upload_tables(P)) {  // leave nothing half-uploaded: a later run starts over
         if (P->dstages)
             (void)hipFree(P->dstages);
+        if (P->dlstages)
+            (void)hipFree(P->dlstages);
         if (P->dpool)
             (void)hipFree(P->dpool);
         P->dstages = nullptr;
+        P->dlstages = nullptr;
         P->dpool = nullptr;
         return rc;
     }
@@ -710,6 +725,94 @@ extern "C" QS_API int qs_plan_create_learned(qs_plan **out, const qs_circuit *c,
 namespace {
 int append_pass(qs_plan *P, const qs_circuit *c, int mode, const std::vector<int> &L, const std::vector<int> &gs, int b,
                 int stage_width);
+
+// Lane-pair records (BlkStageL) of a pass's 4-position stages, for the 512-thread complex128 kernel of 12-qubit
+// blocks, when every op acts on one or two positions. In each stage the lane starts on the position whose first
+// use comes last; an op on the lane's position first exchanges it with the register position, among those the op
+// leaves alone, whose next use comes last (fewest exchanges ahead). Register bits 0..2 hold the other positions in
+// ascending order at the start; each op's matrix is appended to the pool in the bit order of its register bits.
+void build_lane_stages(qs_plan *P, PlanPass &pp, const std::vector<std::vector<int>> &members,
+                       const std::vector<PG> &sorted_ops)
+{
+    for (int t = 0; t < pp.nstages; ++t) {
+        const BlkStage &st = P->stages[pp.stage_begin + t];
+        if (st.nops < 1)
+            return;
+        for (int o = 0; o < st.nops; ++o)
+            if (__builtin_popcount((st.masks >> (4 * o)) & 15u) > 2)
+                return;
+    }
+    pp.lstage_begin = (int)P->lstages.size();
+    for (int t = 0; t < pp.nstages; ++t) {
+        const BlkStage &st = P->stages[pp.stage_begin + t];
+        BlkStageL L{};
+        for (int j = 0; j < pp.b - 4; ++j)
+            L.order[j] = st.order[j];
+        L.nops = st.nops;
+        std::vector<uint32_t> pm(st.nops);
+        for (int o = 0; o < st.nops; ++o)
+            pm[o] = (st.masks >> (4 * o)) & 15u;
+        auto next_use = [&](int j, int from) {
+            for (int o = from; o < st.nops; ++o)
+                if ((pm[o] >> j) & 1)
+                    return o;
+            return st.nops;
+        };
+        int lane = 0;
+        for (int j = 1; j < 4; ++j)
+            if (next_use(j, 0) > next_use(lane, 0))
+                lane = j;
+        int reg_of[4];
+        for (int j = 0, r = 0; j < 4; ++j)
+            reg_of[j] = j == lane ? -1 : r++;
+        auto placement = [&](uint32_t *tab, uint32_t &lane_off) {
+            for (int a = 0; a < 8; ++a) {
+                uint32_t m = 0;
+                for (int j = 0; j < 4; ++j)
+                    if (j != lane)
+                        m |= (uint32_t)((a >> reg_of[j]) & 1) << j;
+                tab[a] = st.soff[m];
+            }
+            lane_off = st.soff[1u << lane];
+        };
+        placement(L.rd, L.rd_lane);
+        L.mat_base = (uint32_t)P->pool.size();
+        for (int o = 0; o < st.nops; ++o) {
+            if ((pm[o] >> lane) & 1) {
+                int best = -1;
+                for (int j = 0; j < 4; ++j)
+                    if (j != lane && !((pm[o] >> j) & 1) && (best < 0 || next_use(j, o + 1) > next_use(best, o + 1)))
+                        best = j;
+                const int r = reg_of[best];
+                reg_of[lane] = r;
+                reg_of[best] = -1;
+                lane = best;
+                L.swaps |= (uint32_t)(r + 1) << (2 * o);
+            }
+            int regs[2], nr = 0;  // register bits of the op's positions, in ascending position order
+            uint32_t rm = 0;
+            for (int j = 0; j < 4; ++j)
+                if ((pm[o] >> j) & 1) {
+                    regs[nr++] = reg_of[j];
+                    rm |= 1u << reg_of[j];
+                }
+            L.masks |= rm << (4 * o);
+            const std::vector<cd> &U = sorted_ops[members[t][o]].m;
+            if (nr == 2 && regs[0] > regs[1]) {  // matrix bits in register order: exchange index bits 0 and 1
+                std::vector<cd> V(16);
+                auto sw = [](int x) { return ((x & 1) << 1) | ((x >> 1) & 1); };
+                for (int a = 0; a < 4; ++a)
+                    for (int b2 = 0; b2 < 4; ++b2)
+                        V[a * 4 + b2] = U[sw(a) * 4 + sw(b2)];
+                push_matrix(P->pool, V);
+            } else {
+                push_matrix(P->pool, U);
+            }
+        }
+        placement(L.wr, L.wr_lane);
+        P->lstages.push_back(L);
+    }
+}
 
 struct PassSpec {
     std::vector<int> L;      // local set (empty: a single non-blockable gate)
@@ -989,6 +1092,8 @@ int append_pass(qs_plan *P, const qs_circuit *c, int mode, const std::vector<int
         for (int i : members)
             for (int gi : fused[i].members)
                 pp.order.push_back(c->gates[gi].raw);
+    if (P->dtype == QS_C128 && W == 4 && b == 12 && qs_tunables().block_lanes)
+        build_lane_stages(P, pp, stage_members, sorted_ops);
     // complex64: the pass's stages with the most arithmetic (at least that of mfma_stage_ops 2-qubit ops; up to
     // kMaxMfmaStages, the LDS they may take) become dense 16 x 16 products on the matrix cores. Op by op a
     // k-qubit op costs 2^(k+2) FMAs per amplitude; the dense product costs 64, but FP32 MFMA runs at twice the
@@ -1129,7 +1234,8 @@ QS_API int qs_plan_run_range(qs_state *st, qs_plan *P, int begin, int end)
         case 0: {
             const InsBits outer = qs_make_ins(pp.lmask, 0);
             QS_HIP(launch_block(st->dtype, pp.b, pp.sw, st->psi, (uint64_t)1 << (P->n - pp.b), outer, pp.bm,
-                                P->dstages + pp.stage_begin, pp.nstages, P->dpool, pp.mf, st->stream));
+                                P->dstages + pp.stage_begin, pp.nstages, P->dpool, pp.mf,
+                                pp.lstage_begin >= 0 ? P->dlstages + pp.lstage_begin : nullptr, st->stream));
             break;
         }
         case 1: {
@@ -1290,6 +1396,8 @@ QS_API int qs_plan_free(qs_plan *P)
         return qs_fail(QS_EINVAL, "qs_plan_free: NULL plan");
     if (P->dstages)
         (void)hipFree(P->dstages);
+    if (P->dlstages)
+        (void)hipFree(P->dlstages);
     if (P->dpool)
         (void)hipFree(P->dpool);
     delete P;

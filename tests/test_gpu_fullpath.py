@@ -26,7 +26,8 @@ TOL128 = 1e-12
 @pytest.fixture
 def tunables():
     """Set tunables for one test and restore the library defaults afterwards."""
-    defaults = {"block_wg_per_cu": 32, "mfma_wg_per_cu": 2, "block_async": 0, "plan_beam": 16, "mfma_stage_ops": 3}
+    defaults = {"block_wg_per_cu": 32, "mfma_wg_per_cu": 2, "block_async": 0, "plan_beam": 16, "mfma_stage_ops": 3,
+                "block_lanes": 0}
     touched = []
 
     def set_(name, value):
@@ -74,6 +75,36 @@ def test_block_pass_many_blocks_per_workgroup(gpu, tunables, n, layers, dtype, l
     got, info = _plan_run(gpu, circ, 12, low, psi0, dtype)
     assert info["block"] >= 2 and (1 << (n - 12)) >= 4 * 256
     _check(np.asarray(got, np.complex128), oracle.run(circ, psi0), dtype)
+
+
+@pytest.mark.parametrize("n,layers,wg", [(14, 8, 32), (22, 6, 1), (24, 4, 32)])
+def test_lane_pair_block_pass(gpu, tunables, n, layers, wg):
+    """complex128 12-qubit block passes in lane-pair form (block_lanes 1: 512 threads, each 16-amplitude register
+    group held by lanes l and l + 32, the lane bit exchanged with a register bit by v_permlane32_swap before an op on
+    the lane's position) against the oracle, with 4 and 3 always-local low qubits; n = 22 with 128 workgroups walks
+    8 blocks per workgroup."""
+    tunables("block_lanes", 1)
+    tunables("block_wg_per_cu", wg)
+    circ = C.su4_u3_random(n=n, seed=970 + n, layers=layers)
+    psi0 = C.random_state(n, 971 + n)
+    ref = oracle.run(circ, psi0)
+    for low in (4, 3):
+        got, info = _plan_run(gpu, circ, 12, low, psi0, "c128")
+        assert info["block"] >= 1
+        _check(got, ref, "c128")
+
+
+def test_lane_pair_form_with_three_position_ops(gpu, tunables):
+    """With block_lanes 1, a plan whose passes mix 1-, 2- and 3-position ops: passes holding a 3-position op keep the
+    one-lane kernel, the others run in lane-pair form, one after the other on the same state."""
+    tunables("block_lanes", 1)
+    n = 20
+    circ = C.mixed_layers(n=n, seed=980, layers=6, toffolis=12, swap_s=4)
+    extra = C.random_circuit(n, seed=981, num_ops=60, kmax=3, kinds=("dense", "diag", "ctrl"))
+    circ = C.Circuit(n, list(circ.ops) + list(extra.ops), name="mixed+random3")
+    psi0 = C.random_state(n, 982)
+    got, info = _plan_run(gpu, circ, 12, 4, psi0, "c128")
+    _check(got, oracle.run(circ, psi0), "c128")
 
 
 def test_block_passes_with_three_position_ops(gpu):
