@@ -430,8 +430,9 @@ def main():
     # plain: one pass per gate (on a prefix of the circuit in tuned mode: the per-gate rate is layer-invariant)
     plain_ops = ops if args.mode == "plain" else [o for o in ops if o.layer <= args.plain_layers]
     units = [(_kernel_class(o), _alg_bytes(o, n, 16), _alg_flops(o, n)) for o in plain_ops]
-    p_times, p_per = time_steps(st, args.steps if args.mode == "plain" else 1,
-                                args.warmup if args.mode == "plain" else 0,
+    # tuned mode: one warmup and two timed passes over the prefix (their spread is reported)
+    p_times, p_per = time_steps(st, args.steps if args.mode == "plain" else 2,
+                                args.warmup if args.mode == "plain" else 1,
                                 lambda ev: run_plain(st, plain_ops, ev) if ev else [st.apply_op(o) for o in plain_ops],
                                 units, torch)
     plain_rate = len(plain_ops) / (sum(p_times) / len(p_times))
@@ -525,7 +526,8 @@ def main():
                          flops_per_launch=fsum // cnt, hbm_tbs=achieved, hbm_frac=achieved / HBM_PEAK_TBS,
                          fp64_tflops=tflops, fp64_frac=tflops / FP64_PEAK_TFLOPS,
                          frac_of_roofline=max(t_hbm, t_alu) / avg),
-        "plain": {"gates_per_s": plain_rate, "gates_timed": len(plain_ops),
+        "plain": {"gates_per_s": plain_rate, "gates_timed": len(plain_ops), "timed_passes": len(p_times),
+                  "spread": (max(p_times) - min(p_times)) / min(p_times),
                   "per_kernel": summarize(p_per, len(p_times))},
         "speedup_vs_plain": (gates / t_step) / plain_rate,
         "speedup_vs_greedy_plan": ((gates / t_step) / results[greedy_key]["gates_per_s"]

@@ -220,10 +220,14 @@ QS_API int qs_circuit_run(qs_state *st, const qs_circuit *c);
 
 enum {
     QS_PLAN_BLOCK = 0, /* LDS block passes over a qubit set of block_bits qubits (8..13) */
-    QS_PLAN_FUSE = 1   /* dense fused blocks of at most block_bits qubits (1..6) */
+    QS_PLAN_FUSE = 1,  /* dense fused blocks of at most block_bits qubits (1..6) */
+    QS_PLAN_REMAP = 2  /* Sec. III-B / III-D on one GPU: block passes over the lowest block_bits physical qubits only,
+                        * a logical -> physical qubit map, fused-swaps inserted to bring each pass's qubits into that
+                        * range, circuit fused-swaps absorbed into the map (relabel passes, no data moved), and the
+                        * identity map restored by fused-swaps at the end */
 };
 typedef struct {
-    int mode;       /* QS_PLAN_BLOCK or QS_PLAN_FUSE */
+    int mode;       /* QS_PLAN_BLOCK, QS_PLAN_FUSE or QS_PLAN_REMAP */
     int block_bits; /* BLOCK: qubits local to one workgroup; FUSE: largest fused gate */
     int low_bits;   /* BLOCK: the lowest low_bits qubits are always local (whole cache lines per segment) */
     int dtype;      /* QS_C128 / QS_C64: precision the plan's matrices are uploaded in */
@@ -239,11 +243,12 @@ QS_API int qs_plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts
  * QS_EINVAL if n or dtype differ from the plan's, or if the plan was uploaded to another device. */
 QS_API int qs_plan_run(qs_state *st, qs_plan *p);
 QS_API int qs_plan_run_range(qs_state *st, qs_plan *p, int begin, int end);
-/* Pass counts: all passes, LDS block passes, dense passes, others (fused-swaps, large controlled gates), and the
- * number of fused operations executed inside the block / dense passes. Any output may be NULL. */
+/* Pass counts: all passes, LDS block passes, dense passes, others (fused-swaps, large controlled gates, relabels),
+ * and the number of fused operations executed inside the block / dense passes. Any output may be NULL. */
 QS_API int qs_plan_info(const qs_plan *p, int *npasses, int *nblock, int *ndense, int *nother, int *nfused_ops);
-/* Pass i: type (0 block, 1 dense, 2 fused-swap, 3 other), qubits it spans and their mask, fused operations in it
- * and circuit gates it carries. */
+/* Pass i: type (0 block, 1 dense, 2 fused-swap, 3 other, 4 relabel: a circuit fused-swap absorbed into a remapped
+ * plan's qubit map, which runs no kernel), qubits it spans and their mask, fused operations in it and circuit gates
+ * it carries. Fused-swaps a remapped plan inserts carry no circuit gates. */
 QS_API int qs_plan_pass_info(const qs_plan *p, int i, int *type, int *nqubits, int64_t *qmask, int *nops,
                              int *ngates);
 /* The circuit gates pass i carries, in the order the pass applies them (inside a block pass: stage by stage, each

@@ -19,7 +19,7 @@ LIB_PATH = os.environ.get("QS_LIBQS") or os.path.join(PKG, "libqs.so")
 QS_OK, QS_EINVAL, QS_ENOMEM, QS_EDEVICE, QS_EUNSUPPORTED = 0, -1, -2, -3, -4
 QS_C128, QS_C64 = 0, 1
 QS_MAX_K, QS_MAX_DIAG_K, QS_MAX_CONTROLS, QS_MAX_QUBITS = 6, 12, 16, 40
-QS_PLAN_BLOCK, QS_PLAN_FUSE = 0, 1
+QS_PLAN_BLOCK, QS_PLAN_FUSE, QS_PLAN_REMAP = 0, 1, 2
 QS_PLAN_NFEAT = 48
 
 

@@ -27,6 +27,8 @@ GREEDY = ("block", 12, 4)
 def candidates(n: int) -> List[Tuple[str, int, int]]:
     out = [("block", b, w) for b in (10, 11, 12, 13) for w in (3, 4) if b <= n and n >= 8]
     out += [("fuse", k, 0) for k in (2, 3, 4, 5, 6) if k <= n]
+    if n >= 13:  # the paper's swap-based remapping: blocks on the low 12 physical qubits, fused-swaps inserted
+        out.append(("remap", 12, 0))
     return out
 
 
@@ -36,6 +38,12 @@ def greedy_for(n: int) -> Tuple[str, int, int]:
 
 def plan_features(plan) -> np.ndarray:
     return np.stack([B.qs_plan_features(plan.h, i) for i in range(plan.info()["passes"])])
+
+
+def kernel_passes(plan) -> np.ndarray:
+    """Mask of the passes that run a kernel: relabels (type 4, a circuit fused-swap absorbed into a remapped plan's
+    qubit map) move no data and cost nothing, so they are neither priced nor trained on."""
+    return np.array([B.qs_plan_pass_info(plan.h, i)["type"] != 4 for i in range(plan.info()["passes"])], dtype=bool)
 
 
 def time_plan_passes(state, plan, reps: int = 2) -> np.ndarray:
@@ -116,8 +124,9 @@ def collect(circs, dtypes=("c128", "c64"), log=print, groups=None):
             t0 = time.perf_counter()
             for ci, (mode, bits, low) in enumerate(candidates(n)):
                 p = Plan(c, mode, bits, low, dt)
-                ms = time_plan_passes(st, p)
-                X.append(plan_features(p))
+                keep = kernel_passes(p)
+                ms = time_plan_passes(st, p)[keep]
+                X.append(plan_features(p)[keep])
                 y.append(np.log(np.maximum(ms, 1e-4)))
                 if groups is not None:
                     groups.extend([(gid, ci)] * len(ms))
@@ -193,7 +202,8 @@ class CostModel:
         return np.concatenate(out) if out else np.zeros(0, np.float32)
 
     def predict_plan_ms(self, plan) -> float:
-        return float(np.exp(self.predict_log_ms(plan_features(plan)).astype(np.float64)).sum())
+        X = plan_features(plan)[kernel_passes(plan)]
+        return float(np.exp(self.predict_log_ms(X).astype(np.float64)).sum()) if len(X) else 0.0
 
     def save(self, path: str) -> None:
         np.savez(path, params=B.qs_mlp_get_params(self.h), mean=self.mean, std=self.std, hidden=self.hidden,

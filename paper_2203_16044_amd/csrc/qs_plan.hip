@@ -6,7 +6,11 @@
 //   QS_PLAN_BLOCK  LDS block passes: each pass picks a set L of `block_bits` qubits (always containing the
 //                  `low_bits` lowest ones) and applies, inside LDS, every pending gate whose qubits lie in L;
 //   QS_PLAN_FUSE   dense fused blocks: each pass multiplies the pending gates on at most `block_bits` (<= 6) qubits
-//                  into one matrix, run by the register kernel (k <= 4) or the MFMA kernel (k = 5, 6).
+//                  into one matrix, run by the register kernel (k <= 4) or the MFMA kernel (k = 5, 6);
+//   QS_PLAN_REMAP  the paper's local / global split (Sec. III-B) with fused-swap insertion (Sec. III-D): block passes
+//                  only over the lowest `block_bits` physical qubits (contiguous blocks), a logical -> physical
+//                  qubit map, fused-swaps that bring a pass's qubits into that range before it, circuit fused-swaps
+//                  absorbed into the map, and the identity map restored at the end.
 // Both respect the circuit's order: a gate joins a pass only when every earlier gate on its qubits has been
 // placed. Fused-swaps and gates too large for a pass run as passes of their own. The plan's final state equals
 // the circuit's (up to rounding): no qubit relabelling is left behind.
@@ -115,7 +119,7 @@ struct qs_circuit {
 };
 
 struct PlanPass {
-    int type = 0;  // 0 block, 1 dense, 2 fused-swap, 3 raw op
+    int type = 0;  // 0 block, 1 dense, 2 fused-swap, 3 raw op, 4 relabel (a circuit fused-swap absorbed into the map)
     int b = 0;
     uint64_t lmask = 0;
     BlockMap bm{};
@@ -1149,6 +1153,154 @@ int append_pass(qs_plan *P, const qs_circuit *c, int mode, const std::vector<int
     return QS_OK;
 }
 
+// QS_PLAN_REMAP: the block passes the former chose (logical qubit sets), run on the lowest b physical qubits. Before
+// each pass, the pass's qubits that sit at physical positions >= b are exchanged with low positions whose qubits the
+// pass does not use (those needed latest again), paired in ascending order and merged into fused_swap(p, q, s)
+// wherever both sides run on contiguously; the gates then act on their physical qubits. A circuit fused-swap is a
+// relabelling of the map (no data moves: a zero-cost pass keeps its place in the pass order). At the end, fused-swaps
+// put every logical qubit back at its own position, so the plan's final state is the circuit's.
+int plan_remap(qs_plan *P, const qs_circuit &c, int b, int stage_width, const std::vector<PassSpec> &passes)
+{
+    const int n = c.n;
+    std::vector<int> phys(n), lg(n);  // logical -> physical, physical -> logical
+    for (int q = 0; q < n; ++q)
+        phys[q] = lg[q] = q;
+    auto swap_pass = [&](int p, int q, int s) {
+        PlanPass sp;
+        sp.type = 2;
+        sp.p = std::min(p, q);
+        sp.q = std::max(p, q);
+        sp.s = s;
+        sp.ngates = 0;
+        for (int j = 0; j < s; ++j) {
+            std::swap(lg[p + j], lg[q + j]);
+            phys[lg[p + j]] = p + j;
+            phys[lg[q + j]] = q + j;
+        }
+        P->passes.push_back(std::move(sp));
+    };
+    // exchange the physical positions hs[i] (>= b) with vs[i] (< b), both ascending, as few fused-swaps as runs allow
+    auto exchange = [&](const std::vector<int> &hs, const std::vector<int> &vs) {
+        for (size_t i = 0; i < hs.size();) {
+            size_t k = i + 1;
+            while (k < hs.size() && hs[k] == hs[k - 1] + 1 && vs[k] == vs[k - 1] + 1)
+                ++k;
+            swap_pass(vs[i], hs[i], (int)(k - i));
+            i = k;
+        }
+    };
+    // whether pass ps uses logical qubit q, and the index of the next pass (from `from` on) that does
+    auto uses = [&](const PassSpec &ps, int q) {
+        if (!ps.L.empty())
+            return std::find(ps.L.begin(), ps.L.end(), q) != ps.L.end();
+        const PG &g = c.gates[ps.gates[0]];
+        if (g.kind == 1) {
+            const RawOp &r = c.raw[g.raw];
+            return (q >= r.p && q < r.p + r.s) || (q >= r.q && q < r.q + r.s);
+        }
+        return std::find(g.q.begin(), g.q.end(), q) != g.q.end();
+    };
+    auto next_use = [&](size_t from, int q) {
+        for (size_t k = from; k < passes.size(); ++k)
+            if (uses(passes[k], q))
+                return k;
+        return passes.size();
+    };
+    qs_circuit pc;  // the gates on physical qubits, in the order the passes take them
+    pc.n = n;
+    auto physical = [&](const PG &g) {
+        PG h = g;
+        for (int &q : h.q)
+            q = phys[q];
+        return h;
+    };
+    for (size_t k = 0; k < passes.size(); ++k) {
+        const PassSpec &ps = passes[k];
+        if (ps.L.empty()) {
+            const PG &g = c.gates[ps.gates[0]];
+            if (g.kind == 1) {  // relabel: logical p + j and q + j trade physical positions
+                const RawOp &r = c.raw[g.raw];
+                for (int j = 0; j < r.s; ++j) {
+                    const int a = r.p + j, d = r.q + j;
+                    std::swap(phys[a], phys[d]);
+                    lg[phys[a]] = a;
+                    lg[phys[d]] = d;
+                }
+                PlanPass rp;
+                rp.type = 4;
+                rp.p = std::min(r.p, r.q);
+                rp.q = std::max(r.p, r.q);
+                rp.s = r.s;
+                rp.ngates = 1;
+                rp.order.assign(1, g.raw);
+                P->passes.push_back(std::move(rp));
+            } else if (g.kind == 2 || (int)g.q.size() > QS_MAX_K) {  // an opaque op on its physical qubits
+                RawOp r = c.raw[g.raw];
+                for (int &q : r.t)
+                    q = phys[q];
+                for (int &q : r.c)
+                    q = phys[q];
+                PlanPass op;
+                op.type = 3;
+                op.raw = (int)P->raw.size();
+                P->raw.push_back(std::move(r));
+                op.ngates = 1;
+                op.order.assign(1, g.raw);
+                P->passes.push_back(std::move(op));
+            } else {
+                PlanPass dp;
+                dp.ngates = 1;
+                dp.order.assign(1, g.raw);
+                if (int rc = make_dense_pass(P, physical(g), dp))
+                    return rc;
+                P->passes.push_back(std::move(dp));
+            }
+            continue;
+        }
+        // bring the pass's qubits into the low b physical positions
+        std::vector<int> hs, vs;
+        for (int q : ps.L)
+            if (phys[q] >= b)
+                hs.push_back(phys[q]);
+        if (!hs.empty()) {
+            std::vector<std::pair<size_t, int>> free_low;  // (next use, position) of low positions the pass leaves
+            for (int v = 0; v < b; ++v)
+                if (std::find(ps.L.begin(), ps.L.end(), lg[v]) == ps.L.end())
+                    free_low.push_back({next_use(k + 1, lg[v]), v});
+            std::stable_sort(free_low.begin(), free_low.end(),
+                             [](const std::pair<size_t, int> &x, const std::pair<size_t, int> &y) {
+                                 return x.first > y.first;
+                             });
+            for (size_t i = 0; i < hs.size(); ++i)
+                vs.push_back(free_low[i].second);
+            std::sort(hs.begin(), hs.end());
+            std::sort(vs.begin(), vs.end());
+            exchange(hs, vs);
+        }
+        std::vector<int> L, gs;
+        for (int q : ps.L)
+            L.push_back(phys[q]);
+        for (int gi : ps.gates) {
+            gs.push_back((int)pc.gates.size());
+            pc.gates.push_back(physical(c.gates[gi]));
+        }
+        if (int rc = append_pass(P, &pc, QS_PLAN_BLOCK, L, gs, b, stage_width))
+            return rc;
+    }
+    // restore the identity map: the lowest misplaced position takes its qubit back, with the following positions as
+    // long as their qubits lie just as far behind
+    for (int i = 0; i < n; ++i) {
+        if (lg[i] == i)
+            continue;
+        const int j = phys[i];  // > i: positions below i are already home
+        int s = 1;
+        while (i + s < n && j + s < n && lg[i + s] != i + s && phys[i + s] == j + s && j - i >= s + 1)
+            ++s;
+        swap_pass(i, j, s);  // positions i .. i + s - 1 now hold their own qubits
+    }
+    return QS_OK;
+}
+
 int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, int stage_width,
                 const qs_plan_model *model)
 {
@@ -1160,7 +1312,7 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
     int mode = opts->mode, b = opts->block_bits, w = opts->low_bits;
     if (opts->dtype != QS_C128 && opts->dtype != QS_C64)
         return qs_fail(QS_EINVAL, "qs_plan_create: bad dtype %d", opts->dtype);
-    if (mode == QS_PLAN_BLOCK) {
+    if (mode == QS_PLAN_BLOCK || mode == QS_PLAN_REMAP) {
         if (c->n < 8) {  // a block needs at least 256 amplitudes: plan small states as fused dense blocks
             mode = QS_PLAN_FUSE;
             b = std::min(c->n, 4);
@@ -1187,7 +1339,7 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
     P->dtype = opts->dtype;
     P->mode = mode;
     P->raw = c->raw;
-    const int maxq = mode == QS_PLAN_BLOCK ? kMaxBlockOpK : b;
+    const int maxq = mode == QS_PLAN_FUSE ? b : kMaxBlockOpK;
     std::vector<PassSpec> passes;
     if (model) {
         if (int rc = learned_passes(*c, P->dtype, *model, stage_width, passes)) {
@@ -1201,6 +1353,14 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
         F.run(fp, singles);
         for (auto &pr : fp)
             passes.push_back({pr.first, pr.second, b});
+    }
+    if (mode == QS_PLAN_REMAP) {
+        if (int rc = plan_remap(P, *c, b, stage_width, passes)) {
+            delete P;
+            return rc;
+        }
+        *out = P;
+        return QS_OK;
     }
     for (const PassSpec &ps : passes)
         if (int rc = append_pass(P, c, mode, ps.L, ps.gates, ps.b, stage_width)) {
@@ -1246,6 +1406,8 @@ QS_API int qs_plan_run_range(qs_state *st, qs_plan *P, int begin, int end)
         }
         case 2:
             QS_HIP(launch_fused_swap(st->dtype, st->psi, P->n, pp.p, pp.q, pp.s, st->stream));
+            break;
+        case 4:  // relabel: absorbed into the qubit map, no data moves
             break;
         default:
             if (int rc = run_raw(st, P->raw[pp.raw]))
@@ -1297,6 +1459,7 @@ QS_API int qs_plan_pass_info(const qs_plan *P, int i, int *type, int *nqubits, i
     case 0: nq = pp.b; m = (int64_t)pp.lmask; break;
     case 1: nq = pp.k; m = (int64_t)pp.tmask; break;
     case 2:
+    case 4:
         nq = 2 * pp.s;
         for (int j = 0; j < pp.s; ++j)
             m |= ((int64_t)1 << (pp.p + j)) | ((int64_t)1 << (pp.q + j));

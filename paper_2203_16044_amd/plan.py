@@ -8,7 +8,7 @@ from __future__ import annotations
 
 from . import binding as B
 
-MODES = {"block": B.QS_PLAN_BLOCK, "fuse": B.QS_PLAN_FUSE}
+MODES = {"block": B.QS_PLAN_BLOCK, "fuse": B.QS_PLAN_FUSE, "remap": B.QS_PLAN_REMAP}
 
 
 class Circuit:

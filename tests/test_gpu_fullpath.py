@@ -107,6 +107,30 @@ def test_lane_pair_form_with_three_position_ops(gpu, tunables):
     _check(got, oracle.run(circ, psi0), "c128")
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,bits,low", [(16, 10, 0), (20, 12, 0), (22, 12, 3)])
+def test_remap_plan(gpu, dtype, n, bits, low):
+    """QS_PLAN_REMAP on the GPU: block passes over the lowest physical qubits, inserted fused-swaps, circuit
+    fused-swaps absorbed as relabels, the identity map restored; against the oracle element by element."""
+    circ = C.mixed_layers(n=n, seed=990 + n, layers=8, toffolis=8, swap_s=4)
+    extra = C.su4_u3_random(n=n, seed=991 + n, layers=3)
+    circ = C.Circuit(n, list(circ.ops) + list(extra.ops), name="mixed+su4")
+    psi0 = C.random_state(n, 992 + n)
+    if dtype == "c64":
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)
+    st = gpu.State(n, dtype)
+    st.set(psi0)
+    c = Circuit.from_ops(n, circ.ops)
+    p = Plan(c, "remap", bits, low, dtype)
+    types = {x["type"] for x in p.passes()}
+    assert 2 in types and 4 in types
+    p.run(st)
+    got = st.get()
+    for h in (p, c, st):
+        h.close()
+    _check(np.asarray(got, np.complex128), oracle.run(circ, psi0), dtype)
+
+
 def test_block_passes_with_three_position_ops(gpu):
     """A circuit with Toffolis, random 3-qubit gates and fused-swaps at 20 qubits: block passes whose stages hold
     3-position ops (8 x 8 matrices) beside 1- and 2-position ones, and fused-swap passes, in one plan."""

@@ -214,3 +214,68 @@ def test_pass_gates_validates():
         B.qs_plan_pass_gates(p.h, -1)
     p.close()
     c.close()
+
+
+def _remap_execute(circ, plan, psi0):
+    """Run a remapped plan on the oracle from its pass list alone: an inserted fused-swap (type 2, no circuit
+    gates) moves amplitudes between physical qubit ranges, a relabel (type 4) only updates the logical -> physical
+    map, and every other gate acts on the physical qubits its logical qubits map to at that point. Returns the final
+    state and the final map."""
+    import dataclasses
+
+    import oracle
+    n = circ.n
+    phys, lg = list(range(n)), list(range(n))
+    psi = np.array(psi0, dtype=np.complex128, copy=True)
+    for info, gs in zip(plan.passes(), plan.pass_gates()):
+        if info["type"] == 2 and info["ngates"] == 0:
+            m = info["qmask"]
+            qs = [q for q in range(n) if (m >> q) & 1]
+            s = len(qs) // 2
+            p, q = qs[0], qs[s]
+            oracle.fused_swap(psi, p, q, s)
+            for j in range(s):
+                lg[p + j], lg[q + j] = lg[q + j], lg[p + j]
+                phys[lg[p + j]], phys[lg[q + j]] = p + j, q + j
+            continue
+        for i in gs:
+            op = circ.ops[i]
+            if op.kind == "fswap":
+                assert info["type"] == 4
+                for j in range(op.s):
+                    a, d = op.p + j, op.q + j
+                    phys[a], phys[d] = phys[d], phys[a]
+                    lg[phys[a]], lg[phys[d]] = a, d
+                continue
+            mapped = dataclasses.replace(op, targets=tuple(phys[t] for t in op.targets),
+                                         controls=tuple(phys[c] for c in op.controls))
+            oracle.apply_op(psi, mapped)
+    return psi, phys
+
+
+@pytest.mark.parametrize("bits,low", [(8, 0), (10, 3), (12, 0)])
+def test_remap_plan_executes_the_circuit(bits, low):
+    """QS_PLAN_REMAP: every gate placed once; every block pass spans the lowest `bits` physical qubits (contiguous
+    blocks); executed from its pass list on the oracle (inserted fused-swaps move data, relabels only rename), the
+    plan gives the circuit's state with the identity map restored. Circuits with fused-swaps (relabel passes),
+    3-qubit gates and more qubits than a block."""
+    import oracle
+    circs = [C.su4_u3_random(n=16, seed=31, layers=6), C.mixed_layers(n=16, seed=32, layers=8, toffolis=8, swap_s=4),
+             C.random_circuit(14, seed=33, num_ops=150, kmax=3)]
+    for circ in circs:
+        c = Circuit.from_ops(circ.n, circ.ops)
+        p = Plan(c, "remap", bits, low)
+        assert _gates_placed(p) == len(circ.ops)
+        kinds = set()
+        for info in p.passes():
+            kinds.add(info["type"])
+            if info["type"] == 0:
+                assert info["qmask"] == (1 << min(bits, circ.n)) - 1
+        psi0 = C.random_state(circ.n, 34)
+        got, phys = _remap_execute(circ, p, psi0)
+        assert phys == list(range(circ.n))
+        assert np.max(np.abs(got - oracle.run(circ, psi0))) <= 1e-12, circ.name
+        if any(o.kind == "fswap" for o in circ.ops):
+            assert 4 in kinds  # circuit fused-swaps became relabels
+        p.close()
+        c.close()
