@@ -31,12 +31,12 @@ __device__ __forceinline__ uint64_t spread(uint32_t m, const BlockMap &bm) { ret
 // with their lowest counter bits, so 16 consecutive lanes always touch 16 different bank groups.
 __device__ __forceinline__ uint32_t swz(uint32_t m) { return blk_swz(m); }
 
-// Apply a k-qubit op (k = popcount(MASK) <= 3) to the 2^W register amplitudes x[a], a = the W stage bits. Matrix
-// bit j <-> the j-th set bit of MASK (ascending); U is 2^k x 2^k, interleaved, in the compute precision.
+// Apply a k-qubit op (k = popcount(MASK) <= 3) to the 2^W register amplitudes x[a], a = the W stage bits, writing
+// the results to y (y must not alias x). Matrix bit j <-> the j-th set bit of MASK (ascending); U is 2^k x 2^k,
+// interleaved, in the compute precision.
 template <class R, int W, int MASK>
-__device__ __forceinline__ void reg_op(typename BT<R>::C2 *x, const R *__restrict__ U)
+__device__ __forceinline__ void reg_op_to(const typename BT<R>::C2 *x, typename BT<R>::C2 *y, const R *__restrict__ U)
 {
-    using C2 = typename BT<R>::C2;
     constexpr int K = __builtin_popcount(MASK);
     constexpr int D = 1 << K;
     int bitpos[3] = {0, 0, 0};
@@ -50,14 +50,14 @@ __device__ __forceinline__ void reg_op(typename BT<R>::C2 *x, const R *__restric
     for (int rest = 0; rest < (1 << W); ++rest) {
         if (rest & MASK)
             continue;  // enumerate the combinations of the other stage bits once
-        C2 v[D];
+        int idx[D];
 #pragma unroll
         for (int a = 0; a < D; ++a) {
             int r = rest;
 #pragma unroll
             for (int j = 0; j < K; ++j)
                 r |= ((a >> j) & 1) << bitpos[j];
-            v[a] = x[r];
+            idx[a] = r;
         }
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -65,19 +65,26 @@ __device__ __forceinline__ void reg_op(typename BT<R>::C2 *x, const R *__restric
 #pragma unroll
             for (int b = 0; b < D; ++b) {
                 const R ur = U[2 * (a * D + b)], ui = U[2 * (a * D + b) + 1];
-                yr = fma(ur, v[b].x, yr);
-                yr = fma(-ui, v[b].y, yr);
-                yi = fma(ur, v[b].y, yi);
-                yi = fma(ui, v[b].x, yi);
+                yr = fma(ur, x[idx[b]].x, yr);
+                yr = fma(-ui, x[idx[b]].y, yr);
+                yi = fma(ur, x[idx[b]].y, yi);
+                yi = fma(ui, x[idx[b]].x, yi);
             }
-            int r = rest;
-#pragma unroll
-            for (int j = 0; j < K; ++j)
-                r |= ((a >> j) & 1) << bitpos[j];
-            x[r].x = yr;
-            x[r].y = yi;
+            y[idx[a]].x = yr;
+            y[idx[a]].y = yi;
         }
     }
+}
+
+// The same op in place.
+template <class R, int W, int MASK>
+__device__ __forceinline__ void reg_op(typename BT<R>::C2 *x, const R *__restrict__ U)
+{
+    typename BT<R>::C2 v[1 << W];
+#pragma unroll
+    for (int a = 0; a < (1 << W); ++a)
+        v[a] = x[a];
+    reg_op_to<R, W, MASK>(v, x, U);
 }
 
 template <class R, int W>
@@ -113,23 +120,35 @@ __device__ __forceinline__ void reg_op_dispatch(typename BT<R>::C2 *x, int mask,
     }
 }
 
-// Ops on at most two stage positions, their matrix read from U (which may be a register array of 32 values: the
-// largest such matrix, 4 x 4 complex, has 16 entries).
-template <class R, int W>
-__device__ __forceinline__ void reg_op_dispatch_k2(typename BT<R>::C2 *x, int mask, const R *U)
+// Out-of-place dispatch over the masks of a 4-position stage (K2: ops on at most two positions only, whose matrix
+// U may be a register array of 32 values: the largest such matrix, 4 x 4 complex, has 16 entries).
+template <class R, bool K2>
+__device__ __forceinline__ void reg_op_dispatch_to(const typename BT<R>::C2 *x, typename BT<R>::C2 *y, int mask,
+                                                   const R *U)
 {
-    static_assert(W == 4, "4-position stages");
     switch (mask) {
-    case 1: reg_op<R, 4, 1>(x, U); break;
-    case 2: reg_op<R, 4, 2>(x, U); break;
-    case 3: reg_op<R, 4, 3>(x, U); break;
-    case 4: reg_op<R, 4, 4>(x, U); break;
-    case 5: reg_op<R, 4, 5>(x, U); break;
-    case 6: reg_op<R, 4, 6>(x, U); break;
-    case 8: reg_op<R, 4, 8>(x, U); break;
-    case 9: reg_op<R, 4, 9>(x, U); break;
-    case 10: reg_op<R, 4, 10>(x, U); break;
-    default: reg_op<R, 4, 12>(x, U); break;
+    case 1: reg_op_to<R, 4, 1>(x, y, U); break;
+    case 2: reg_op_to<R, 4, 2>(x, y, U); break;
+    case 3: reg_op_to<R, 4, 3>(x, y, U); break;
+    case 4: reg_op_to<R, 4, 4>(x, y, U); break;
+    case 5: reg_op_to<R, 4, 5>(x, y, U); break;
+    case 6: reg_op_to<R, 4, 6>(x, y, U); break;
+    case 8: reg_op_to<R, 4, 8>(x, y, U); break;
+    case 9: reg_op_to<R, 4, 9>(x, y, U); break;
+    case 10: reg_op_to<R, 4, 10>(x, y, U); break;
+    default:
+        if constexpr (K2) {
+            reg_op_to<R, 4, 12>(x, y, U);
+        } else {
+            switch (mask) {
+            case 7: reg_op_to<R, 4, 7>(x, y, U); break;
+            case 11: reg_op_to<R, 4, 11>(x, y, U); break;
+            case 12: reg_op_to<R, 4, 12>(x, y, U); break;
+            case 13: reg_op_to<R, 4, 13>(x, y, U); break;
+            default: reg_op_to<R, 4, 14>(x, y, U); break;
+            }
+        }
+        break;
     }
 }
 
@@ -195,7 +214,6 @@ struct StagePipe {
     uint32_t addr[1 << W];  // LDS byte address of member a of this thread's group
     uint32_t masks, mat_base;
     int nops, mfma;
-    R m0[32];  // the first op's matrix when it acts on at most two positions (the pool is padded past its end)
 };
 
 template <class R, int B, int W>
@@ -214,45 +232,67 @@ __device__ __forceinline__ void stage_fetch(StagePipe<R, B, W> &p, const BlkStag
     p.mat_base = stg.mat_base;
     p.nops = stg.nops;
     p.mfma = stg.mfma;
-    if constexpr (W == 4) {
-        const R *u = mats + stg.mat_base;
-#pragma unroll
-        for (int i = 0; i < 32; ++i)
-            p.m0[i] = u[i];
-    }
 }
 
-// Run stage `cur` (one group per thread) and form `nxt` from record `next` meanwhile.
+// Run stage `cur` (one group per thread) and form `nxt` from record `next` meanwhile. The ops alternate between two
+// register arrays (x -> y -> x ...), so that no op's results have to be copied back over its inputs.
 template <class R, int B, int W>
 __device__ __forceinline__ void run_stage_piped(typename BT<R>::C2 *s, const StagePipe<R, B, W> &cur,
                                                 StagePipe<R, B, W> &nxt, const BlkStage &next,
                                                 const R *__restrict__ mats)
 {
     using C2 = typename BT<R>::C2;
-    C2 x[1 << W];
+    if constexpr (W != 4) {
+        C2 x[1 << W];
 #pragma unroll
-    for (int a = 0; a < (1 << W); ++a)
-        x[a] = lds_at(s, cur.addr[a]);
+        for (int a = 0; a < (1 << W); ++a)
+            x[a] = lds_at(s, cur.addr[a]);
+        uint32_t moff = cur.mat_base;
+        for (int o = 0; o < cur.nops; ++o) {
+            const int mask = (int)(cur.masks >> (4 * o)) & 15;
+            reg_op_dispatch<R, W>(x, mask, mats + moff);
+            moff += 2u << (2 * __builtin_popcount(mask));
+        }
+#pragma unroll
+        for (int a = 0; a < (1 << W); ++a)
+            lds_at(s, cur.addr[a]) = x[a];
+        stage_fetch<R, B, W>(nxt, next, mats);
+        return;
+    }
+    // The group is read into x when the stage has an odd number of ops (the first op then takes it to y) and into
+    // y otherwise, so that pairs of ops (y -> x -> y) always leave it in y. (The empty asm statements keep the
+    // compiler from hoisting the reads out of the two branches or merging the pair into one copying loop.)
+    C2 x[16], y[16];
     uint32_t moff = cur.mat_base;
     int o = 0;
-    if constexpr (W == 4) {
-        // the first op takes its matrix from the registers loaded during the previous stage, so its arithmetic can
-        // start on the first LDS reads to arrive instead of waiting for a scalar load as well
+    if (cur.nops & 1) {
+        asm volatile("; odd op count" ::: "memory");
+#pragma unroll
+        for (int a = 0; a < 16; ++a)
+            x[a] = lds_at(s, cur.addr[a]);
         const int mask = (int)(cur.masks & 15u);
-        if (cur.nops > 0 && __builtin_popcount(mask) <= 2) {
-            reg_op_dispatch_k2<R, W>(x, mask, cur.m0);
-            moff += 2u << (2 * __builtin_popcount(mask));
-            o = 1;
-        }
+        reg_op_dispatch_to<R, false>(x, y, mask, mats + moff);
+        moff += 2u << (2 * __builtin_popcount(mask));
+        o = 1;
+    } else {
+        asm volatile("; even op count" ::: "memory");
+#pragma unroll
+        for (int a = 0; a < 16; ++a)
+            y[a] = lds_at(s, cur.addr[a]);
     }
-    for (; o < cur.nops; ++o) {
-        const int mask = (int)(cur.masks >> (4 * o)) & 15;
-        reg_op_dispatch<R, W>(x, mask, mats + moff);
+    for (; o < cur.nops; o += 2) {
+        int mask = (int)(cur.masks >> (4 * o)) & 15;
+        asm volatile("; y to x" ::: "memory");
+        reg_op_dispatch_to<R, false>(y, x, mask, mats + moff);
+        moff += 2u << (2 * __builtin_popcount(mask));
+        mask = (int)(cur.masks >> (4 * (o + 1))) & 15;
+        asm volatile("; x to y" ::: "memory");
+        reg_op_dispatch_to<R, false>(x, y, mask, mats + moff);
         moff += 2u << (2 * __builtin_popcount(mask));
     }
 #pragma unroll
-    for (int a = 0; a < (1 << W); ++a)
-        lds_at(s, cur.addr[a]) = x[a];
+    for (int a = 0; a < 16; ++a)
+        lds_at(s, cur.addr[a]) = y[a];
     stage_fetch<R, B, W>(nxt, next, mats);
 }
 
@@ -349,24 +389,26 @@ __device__ __forceinline__ void run_stage_n(typename BT<R>::C2 *s, const BlkStag
 }
 
 // NT threads per workgroup: one register group per thread with 4-position stages (64 threads for 10-qubit blocks,
-// 128 for 11, 256 for 12 and 13); 512 with 3-position stages (8 register amplitudes per thread, so that two 64 KB
-// complex128 blocks per CU run 16 waves when the kernel stays within 128 VGPRs).
-template <class R, int B, int NT> struct BlockBounds {
-    static constexpr int waves_per_eu = NT == 512 || (sizeof(R) == 4 && NT >= 128 && B <= 12) ? 4 : 1;
+// 128 for 11, 256 for 12, 512 for complex128 13-qubit blocks, whose 128 KB hold a CU alone: 8 waves, 2 per SIMD);
+// 512 with 3-position stages (8 register amplitudes per thread, so that two 64 KB complex128 blocks per CU run 16
+// waves when the kernel stays within 128 VGPRs).
+template <class R, int B, int W, int NT> struct BlockBounds {
+    static constexpr int waves_per_eu = (NT == 512 && W == 3) || (sizeof(R) == 4 && NT >= 128 && B <= 12) ? 4 : 1;
 };
 // Complex64 blocks of 11-12 qubits (16-32 KB of LDS) are held to 128 VGPRs for 4 waves per SIMD: 2-4 % faster
 // at 33 qubits than the 3 waves of the unconstrained ~130-VGPR build (the bound costs three 64-bit scratch reloads
 // per block, outside the stage loop); 13-qubit complex64 blocks would spill far more and keep the compiler's choice.
 
 // Threads of a block workgroup: one 2^W-amplitude group per thread (at least one wave; 4-position stages of
-// 13-qubit blocks take two groups per thread).
-template <int B, int W> struct BlockThreads {
+// complex64 13-qubit blocks take two groups per thread).
+template <class R, int B, int W> struct BlockThreads {
     static constexpr int groups = 1 << (B - W);
-    static constexpr int value = W == 3 ? 512 : (groups < 64 ? 64 : (groups > 256 ? 256 : groups));
+    static constexpr int cap = sizeof(R) == 8 ? 512 : 256;
+    static constexpr int value = W == 3 ? 512 : (groups < 64 ? 64 : (groups > cap ? cap : groups));
 };
 
 template <class R, int B, int W, int NT>
-__global__ __launch_bounds__(NT, (BlockBounds<R, B, NT>::waves_per_eu)) void k_block(
+__global__ __launch_bounds__(NT, (BlockBounds<R, B, W, NT>::waves_per_eu)) void k_block(
     typename BT<R>::C2 *__restrict__ psi, uint64_t nblocks, InsBits outer, BlockMap bm,
     const BlkStage *__restrict__ stages, int nstages, const R *__restrict__ mats, BlkMfma mf)
 {
@@ -1123,7 +1165,7 @@ hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const Bloc
                    int nstages, const void *mats, const BlkMfma &mf, const BlkStageL *lstages, hipStream_t s)
 {
     using C2 = typename BT<R>::C2;
-    constexpr int NT = BlockThreads<B, W>::value;
+    constexpr int NT = BlockThreads<R, B, W>::value;
     static_assert((1 << B) >= NT, "block smaller than the workgroup");
     if (mf.n < 0 || mf.n > kMaxMfmaStages || (mf.n > 0 && (sizeof(R) != 4 || W != 4)))
         return hipErrorInvalidValue;

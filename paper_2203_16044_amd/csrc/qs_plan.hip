@@ -469,8 +469,7 @@ int upload_tables(qs_plan *P)
         QS_HIP(hipMemcpy(P->dlstages, P->lstages.data(), P->lstages.size() * sizeof(BlkStageL),
                          hipMemcpyHostToDevice));
     }
-    // 64 zero elements past the end: a block kernel loads 32 elements from the start of a stage's first matrix
-    // whatever its size
+    // 64 zero elements past the end: slack for scalar loads that the kernels issue in whole 64-byte lines
     const size_t npool = P->pool.size() + 64;
     const size_t esz = P->dtype == QS_C128 ? sizeof(double) : sizeof(float);
     p = nullptr;

@@ -77,6 +77,19 @@ def test_block_pass_many_blocks_per_workgroup(gpu, tunables, n, layers, dtype, l
     _check(np.asarray(got, np.complex128), oracle.run(circ, psi0), dtype)
 
 
+@pytest.mark.parametrize("low", [3, 4])
+def test_thirteen_qubit_blocks_many_per_workgroup(gpu, tunables, low):
+    """complex128 13-qubit blocks run one 16-amplitude register group per thread (512 threads, a CU per 128 KB
+    block); with 256 persistent workgroups each walks 8 blocks per pass at n = 24."""
+    tunables("block_wg_per_cu", 1)
+    n = 24
+    circ = C.su4_u3_random(n=n, seed=930 + low, layers=5)
+    psi0 = C.random_state(n, 931 + low)
+    got, info = _plan_run(gpu, circ, 13, low, psi0, "c128")
+    assert info["block"] >= 2 and (1 << (n - 13)) >= 8 * 256
+    _check(np.asarray(got, np.complex128), oracle.run(circ, psi0), "c128")
+
+
 @pytest.mark.parametrize("n,layers,wg", [(14, 8, 32), (22, 6, 1), (24, 4, 32)])
 def test_lane_pair_block_pass(gpu, tunables, n, layers, wg):
     """complex128 12-qubit block passes in lane-pair form (block_lanes 1: 512 threads, each 16-amplitude register
