@@ -40,11 +40,11 @@ PMC_TRAFFIC = {
     "block_b12": {"fetch_kib": 33554778.51, "write_kib": 67110537.76, "fetch_scale": 2.0, "write_scale": 1.0,
                   "sources": ["paper_2203_16044_amd/csrc/qs_block.hip", "paper_2203_16044_amd/csrc/qs_internal.h",
                               "paper_2203_16044_amd/csrc/qs_index.h"],
-                  "sha1": "a79ae94827dca626db76a75a2a4539779d0411d4"},
+                  "sha1": "235cb063a38db5961722df34488b8faade46475d"},
     "dense_k1": {"fetch_kib": 33554446.82, "write_kib": 67110458.13, "fetch_scale": 2.0, "write_scale": 1.0,
                  "sources": ["paper_2203_16044_amd/csrc/qs_kernels.hip", "paper_2203_16044_amd/csrc/qs_internal.h",
                              "paper_2203_16044_amd/csrc/qs_index.h"],
-                 "sha1": "c2159f5d21091fe13e22e4852a9863f219887bf2"},
+                 "sha1": "310359c284daeb789970b997d76a65ff6322e44e"},
 }
 
 

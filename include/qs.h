@@ -376,6 +376,10 @@ QS_API int qs_probe_rmw(void *buf, size_t bytes, void *hip_stream);
  *               stages whose ops amount to at least this many 2-qubit ops' arithmetic (a k-qubit op counts
  *               2^(k-2); the stages with the most) run as one fused 16 x 16 product on the FP32 matrix cores
  *               (0..8, default 3; 0: every stage op by op on the vector ALUs);
+ * "stage_pack"  0/1: how block plans created afterwards group a pass's ops into register stages. 0: repeatedly
+ *               take the ready op that adds the fewest new positions until none fits. 1 (default): each stage
+ *               is seeded in turn by every ready op and filled that way, and the seed whose remaining ops then
+ *               need the fewest such stages wins (ties: more ops in the stage);
  * "plan_beam"   beam width of pass formation for plans created afterwards (0..64, default 16): the local set of a
  *               pass grows one ready gate at a time, keeping the candidates that take the most gates; 0 selects
  *               the fewest-new-qubits greedy. Batches always plan with 4-position stages.

@@ -807,6 +807,10 @@ QS_API int qs_set_tunable(const char *name, int64_t value)
         if (value < 0 || value > 64)
             return qs_fail(QS_EINVAL, "plan_beam must be in [0, 64]");
         t.plan_beam = (int)value;
+    } else if (!std::strcmp(name, "stage_pack")) {
+        if (value != 0 && value != 1)
+            return qs_fail(QS_EINVAL, "stage_pack must be 0 or 1");
+        t.stage_pack = (int)value;
     } else if (!std::strcmp(name, "block_stage_width")) {
         if (value != 3 && value != 4)
             return qs_fail(QS_EINVAL, "block_stage_width must be 3 or 4");

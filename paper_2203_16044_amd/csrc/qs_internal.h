@@ -231,6 +231,7 @@ struct Tunables {
     std::atomic<int> block_async{0};      // 12-qubit block passes: double-buffered LDS with direct-to-LDS loads
     std::atomic<int> block_lanes{0};      // plans created afterwards: complex128 12-qubit lane-pair stages, 512 threads
     std::atomic<int> mfma_stage_ops{3};   // complex64 plans: stages of at least this many ops run fused on MFMA
+    std::atomic<int> stage_pack{1};       // block plans: 0 greedy stage packing, 1 with one stage of lookahead
 };
 Tunables &qs_tunables();
 

@@ -1005,28 +1005,26 @@ int append_pass(qs_plan *P, const qs_circuit *c, int mode, const std::vector<int
             pm |= 1u << (int)(std::find(LL.begin(), LL.end(), q) - LL.begin());
         posmask.push_back(pm);
     }
-    // stages of at most W positions (W = 3 only where a 512-thread kernel exists): repeatedly take ready ops
-    // (every earlier op sharing a position placed) that keep the stage within W positions, fewest new first
+    // stages of at most W positions (W = 3 only where a 512-thread kernel exists). A stage is filled by repeatedly
+    // taking a ready op (every earlier op sharing a position placed) that keeps it within W positions, fewest new
+    // first. With stage_pack 1 each ready op seeds a candidate stage filled that way, and the candidate whose
+    // remaining ops need the fewest stages under the plain rule wins (ties: more ops; then the earliest seed).
     const int W = (stage_width == 3 && (b == 12 || b == 13)) ? 3 : 4;
     pp.sw = W;
     const int nf = (int)fused.size();
-    std::vector<char> placed(nf, 0);
-    int left = nf;
-    pp.stage_begin = (int)P->stages.size();
-    std::vector<std::vector<int>> stage_members;  // fused-op indices of each stage of this pass, in order
-    while (left) {
-        uint32_t S = 0;
-        std::vector<int> members;
+    auto is_ready = [&](const std::vector<char> &pl, int i) {
+        if (pl[i])
+            return false;
+        for (int j = 0; j < i; ++j)
+            if (!pl[j] && (posmask[j] & posmask[i]))
+                return false;
+        return true;
+    };
+    auto fill = [&](std::vector<char> &pl, uint32_t &S, std::vector<int> &members) {
         while ((int)members.size() < kStageMaxOps) {
             int best = -1, bestnew = 99;
             for (int i = 0; i < nf; ++i) {
-                if (placed[i])
-                    continue;
-                bool rdy = true;
-                for (int j = 0; j < i && rdy; ++j)
-                    if (!placed[j] && (posmask[j] & posmask[i]))
-                        rdy = false;
-                if (!rdy)
+                if (!is_ready(pl, i))
                     continue;
                 const int nw = __builtin_popcount(posmask[i] & ~S);
                 if (__builtin_popcount(S | posmask[i]) <= W && nw < bestnew) {
@@ -1036,11 +1034,57 @@ int append_pass(qs_plan *P, const qs_circuit *c, int mode, const std::vector<int
             }
             if (best < 0)
                 break;
-            placed[best] = 1;
-            --left;
+            pl[best] = 1;
             S |= posmask[best];
             members.push_back(best);
         }
+    };
+    auto greedy_stages = [&](std::vector<char> pl) {
+        int cnt = 0;
+        for (;;) {
+            bool left = false;
+            for (char c : pl)
+                left |= !c;
+            if (!left)
+                return cnt;
+            uint32_t S = 0;
+            std::vector<int> m;
+            fill(pl, S, m);
+            ++cnt;
+        }
+    };
+    const bool lookahead = qs_tunables().stage_pack != 0;
+    std::vector<char> placed(nf, 0);
+    int left = nf;
+    pp.stage_begin = (int)P->stages.size();
+    std::vector<std::vector<int>> stage_members;  // fused-op indices of each stage of this pass, in order
+    while (left) {
+        uint32_t S = 0;
+        std::vector<int> members;
+        if (!lookahead) {
+            fill(placed, S, members);
+        } else {
+            int best_rest = 1 << 30;
+            std::vector<char> best_pl;
+            for (int i = 0; i < nf; ++i) {
+                if (!is_ready(placed, i))
+                    continue;
+                std::vector<char> pl = placed;
+                pl[i] = 1;
+                uint32_t s2 = posmask[i];
+                std::vector<int> m{i};
+                fill(pl, s2, m);
+                const int rest = greedy_stages(pl);
+                if (rest < best_rest || (rest == best_rest && m.size() > members.size())) {
+                    best_rest = rest;
+                    best_pl = pl;
+                    members = m;
+                    S = s2;
+                }
+            }
+            placed = best_pl;
+        }
+        left -= (int)members.size();
         for (int p = 0; __builtin_popcount(S) < W && p < b; ++p)
             S |= 1u << p;  // pad with unused positions
         BlkStage stg{};

@@ -70,7 +70,8 @@ def test_tunables_validate():
     B.qs_set_tunable("dense_gpt", 1)
     for name, bad, good in (("block_wg_per_cu", 0, 32), ("block_wg_per_cu", 4097, 32), ("block_stage_width", 5, 4),
                             ("plan_beam", 65, 16), ("plan_beam", -1, 16), ("mfma_stage_ops", 9, 3),
-                            ("mfma_stage_ops", -1, 3), ("block_async", 2, 0), ("block_lanes", 2, 0)):
+                            ("mfma_stage_ops", -1, 3), ("block_async", 2, 0), ("block_lanes", 2, 0),
+                            ("stage_pack", 2, 1), ("stage_pack", -1, 1)):
         with pytest.raises(qs.QSError):
             B.qs_set_tunable(name, bad)
         B.qs_set_tunable(name, good)  # the defaults

@@ -189,6 +189,50 @@ def test_plan_gate_order_reproduces_the_circuit(beam, mode, bits, low, width):
         B.qs_set_tunable("block_stage_width", 4)
 
 
+@pytest.mark.parametrize("pack", [0, 1])
+@pytest.mark.parametrize("mode,bits,low,width", [("block", 10, 3, 4), ("block", 12, 4, 4), ("block", 12, 3, 3),
+                                                 ("block", 13, 3, 4)])
+def test_stage_packing_keeps_the_gate_order(pack, mode, bits, low, width):
+    """Both stage-packing rules (greedy, and greedy with one stage of lookahead) apply the gates in an order that
+    replays to the circuit's state on the oracle."""
+    import oracle
+    circs = [C.random_circuit(13, seed=640 + pack, num_ops=160, kmax=3), C.su4_u3_random(n=14, seed=9, layers=8)]
+    try:
+        B.qs_set_tunable("stage_pack", pack)
+        B.qs_set_tunable("block_stage_width", width)
+        for circ in circs:
+            c = Circuit.from_ops(circ.n, circ.ops)
+            p = Plan(c, mode, bits, low)
+            order = _checked_order(circ, p)
+            p.close()
+            c.close()
+            psi0 = C.random_state(circ.n, 4)
+            got = oracle.run(circ, psi0, ops=[circ.ops[i] for i in order])
+            assert np.max(np.abs(got - oracle.run(circ, psi0))) <= 1e-12, circ.name
+    finally:
+        B.qs_set_tunable("stage_pack", 1)
+        B.qs_set_tunable("block_stage_width", 4)
+
+
+def test_lookahead_packing_takes_fewer_stages():
+    """On the 32-qubit benchmark circuit the lookahead rule packs the same block passes into fewer register stages
+    than the greedy rule (feature 8 of each pass is its stage count / 16)."""
+    circ = C.su4_u3_random(n=32, seed=32, layers=40)
+    c = Circuit.from_ops(circ.n, circ.ops)
+    stages = {}
+    try:
+        for pack in (0, 1):
+            B.qs_set_tunable("stage_pack", pack)
+            p = Plan(c, "block", 12, 4)
+            n = p.info()["passes"]
+            stages[pack] = round(sum(float(B.qs_plan_features(p.h, i)[8]) * 16 for i in range(n)))
+            p.close()
+    finally:
+        B.qs_set_tunable("stage_pack", 1)
+        c.close()
+    assert stages[1] < stages[0], stages
+
+
 @pytest.mark.parametrize("beam", [16, 64])
 def test_benchmark_plan_gate_order(beam):
     """The 32-qubit benchmark circuit's plans (12-qubit blocks, 3 low qubits): the same structural checks."""
