@@ -93,6 +93,7 @@ constexpr int kMaxDev = 64;
 std::atomic<int> g_cus[kMaxDev];  // 0: not queried yet
 std::mutex g_lds_mu;
 std::vector<std::tuple<int, const void *, size_t>> g_lds_set;  // (device, kernel, bytes allowed)
+std::vector<std::pair<int, const void *>> g_nostatic;             // (device, kernel) checked to have no static LDS
 }  // namespace
 
 int qs_cu_count()
@@ -125,6 +126,26 @@ hipError_t qs_allow_lds(const void *fn, size_t bytes)
     if (e != hipSuccess)
         return e;
     g_lds_set.emplace_back(dev, fn, bytes);
+    return hipSuccess;
+}
+
+hipError_t qs_check_no_static_lds(const void *fn)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    std::lock_guard<std::mutex> lock(g_lds_mu);
+    for (auto &t : g_nostatic)
+        if (t.first == dev && t.second == fn)
+            return hipSuccess;
+    hipFuncAttributes attr{};
+    e = hipFuncGetAttributes(&attr, fn);
+    if (e != hipSuccess)
+        return e;
+    if (attr.sharedSizeBytes != 0)
+        return hipErrorInvalidDeviceFunction;
+    g_nostatic.emplace_back(dev, fn);
     return hipSuccess;
 }
 

@@ -163,6 +163,28 @@ __device__ __forceinline__ C2 &lds_at(C2 *s, uint32_t bytes)
     return *reinterpret_cast<C2 *>(reinterpret_cast<unsigned char *>(s) + bytes);
 }
 
+// LDS access by absolute byte address, for kernels whose only LDS is their dynamic buffer (which then starts at
+// address 0; the launch checks that the kernel has no static LDS): no base address to add per access.
+template <class R>
+__device__ __forceinline__ typename BT<R>::C2 lds_get(uint32_t addr)
+{
+    using NV = typename NT2<R>::type;
+    const NV v = *(const __attribute__((address_space(3))) NV *)(uintptr_t)addr;
+    typename BT<R>::C2 c;
+    c.x = v.x;
+    c.y = v.y;
+    return c;
+}
+template <class R>
+__device__ __forceinline__ void lds_put(uint32_t addr, const typename BT<R>::C2 &c)
+{
+    using NV = typename NT2<R>::type;
+    NV v;
+    v.x = c.x;
+    v.y = c.y;
+    *(__attribute__((address_space(3))) NV *)(uintptr_t)addr = v;
+}
+
 // the stage's member offsets, formed by the planner for the plan's precision (slot_bytes of each member's offset)
 template <class C2, int W>
 __device__ __forceinline__ void stage_offsets(const BlkStage &stg, uint32_t *soff)
@@ -269,7 +291,7 @@ __device__ __forceinline__ void run_stage_piped(typename BT<R>::C2 *s, const Sta
         asm volatile("; odd op count" ::: "memory");
 #pragma unroll
         for (int a = 0; a < 16; ++a)
-            x[a] = lds_at(s, cur.addr[a]);
+            x[a] = lds_get<R>(cur.addr[a]);
         const int mask = (int)(cur.masks & 15u);
         reg_op_dispatch_to<R, false>(x, y, mask, mats + moff);
         moff += 2u << (2 * __builtin_popcount(mask));
@@ -278,7 +300,7 @@ __device__ __forceinline__ void run_stage_piped(typename BT<R>::C2 *s, const Sta
         asm volatile("; even op count" ::: "memory");
 #pragma unroll
         for (int a = 0; a < 16; ++a)
-            y[a] = lds_at(s, cur.addr[a]);
+            y[a] = lds_get<R>(cur.addr[a]);
     }
     for (; o < cur.nops; o += 2) {
         int mask = (int)(cur.masks >> (4 * o)) & 15;
@@ -292,7 +314,7 @@ __device__ __forceinline__ void run_stage_piped(typename BT<R>::C2 *s, const Sta
     }
 #pragma unroll
     for (int a = 0; a < 16; ++a)
-        lds_at(s, cur.addr[a]) = y[a];
+        lds_put<R>(cur.addr[a], y[a]);
     stage_fetch<R, B, W>(nxt, next, mats);
 }
 
@@ -483,7 +505,7 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, B, W, NT>::waves_per_eu)) void 
             C2 v;
             v.x = pre[it].x;
             v.y = pre[it].y;
-            lds_at(s, slot_of(sb, it)) = v;
+            lds_put<R>(slot_of(sb, it), v);
         }
     }
     lds_barrier();
@@ -537,7 +559,7 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, B, W, NT>::waves_per_eu)) void 
             const uint32_t sb = opaque_s();
 #pragma unroll
             for (int it = 0; it < PER; ++it) {
-                const C2 v = lds_at(s, slot_of(sb, it));
+                const C2 v = lds_get<R>(slot_of(sb, it));
                 NV w;
                 w.x = v.x;
                 w.y = v.y;
@@ -556,7 +578,7 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, B, W, NT>::waves_per_eu)) void 
                 C2 v;
                 v.x = pre[it].x;
                 v.y = pre[it].y;
-                lds_at(s, slot_of(sb, it)) = v;
+                lds_put<R>(slot_of(sb, it), v);
             }
         }
         lds_barrier();
@@ -1173,6 +1195,9 @@ hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const Bloc
     const size_t shm = data + 256 * sizeof(C2) * mf.n;
     const size_t shm_max = data + (sizeof(R) == 4 && W == 4 ? 256 * sizeof(C2) * kMaxMfmaStages : 0);
     if (hipError_t e = qs_allow_lds((const void *)k_block<R, B, W, NT>, shm_max))
+        return e;
+    // the kernel addresses its LDS absolutely (lds_get / lds_put)
+    if (hipError_t e = qs_check_no_static_lds((const void *)k_block<R, B, W, NT>))
         return e;
     // persistent workgroups (each walks several blocks so its loads can run ahead of its arithmetic)
     const uint64_t cus = (uint64_t)qs_cu_count();

@@ -240,6 +240,9 @@ int qs_cu_count();
 // Allow `fn` up to `bytes` of dynamic LDS on the current device (hipFuncSetAttribute once per device, kernel and
 // larger size; thread-safe).
 hipError_t qs_allow_lds(const void *fn, size_t bytes);
+// hipSuccess if kernel `fn` has no static LDS (its dynamic LDS then starts at address 0), checked once per device
+// and kernel; hipErrorInvalidDeviceFunction otherwise.
+hipError_t qs_check_no_static_lds(const void *fn);
 
 // input width of a cost-model MLP (qs_mlp.hip)
 int qs_mlp_nin(const qs_mlp *m);
