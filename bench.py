@@ -31,13 +31,13 @@ HBM_PEAK_TBS = 8.0  # MI355X HBM3E, published
 FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (= FP64 MFMA): 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
 
 # HBM traffic per dispatch of the dominant kernels, from two rocprofv3 PMC runs of this script (FETCH_SIZE, then
-# WRITE_SIZE; KiB per dispatch, mean over the 32-qubit dispatches), each scaled by what the same counter reads for
-# a device copy of known size (paper_2203_16044_amd.probe copy of 4 GiB: FETCH_SIZE reports 2097200 KiB, half of
+# WRITE_SIZE; KiB per dispatch, mean over the 32-qubit dispatches of the headline plan), each scaled by what the same counter reads for
+# a device copy of known size (paper_2203_16044_amd.probe copy of 4 GiB: FETCH_SIZE reports 2097197 KiB, half of
 # the bytes read, WRITE_SIZE 4194304 KiB, all bytes written). Commands and figures: profiles/*_pmc_traffic.md.
 # The readings hold for the kernel sources they were taken on: `sha1` fingerprints those files and the traffic is
 # reported as null once they differ.
 PMC_TRAFFIC = {
-    "block_b12": {"fetch_kib": 33554812.23, "write_kib": 67110456.75, "fetch_scale": 2.0, "write_scale": 1.0,
+    "block_b12": {"fetch_kib": 33555046.96, "write_kib": 67111911.55, "fetch_scale": 2.0, "write_scale": 1.0,
                   "sources": ["paper_2203_16044_amd/csrc/qs_block.hip", "paper_2203_16044_amd/csrc/qs_internal.h",
                               "paper_2203_16044_amd/csrc/qs_index.h"],
                   "sha1": "c48f66fa64f92e3b98095d93ad320f1d173169a4"},
