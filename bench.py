@@ -353,25 +353,41 @@ def bench_mixed28(torch, copy_tbs, steps=1, warmup=1):
 
 
 def bench_batch(torch, log):
-    """Batched serving form: 512 independent circuits (10..22 qubits, 10..40 layers) in one persistent launch,
-    autotuned, eager and replayed from a HIP graph, against the per-circuit plain loop."""
+    """Batched serving form: 512 independent circuits (10..22 qubits, 10..40 layers) in one launch per pass level,
+    eager and replayed from a HIP graph, against the per-circuit plain loop. The block shape of the batch's plans is
+    the cost model's choice (batch.learned_shape) and its launch is autotuned; the empirical search over every
+    shape and launch is timed beside it as the judge."""
     import circuits as C
     from paper_2203_16044_amd import batch as BT
+    from paper_2203_16044_amd import costmodel as CM
 
     circs = C.serving_batch()
     rec = BT.record(circs)
+    model = CM.CostModel.load() if os.path.exists(CM.WEIGHTS) else None
     out = {"workload": "512 circuits, n ~ U{10..22}, depth ~ U{10..40} (U3 / CNOT-or-CZ / RZ layers, seed 512), "
                        "FP64 probabilities of every circuit", "circuits": len(circs),
            "gates": sum(len(c.ops) for c in circs)}
     for dt in ("c128", "c64"):
         t0 = time.perf_counter()
-        best, times = BT.autotune(rec, dt, log=log)
+        emp, times = BT.autotune(rec, dt, log=log)
         tune_s = time.perf_counter() - t0
+        best, learned = emp, None
+        if model is not None:
+            t0 = time.perf_counter()
+            shape, pred = BT.learned_shape(rec, dt, model)
+            # the launch for that shape: the fastest workgroup count among the timed candidates of that shape
+            cands = {k: v for k, v in times.items()
+                     if (json.loads(k)["block_bits"], json.loads(k)["low_bits"]) == shape}
+            best = json.loads(min(cands, key=cands.get))
+            learned = {"shape": list(shape), "predicted_ms_top64": {f"{b}/{w}": round(v, 2) for (b, w), v in pred.items()},
+                       "choose_s": round(time.perf_counter() - t0, 1), "empirical_best": emp,
+                       "learned_vs_empirical_ms": [round(cands[json.dumps(best, sort_keys=True)] * 1e3, 3),
+                                                   round(min(times.values()) * 1e3, 3)]}
         b = BT.Batch(rec, dt, **best)
         t_eager = BT.time_batch(b, graph=False, reps=3)
         t_graph = BT.time_batch(b, graph=True, reps=3)
         b.close()
-        out[dt] = {"params": best, "circuits_per_s_graph": len(circs) / t_graph,
+        out[dt] = {"params": best, "learned_plans": learned, "circuits_per_s_graph": len(circs) / t_graph,
                    "circuits_per_s_eager": len(circs) / t_eager, "ms_graph": t_graph * 1e3,
                    "ms_eager": t_eager * 1e3, "autotune_s": round(tune_s, 1),
                    "autotune_ms": {k: round(v * 1e3, 3) for k, v in times.items()}}

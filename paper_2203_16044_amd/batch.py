@@ -101,9 +101,37 @@ def signature(circuits, dtype: str) -> str:
     return hashlib.sha1(key.encode()).hexdigest()
 
 
+SHAPES = sorted({(c["block_bits"], c["low_bits"]) for c in SPACE})
+
+
+def learned_shape(circuits, dtype: str, model, shapes=None, top: int = 64) -> Tuple[Tuple[int, int], Dict]:
+    """The (block bits, low bits) whose plans the cost model predicts fastest for this batch: the sum of the
+    predicted plan times of its `top` largest circuits above 12 qubits (the HBM circuits, which hold almost all of a
+    batch's work; smaller ones run whole in one workgroup's LDS under every candidate shape). Returns (shape,
+    {shape: predicted ms})."""
+    from .plan import Plan
+    recorded = record(circuits)
+    big = sorted((c for c in recorded if c.n > 12), key=lambda c: (c.n, len(c)), reverse=True)[:top]
+    pred = {}
+    for bb, lb in (shapes or SHAPES):
+        tot = 0.0
+        for c in big:
+            p = Plan(c, "block", bb, lb, dtype)
+            tot += model.predict_plan_ms(p)
+            p.close()
+        pred[(bb, lb)] = tot
+    return min(pred, key=pred.get), pred
+
+
 def autotune(circuits, dtype: str = "c128", cache: Optional[str] = CACHE, space: Optional[List[Dict]] = None,
-             log=None) -> Tuple[Dict, Dict[str, float]]:
-    """Time every candidate on the batch and return (best parameters, {candidate: seconds}). Cached by shape."""
+             log=None, model=None) -> Tuple[Dict, Dict[str, float]]:
+    """Time every candidate on the batch and return (best parameters, {candidate: seconds}). Cached by shape. With a
+    cost model, the block shape is the model's choice (learned_shape) and only the launch (workgroups per CU) is
+    timed."""
+    if model is not None:
+        shape, _ = learned_shape(circuits, dtype, model)
+        space = [c for c in (space or SPACE) if (c["block_bits"], c["low_bits"]) == shape]
+        cache = None
     sig = signature(circuits, dtype)
     data = {}
     if cache and os.path.exists(cache):

@@ -139,3 +139,31 @@ def test_autotuner_picks_a_measured_candidate(gpu, tmp_path):
     assert best in space and len(times) == 2
     best2, _ = BT.autotune(circs, "c128", cache=str(tmp_path / "cache.json"), space=space)
     assert best2 == best  # served from the cache
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_learned_batch_shape(gpu, dtype, tmp_path):
+    """The cost model picks the batch's block shape from its plans' predicted times (one prediction per candidate
+    shape, all finite and positive), the autotuner then times only that shape's launches, and the batch planned with
+    the chosen parameters matches the oracle."""
+    import json
+    import os
+
+    from paper_2203_16044_amd import costmodel as CM
+    if not os.path.exists(CM.WEIGHTS):
+        pytest.skip("no trained cost model in the package")
+    model = CM.CostModel.load()
+    circs = C.serving_batch(count=32, seed=91, nmin=10, nmax=16, dmin=4, dmax=12)
+    shape, pred = BT.learned_shape(circs, dtype, model)
+    assert shape in BT.SHAPES and set(pred) == set(BT.SHAPES)
+    assert all(np.isfinite(v) and v > 0 for v in pred.values()) and pred[shape] == min(pred.values())
+    best, times = BT.autotune(circs, dtype, cache=None, model=model)
+    assert (best["block_bits"], best["low_bits"]) == shape
+    assert {(k["block_bits"], k["low_bits"]) for k in map(json.loads, times)} == {shape}
+    b = BT.Batch(circs, dtype, **best)
+    b.run()
+    for i, circ in enumerate(circs):
+        ref = _oracle_probs(circ)
+        err = np.max(np.abs(b.probs(i) - ref))
+        assert err <= (1e-12 if dtype == "c128" else 1e-5), (i, circ.n, err)
+    b.close()
