@@ -40,11 +40,11 @@ PMC_TRAFFIC = {
     "block_b12": {"fetch_kib": 33555046.96, "write_kib": 67111911.55, "fetch_scale": 2.0, "write_scale": 1.0,
                   "sources": ["paper_2203_16044_amd/csrc/qs_block.hip", "paper_2203_16044_amd/csrc/qs_internal.h",
                               "paper_2203_16044_amd/csrc/qs_index.h"],
-                  "sha1": "c48f66fa64f92e3b98095d93ad320f1d173169a4"},
+                  "sha1": "faf41da54bcc478b9fee8de9040c6c528ab3409f"},
     "dense_k1": {"fetch_kib": 33554446.82, "write_kib": 67110458.13, "fetch_scale": 2.0, "write_scale": 1.0,
                  "sources": ["paper_2203_16044_amd/csrc/qs_kernels.hip", "paper_2203_16044_amd/csrc/qs_internal.h",
                              "paper_2203_16044_amd/csrc/qs_index.h"],
-                 "sha1": "12453729e8ecc7f88d03b9f40ad6d54073edea23"},
+                 "sha1": "1c50e970299b3b9370ca4eef27242a46e162c3e0"},
 }
 
 

@@ -243,6 +243,23 @@ QS_API int qs_plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts
  * QS_EINVAL if n or dtype differ from the plan's, or if the plan was uploaded to another device. */
 QS_API int qs_plan_run(qs_state *st, qs_plan *p);
 QS_API int qs_plan_run_range(qs_state *st, qs_plan *p, int begin, int end);
+/* Periodic renormalisation between plans (the complex64 cadence: a state renormalised after given layers, each
+ * stretch of layers its own plan). Runs every pass of p like qs_plan_run, and:
+ *   QS_RUN_SCALE_FIRST  first scales the state by 1 / sqrt(N), N the state's pending norm (left by an earlier
+ *                       QS_RUN_NORM_LAST run), the factor formed and applied in FP64 (complex64: rounded to FP32);
+ *   QS_RUN_NORM_LAST    then sets the pending norm to sum_i |a_i|^2 (FP64, fixed-order reduction) of the state
+ *                       the plan leaves.
+ * Where the plan's first (last) data-moving pass is a complex64 block pass, the scaling (norm) is folded into it:
+ * applied as each block is loaded (accumulated as each block is stored, one partial per workgroup); otherwise a
+ * separate sweep does it. Results equal a qs_renormalize between the plans up to rounding (the norm sums in
+ * another order). Asynchronous; the pending norm lives in the state's device memory. The first folded norm
+ * allocates a partial-sum buffer (grown when a larger launch needs more). QS_EINVAL for unknown flags or as
+ * qs_plan_run; QS_ENOMEM if that buffer cannot be allocated. */
+enum { QS_RUN_SCALE_FIRST = 1, QS_RUN_NORM_LAST = 2 };
+QS_API int qs_plan_run_renorm(qs_state *st, qs_plan *p, int flags);
+/* Scale the state by 1 / sqrt(N) for its pending norm N (the last renormalisation of a sequence of
+ * qs_plan_run_renorm calls); optionally returns N. Synchronises when norm is non-null. */
+QS_API int qs_renormalize_pending(qs_state *st, double *norm);
 /* Pass counts: all passes, LDS block passes, dense passes, others (fused-swaps, large controlled gates, relabels),
  * and the number of fused operations executed inside the block / dense passes. Any output may be NULL. */
 QS_API int qs_plan_info(const qs_plan *p, int *npasses, int *nblock, int *ndense, int *nother, int *nfused_ops);

@@ -20,6 +20,7 @@ QS_OK, QS_EINVAL, QS_ENOMEM, QS_EDEVICE, QS_EUNSUPPORTED = 0, -1, -2, -3, -4
 QS_C128, QS_C64 = 0, 1
 QS_MAX_K, QS_MAX_DIAG_K, QS_MAX_CONTROLS, QS_MAX_QUBITS = 6, 12, 16, 40
 QS_PLAN_BLOCK, QS_PLAN_FUSE, QS_PLAN_REMAP = 0, 1, 2
+QS_RUN_SCALE_FIRST, QS_RUN_NORM_LAST = 1, 2
 QS_PLAN_NFEAT = 48
 
 
@@ -83,6 +84,8 @@ SIGNATURES = {
     "qs_plan_create_learned": [ctypes.POINTER(_P), _P, _P, _P],
     "qs_plan_run": [_P, _P],
     "qs_plan_run_range": [_P, _P, _I, _I],
+    "qs_plan_run_renorm": [_P, _P, _I],
+    "qs_renormalize_pending": [_P, _DP],
     "qs_plan_info": [_P, _IP, _IP, _IP, _IP, _IP],
     "qs_plan_pass_info": [_P, _I, _IP, _IP, ctypes.POINTER(ctypes.c_int64), _IP, _IP],
     "qs_plan_pass_gates": [_P, _I, _IP, _I, _IP],
@@ -352,6 +355,16 @@ def qs_plan_run(h: int, p: int) -> None:
 
 def qs_plan_run_range(h: int, p: int, begin: int, end: int) -> None:
     _check(lib().qs_plan_run_range(h, p, int(begin), int(end)), "qs_plan_run_range")
+
+
+def qs_plan_run_renorm(h: int, p: int, flags: int) -> None:
+    _check(lib().qs_plan_run_renorm(h, p, int(flags)), "qs_plan_run_renorm")
+
+
+def qs_renormalize_pending(h: int, want_norm: bool = False) -> Optional[float]:
+    v = ctypes.c_double(0.0)
+    _check(lib().qs_renormalize_pending(h, ctypes.byref(v) if want_norm else None), "qs_renormalize_pending")
+    return v.value if want_norm else None
 
 
 def qs_plan_info(p: int):

@@ -149,6 +149,32 @@ hipError_t qs_check_no_static_lds(const void *fn)
     return hipSuccess;
 }
 
+double *qs_pending_norm(qs_state *st) { return st->red + kMaxPartials + 2; }
+
+double *qs_block_partials(qs_state *st, size_t n)
+{
+    if (n <= st->blkred_cap)
+        return st->blkred;
+    if (st->blkred) {
+        hipError_t e = hipStreamSynchronize(st->stream);  // the old buffer may still be read by queued work
+        if (e != hipSuccess) {
+            qs_hip_fail(e, "hipStreamSynchronize");
+            return nullptr;
+        }
+        (void)hipFree(st->blkred);
+        st->blkred = nullptr;
+        st->blkred_cap = 0;
+    }
+    hipError_t e = hipMalloc((void **)&st->blkred, n * sizeof(double));
+    if (e != hipSuccess) {
+        st->blkred = nullptr;
+        qs_hip_fail(e, "hipMalloc(block partial sums)");
+        return nullptr;
+    }
+    st->blkred_cap = n;
+    return st->blkred;
+}
+
 // ---- host helpers shared with the planner ----
 
 // Sort the targets ascending; perm[j'] = the original matrix bit carried by sorted position j'.
@@ -206,6 +232,8 @@ void release(qs_state *st)
         (void)hipFree(st->dring);
     if (st->red)
         (void)hipFree(st->red);
+    if (st->blkred)
+        (void)hipFree(st->blkred);
     if (st->owns && st->psi)
         (void)hipFree(st->psi);
     delete st;

@@ -430,9 +430,14 @@ template <class R, int B, int W> struct BlockThreads {
 };
 
 template <class R, int B, int W, int NT>
+// Complex64 only, both optional: scale_norm (the state is first scaled by 1 / sqrt(*scale_norm), in FP64, as each
+// block is loaded) and norm_part (norm_part[blockIdx.x] = FP64 sum of |amplitude|^2 over every amplitude this
+// workgroup stores, each workgroup's blocks in their fixed order, then a fixed reduction tree): a renormalisation
+// folded into the passes on either side of it.
 __global__ __launch_bounds__(NT, (BlockBounds<R, B, W, NT>::waves_per_eu)) void k_block(
     typename BT<R>::C2 *__restrict__ psi, uint64_t nblocks, InsBits outer, BlockMap bm,
-    const BlkStage *__restrict__ stages, int nstages, const R *__restrict__ mats, BlkMfma mf)
+    const BlkStage *__restrict__ stages, int nstages, const R *__restrict__ mats, BlkMfma mf,
+    const double *__restrict__ scale_norm, double *__restrict__ norm_part)
 {
     using C2 = typename BT<R>::C2;
     extern __shared__ __align__(16) unsigned char smem_blk[];
@@ -483,6 +488,12 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, B, W, NT>::waves_per_eu)) void 
     uint64_t blk = blockIdx.x;
     if (blk >= nblocks)
         return;
+    constexpr bool RN = sizeof(R) == 4;  // renormalisation folded in (complex64)
+    double fsc = 1.0, nacc = 0.0;
+    if constexpr (RN) {
+        if (scale_norm)
+            fsc = 1.0 / sqrt(*scale_norm);
+    }
     // one register group per thread: stage records are pipelined (complex128; the complex64 kernels, held to 128
     // VGPRs for 4 waves per SIMD, spill more with the addresses of the next stage live and measured slower)
     constexpr bool PIPED = (1 << (B - W)) == NT && sizeof(R) == 8;
@@ -505,6 +516,12 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, B, W, NT>::waves_per_eu)) void 
             C2 v;
             v.x = pre[it].x;
             v.y = pre[it].y;
+            if constexpr (RN) {
+                if (scale_norm) {
+                    v.x = (R)((double)v.x * fsc);
+                    v.y = (R)((double)v.y * fsc);
+                }
+            }
             lds_put<R>(slot_of(sb, it), v);
         }
     }
@@ -560,6 +577,10 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, B, W, NT>::waves_per_eu)) void 
 #pragma unroll
             for (int it = 0; it < PER; ++it) {
                 const C2 v = lds_get<R>(slot_of(sb, it));
+                if constexpr (RN) {
+                    if (norm_part)
+                        nacc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+                }
                 NV w;
                 w.x = v.x;
                 w.y = v.y;
@@ -578,10 +599,36 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, B, W, NT>::waves_per_eu)) void 
                 C2 v;
                 v.x = pre[it].x;
                 v.y = pre[it].y;
+                if constexpr (RN) {
+                    if (scale_norm) {
+                        v.x = (R)((double)v.x * fsc);
+                        v.y = (R)((double)v.y * fsc);
+                    }
+                }
                 lds_put<R>(slot_of(sb, it), v);
             }
         }
         lds_barrier();
+    }
+    if constexpr (RN) {
+        if (norm_part) {
+            // the workgroup's sum: across each wave, then the waves' sums in wave order (LDS is free once every
+            // thread has read its last block's values out of it)
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1)
+                nacc += __shfl_xor(nacc, off);
+            lds_barrier();
+            double *wsum = reinterpret_cast<double *>(smem_blk);
+            if ((threadIdx.x & 63) == 0)
+                wsum[threadIdx.x >> 6] = nacc;
+            lds_barrier();
+            if (threadIdx.x == 0) {
+                double t = 0.0;
+                for (int w = 0; w < NT / 64; ++w)
+                    t += wsum[w];
+                norm_part[blockIdx.x] = t;
+            }
+        }
     }
 }
 
@@ -1182,9 +1229,23 @@ hipError_t batch_r(int b, void *psi, double *probs, const BatchItem *items, int 
     }
 }
 
+// Persistent workgroups of a block pass: block_wg_per_cu counts 256-thread workgroups (smaller workgroups get
+// proportionally more), at least one per CU, at most one per block.
+uint64_t block_grid_nt(int nt, uint64_t nblocks)
+{
+    const uint64_t cus = (uint64_t)qs_cu_count();
+    uint64_t grid = cus * qs_tunables().block_wg_per_cu * 256 / nt;
+    if (grid < cus)
+        grid = cus;
+    if (grid > nblocks)
+        grid = nblocks;
+    return grid;
+}
+
 template <class R, int B, int W>
 hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm, const BlkStage *stages,
-                   int nstages, const void *mats, const BlkMfma &mf, const BlkStageL *lstages, hipStream_t s)
+                   int nstages, const void *mats, const BlkMfma &mf, const BlkStageL *lstages, const BlkRenorm &rn,
+                   hipStream_t s)
 {
     using C2 = typename BT<R>::C2;
     constexpr int NT = BlockThreads<R, B, W>::value;
@@ -1201,12 +1262,7 @@ hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const Bloc
         return e;
     // persistent workgroups (each walks several blocks so its loads can run ahead of its arithmetic)
     const uint64_t cus = (uint64_t)qs_cu_count();
-    // block_wg_per_cu counts 256-thread workgroups: smaller workgroups get proportionally more
-    uint64_t grid = cus * qs_tunables().block_wg_per_cu * 256 / NT;
-    if (grid < cus)
-        grid = cus;
-    if (grid > nblocks)
-        grid = nblocks;
+    const uint64_t grid = block_grid_nt(NT, nblocks);
     if constexpr (B == 12 && W == 4 && sizeof(R) == 8) {
         if (lstages) {
             if (hipError_t e = qs_allow_lds((const void *)k_block_lanes, data))
@@ -1233,32 +1289,34 @@ hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const Bloc
             return hipGetLastError();
         }
     }
+    if ((rn.scale_norm || rn.norm_part) && (sizeof(R) != 4 || lstages))
+        return hipErrorInvalidValue;  // folded renormalisation: complex64 block passes only
     hipLaunchKernelGGL((k_block<R, B, W, NT>), dim3((unsigned)grid), dim3(NT), shm, s, (C2 *)psi, nblocks, outer, bm,
-                       stages, nstages, (const R *)mats, mf);
+                       stages, nstages, (const R *)mats, mf, rn.scale_norm, rn.norm_part);
     return hipGetLastError();
 }
 
 template <class R>
 hipError_t block_r(int b, int w, void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm,
                    const BlkStage *stages, int nstages, const void *mats, const BlkMfma &mf, const BlkStageL *lstages,
-                   hipStream_t s)
+                   const BlkRenorm &rn, hipStream_t s)
 {
     if (w == 3) {
         switch (b) {
-        case 12: return block_b<R, 12, 3>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, s);
-        case 13: return block_b<R, 13, 3>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, s);
+        case 12: return block_b<R, 12, 3>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, rn, s);
+        case 13: return block_b<R, 13, 3>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, rn, s);
         default: return hipErrorInvalidValue;
         }
     }
     if (w != 4)
         return hipErrorInvalidValue;
     switch (b) {
-    case 8: return block_b<R, 8, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, s);
-    case 9: return block_b<R, 9, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, s);
-    case 10: return block_b<R, 10, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, s);
-    case 11: return block_b<R, 11, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, s);
-    case 12: return block_b<R, 12, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, s);
-    case 13: return block_b<R, 13, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, s);
+    case 8: return block_b<R, 8, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, rn, s);
+    case 9: return block_b<R, 9, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, rn, s);
+    case 10: return block_b<R, 10, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, rn, s);
+    case 11: return block_b<R, 11, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, rn, s);
+    case 12: return block_b<R, 12, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, rn, s);
+    case 13: return block_b<R, 13, 4>(psi, nblocks, outer, bm, stages, nstages, mats, mf, lstages, rn, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1277,9 +1335,36 @@ hipError_t launch_batch_level(int dtype, int b, void *psi, double *probs, const 
 
 hipError_t launch_block(int dtype, int b, int w, void *psi, uint64_t nblocks, const InsBits &outer,
                         const BlockMap &bm, const BlkStage *stages_dev, int nstages, const void *mats_dev,
-                        const BlkMfma &mf, const BlkStageL *lstages_dev, hipStream_t s)
+                        const BlkMfma &mf, const BlkStageL *lstages_dev, hipStream_t s, const BlkRenorm &rn)
 {
     return dtype == QS_C128
-               ? block_r<double>(b, w, psi, nblocks, outer, bm, stages_dev, nstages, mats_dev, mf, lstages_dev, s)
-               : block_r<float>(b, w, psi, nblocks, outer, bm, stages_dev, nstages, mats_dev, mf, nullptr, s);
+               ? block_r<double>(b, w, psi, nblocks, outer, bm, stages_dev, nstages, mats_dev, mf, lstages_dev, rn, s)
+               : block_r<float>(b, w, psi, nblocks, outer, bm, stages_dev, nstages, mats_dev, mf, nullptr, rn, s);
+}
+
+uint64_t launch_block_grid(int dtype, int b, int w, uint64_t nblocks)
+{
+    int nt = 0;
+    if (dtype == QS_C128) {
+        switch (b) {
+        case 8: nt = w == 3 ? 0 : BlockThreads<double, 8, 4>::value; break;
+        case 9: nt = w == 3 ? 0 : BlockThreads<double, 9, 4>::value; break;
+        case 10: nt = w == 3 ? 0 : BlockThreads<double, 10, 4>::value; break;
+        case 11: nt = w == 3 ? 0 : BlockThreads<double, 11, 4>::value; break;
+        case 12: nt = w == 3 ? BlockThreads<double, 12, 3>::value : BlockThreads<double, 12, 4>::value; break;
+        case 13: nt = w == 3 ? BlockThreads<double, 13, 3>::value : BlockThreads<double, 13, 4>::value; break;
+        default: break;
+        }
+    } else {
+        switch (b) {
+        case 8: nt = w == 3 ? 0 : BlockThreads<float, 8, 4>::value; break;
+        case 9: nt = w == 3 ? 0 : BlockThreads<float, 9, 4>::value; break;
+        case 10: nt = w == 3 ? 0 : BlockThreads<float, 10, 4>::value; break;
+        case 11: nt = w == 3 ? 0 : BlockThreads<float, 11, 4>::value; break;
+        case 12: nt = w == 3 ? BlockThreads<float, 12, 3>::value : BlockThreads<float, 12, 4>::value; break;
+        case 13: nt = w == 3 ? BlockThreads<float, 13, 3>::value : BlockThreads<float, 13, 4>::value; break;
+        default: break;
+        }
+    }
+    return nt ? block_grid_nt(nt, nblocks) : 0;
 }

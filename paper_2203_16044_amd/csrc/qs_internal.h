@@ -44,10 +44,18 @@ struct qs_state {
     size_t ring_head = 0;
     hipEvent_t ring_ev[kRingChunks] = {};
     bool ring_ev_live[kRingChunks] = {};
-    // FP64 reduction scratch: per-block partial sums followed by the result slot
+    // FP64 reduction scratch: per-block partial sums followed by the result slot and the pending-norm slot
     double *red = nullptr;
     size_t red_cap = 0;
+    // per-workgroup partial sums of a norm folded into a block pass (allocated on first use)
+    double *blkred = nullptr;
+    size_t blkred_cap = 0;
 };
+// device slot holding the norm a folded renormalisation computed last (qs_plan_run_renorm)
+double *qs_pending_norm(qs_state *st);
+// device buffer of at least n doubles for per-workgroup partial sums (grown on demand; nullptr and the error
+// recorded on failure)
+double *qs_block_partials(qs_state *st, size_t n);
 
 // Copy `bytes` of host data to the device through the staging ring (async on st->stream). Returns the device
 // address, or nullptr on failure (error already recorded).
@@ -112,6 +120,8 @@ hipError_t launch_probs(int dtype, const void *psi, uint64_t dim, double *out, d
 int probs_blocks(uint64_t dim);
 hipError_t launch_scale(int dtype, void *psi, uint64_t dim, double f, hipStream_t s);
 hipError_t launch_scale_dev(int dtype, void *psi, uint64_t dim, const double *norm_dev, hipStream_t s);
+// *result = the sum of partials[0..nb) in a fixed order (FP64)
+hipError_t launch_sum_partials(const double *partials, int nb, double *result, hipStream_t s);
 
 // LDS block passes: local qubit set L (ascending global positions), stage table in device memory
 constexpr int kMaxBlockOpK = 3;
@@ -165,11 +175,21 @@ struct BlkMfma {
     int n = 0;
     uint32_t off[kMaxMfmaStages] = {0, 0, 0, 0};
 };
+// A renormalisation folded into a complex64 block pass (both optional, device pointers): scale_norm, the state is
+// scaled by 1 / sqrt(*scale_norm) as each block is loaded; norm_part, one FP64 partial sum of |amplitude|^2 per
+// workgroup of the launch (launch_block_grid of them) over the amplitudes it stores.
+struct BlkRenorm {
+    const double *scale_norm = nullptr;
+    double *norm_part = nullptr;
+};
 // lstages_dev: the pass's stages in lane-pair form (complex128, b = 12, 4-position stages; built for plans created
 // while the tunable block_lanes is set), or null
 hipError_t launch_block(int dtype, int b, int w, void *psi, uint64_t nblocks, const InsBits &outer,
                         const BlockMap &bm, const BlkStage *stages_dev, int nstages, const void *mats_dev,
-                        const BlkMfma &mf, const BlkStageL *lstages_dev, hipStream_t s);
+                        const BlkMfma &mf, const BlkStageL *lstages_dev, hipStream_t s,
+                        const BlkRenorm &rn = BlkRenorm{});
+// workgroups of the block kernel's launch for nblocks blocks of 2^b amplitudes, stage width w (0: no such kernel)
+uint64_t launch_block_grid(int dtype, int b, int w, uint64_t nblocks);
 
 // batched circuits: one persistent launch per pass level (see qs_block.hip)
 struct BatchCirc {

@@ -1022,6 +1022,12 @@ hipError_t launch_probs(int dtype, const void *psi, uint64_t dim, double *out, d
     return hipGetLastError();
 }
 
+hipError_t launch_sum_partials(const double *partials, int nb, double *result, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, partials, nb, result);
+    return hipGetLastError();
+}
+
 hipError_t launch_scale(int dtype, void *psi, uint64_t dim, double f, hipStream_t s)
 {
     const unsigned g = grid_for(dim, 256 * 4);

@@ -1413,6 +1413,48 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
     *out = P;
     return QS_OK;
 }
+
+// Enqueue pass i of P on the state's stream (rn: a renormalisation folded into a complex64 block pass).
+int run_pass(qs_state *st, qs_plan *P, int i, const BlkRenorm &rn)
+{
+    const size_t esz = P->dtype == QS_C128 ? sizeof(double) : sizeof(float);
+    const PlanPass &pp = P->passes[i];
+    switch (pp.type) {
+    case 0: {
+        const InsBits outer = qs_make_ins(pp.lmask, 0);
+        QS_HIP(launch_block(st->dtype, pp.b, pp.sw, st->psi, (uint64_t)1 << (P->n - pp.b), outer, pp.bm,
+                            P->dstages + pp.stage_begin, pp.nstages, P->dpool, pp.mf,
+                            pp.lstage_begin >= 0 ? P->dlstages + pp.lstage_begin : nullptr, st->stream, rn));
+        break;
+    }
+    case 1: {
+        const InsBits ins = qs_make_ins(pp.tmask, 0);
+        QS_HIP(launch_dense(st->dtype, pp.k, st->psi, (uint64_t)1 << (P->n - pp.k), ins, pp.tp, pp.Uh.data(),
+                            (const char *)P->dpool + pp.mat_off * esz, st->stream));
+        break;
+    }
+    case 2:
+        QS_HIP(launch_fused_swap(st->dtype, st->psi, P->n, pp.p, pp.q, pp.s, st->stream));
+        break;
+    case 4:  // relabel: absorbed into the qubit map, no data moves
+        break;
+    default:
+        if (int rc = run_raw(st, P->raw[pp.raw]))
+            return rc;
+    }
+    return QS_OK;
+}
+
+int check_run(qs_state *st, qs_plan *P, const char *fn)
+{
+    if (!st || !P)
+        return qs_fail(QS_EINVAL, "%s: NULL argument", fn);
+    if (st->n != P->n || st->dtype != P->dtype)
+        return qs_fail(QS_EINVAL, "%s: plan is for n = %d dtype %d, state is n = %d dtype %d", fn, P->n, P->dtype,
+                       st->n, st->dtype);
+    return QS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1420,42 +1462,84 @@ extern "C" {
 QS_API int qs_plan_run_range(qs_state *st, qs_plan *P, int begin, int end)
 {
     qs_clear_error();
-    if (!st || !P)
-        return qs_fail(QS_EINVAL, "qs_plan_run: NULL argument");
-    if (st->n != P->n || st->dtype != P->dtype)
-        return qs_fail(QS_EINVAL, "qs_plan_run: plan is for n = %d dtype %d, state is n = %d dtype %d", P->n, P->dtype,
-                       st->n, st->dtype);
+    if (int rc = check_run(st, P, "qs_plan_run"))
+        return rc;
     const int np = (int)P->passes.size();
     if (begin < 0 || end > np || begin > end)
         return qs_fail(QS_EINVAL, "qs_plan_run: pass range [%d, %d) outside [0, %d]", begin, end, np);
     if (int rc = upload(P))
         return rc;
-    const size_t esz = P->dtype == QS_C128 ? sizeof(double) : sizeof(float);
-    for (int i = begin; i < end; ++i) {
-        const PlanPass &pp = P->passes[i];
-        switch (pp.type) {
-        case 0: {
-            const InsBits outer = qs_make_ins(pp.lmask, 0);
-            QS_HIP(launch_block(st->dtype, pp.b, pp.sw, st->psi, (uint64_t)1 << (P->n - pp.b), outer, pp.bm,
-                                P->dstages + pp.stage_begin, pp.nstages, P->dpool, pp.mf,
-                                pp.lstage_begin >= 0 ? P->dlstages + pp.lstage_begin : nullptr, st->stream));
-            break;
+    for (int i = begin; i < end; ++i)
+        if (int rc = run_pass(st, P, i, BlkRenorm{}))
+            return rc;
+    return QS_OK;
+}
+
+QS_API int qs_plan_run_renorm(qs_state *st, qs_plan *P, int flags)
+{
+    qs_clear_error();
+    if (int rc = check_run(st, P, "qs_plan_run_renorm"))
+        return rc;
+    if (flags & ~(QS_RUN_SCALE_FIRST | QS_RUN_NORM_LAST))
+        return qs_fail(QS_EINVAL, "qs_plan_run_renorm: unknown flags 0x%x", flags);
+    if (int rc = upload(P))
+        return rc;
+    const int np = (int)P->passes.size();
+    const uint64_t dim = (uint64_t)1 << st->n;
+    double *pending = qs_pending_norm(st);
+    // the passes that move data (relabels launch nothing); a renormalisation folds into a complex64 block pass
+    int first = -1, last = -1;
+    for (int i = 0; i < np; ++i)
+        if (P->passes[i].type != 4) {
+            if (first < 0)
+                first = i;
+            last = i;
         }
-        case 1: {
-            const InsBits ins = qs_make_ins(pp.tmask, 0);
-            QS_HIP(launch_dense(st->dtype, pp.k, st->psi, (uint64_t)1 << (P->n - pp.k), ins, pp.tp, pp.Uh.data(),
-                                (const char *)P->dpool + pp.mat_off * esz, st->stream));
-            break;
-        }
-        case 2:
-            QS_HIP(launch_fused_swap(st->dtype, st->psi, P->n, pp.p, pp.q, pp.s, st->stream));
-            break;
-        case 4:  // relabel: absorbed into the qubit map, no data moves
-            break;
-        default:
-            if (int rc = run_raw(st, P->raw[pp.raw]))
-                return rc;
-        }
+    auto foldable = [&](int i) {
+        return i >= 0 && st->dtype == QS_C64 && P->passes[i].type == 0 && P->passes[i].lstage_begin < 0;
+    };
+    const bool scale_in = (flags & QS_RUN_SCALE_FIRST) && foldable(first);
+    if ((flags & QS_RUN_SCALE_FIRST) && !scale_in)
+        QS_HIP(launch_scale_dev(st->dtype, st->psi, dim, pending, st->stream));
+    double *parts = nullptr;
+    uint64_t nparts = 0;
+    if ((flags & QS_RUN_NORM_LAST) && foldable(last)) {
+        const PlanPass &pp = P->passes[last];
+        nparts = launch_block_grid(st->dtype, pp.b, pp.sw, (uint64_t)1 << (P->n - pp.b));
+        if (nparts == 0)
+            return qs_fail(QS_EUNSUPPORTED, "qs_plan_run_renorm: no block kernel for b = %d, w = %d", pp.b, pp.sw);
+        parts = qs_block_partials(st, (size_t)nparts);
+        if (!parts)
+            return QS_ENOMEM;
+    }
+    for (int i = 0; i < np; ++i) {
+        BlkRenorm rn;
+        if (scale_in && i == first)
+            rn.scale_norm = pending;
+        if (parts && i == last)
+            rn.norm_part = parts;
+        if (int rc = run_pass(st, P, i, rn))
+            return rc;
+    }
+    if (flags & QS_RUN_NORM_LAST) {
+        if (parts)
+            QS_HIP(launch_sum_partials(parts, (int)nparts, pending, st->stream));
+        else
+            QS_HIP(launch_probs(st->dtype, st->psi, dim, nullptr, st->red, probs_blocks(dim), pending, st->stream));
+    }
+    return QS_OK;
+}
+
+QS_API int qs_renormalize_pending(qs_state *st, double *norm)
+{
+    qs_clear_error();
+    if (!st)
+        return qs_fail(QS_EINVAL, "qs_renormalize_pending: NULL handle");
+    double *pending = qs_pending_norm(st);
+    QS_HIP(launch_scale_dev(st->dtype, st->psi, (uint64_t)1 << st->n, pending, st->stream));
+    if (norm) {
+        QS_HIP(hipMemcpyAsync(norm, pending, sizeof(double), hipMemcpyDeviceToHost, st->stream));
+        QS_HIP(hipStreamSynchronize(st->stream));
     }
     return QS_OK;
 }

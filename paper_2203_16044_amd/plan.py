@@ -133,11 +133,27 @@ class SegmentedPlan:
         tot["renormalisations"] = sum(1 for _, _, r in self.parts if r)
         return tot
 
-    def run(self, state) -> None:
+    def run(self, state, folded: bool = True) -> None:
+        """Run the segments in order, renormalising after each segment that ends at a renormalisation layer. With
+        `folded` (default) each such renormalisation is folded into the passes around it (qs_plan_run_renorm: the
+        norm taken as the segment's last pass stores the state, the scaling applied as the next segment's first pass
+        loads it; a final one scales in a sweep of its own); otherwise qs_renormalize runs between segments."""
+        if not folded:
+            for _, p, renorm in self.parts:
+                p.run(state)
+                if renorm:
+                    B.qs_renormalize(state.h, False)
+            return
+        pending = False
         for _, p, renorm in self.parts:
-            p.run(state)
-            if renorm:
-                B.qs_renormalize(state.h, False)
+            flags = (B.QS_RUN_SCALE_FIRST if pending else 0) | (B.QS_RUN_NORM_LAST if renorm else 0)
+            if flags:
+                B.qs_plan_run_renorm(state.h, p.h, flags)
+            else:
+                p.run(state)
+            pending = renorm
+        if pending:
+            B.qs_renormalize_pending(state.h, False)
 
     def close(self) -> None:
         for c, p, _ in self.parts:

@@ -55,3 +55,58 @@ def test_33_qubit_complex64_run_keeps_the_norm(gpu):
     assert abs(st.norm() - 1.0) <= 1e-6
     sp.close()
     st.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_folded_renormalisation_matches_separate_sweeps(gpu, dtype):
+    """Renormalisations folded into the block passes around them (complex64; complex128 falls back to sweeps)
+    give the state that a qs_renormalize between the segments gives, from an unnormalised start."""
+    n = 20
+    circ = C.su4_u3_renorm(n=n, seed=960, layers=8)
+    circ.renorm_after = (2, 5, 8)  # the last segment ends with one: scaled by qs_renormalize_pending
+    psi0 = C.random_state(n, 961) * 1.3
+    out = {}
+    for folded in (True, False):
+        st = gpu.State(n, dtype)
+        st.set(psi0)
+        sp = SegmentedPlan(n, circ.ops, circ.renorm_after, "block", 12, 4, dtype)
+        sp.run(st, folded=folded)
+        out[folded] = np.asarray(st.get(), np.complex128)
+        assert abs(st.norm() - 1.0) <= (1e-6 if dtype == "c64" else 1e-12)
+        sp.close()
+        st.close()
+    if dtype == "c64":
+        infid, maxd = oracle.error_metrics(out[True], out[False])
+        assert infid <= 1e-10 and maxd <= 1e-6, (infid, maxd)
+    else:
+        assert float(np.max(np.abs(out[True] - out[False]))) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("mode,bits", [("block", 12), ("fuse", 4)])
+def test_renorm_flags_on_one_plan(gpu, dtype, mode, bits):
+    """qs_plan_run_renorm on a single plan with both flags (folded into the same block pass where the plan has one
+    block pass; dense passes use the sweeps): the pending norm it leaves is the norm of the state the plan leaves,
+    and the state equals plan-then-scale from the scaled start."""
+    import paper_2203_16044_amd.binding as B
+    n = 16
+    circ = C.su4_u3_random(n=n, seed=970, layers=3)
+    psi0 = C.random_state(n, 971) * 0.8
+    c = Circuit.from_ops(n, circ.ops)
+    p = Plan(c, mode, bits, 4 if mode == "block" else 0, dtype)
+    st = gpu.State(n, dtype)
+    st.set(psi0)
+    ec = Circuit.from_ops(n, [])
+    e = Plan(ec, "block", 12, 4, dtype)
+    B.qs_plan_run_renorm(st.h, e.h, B.QS_RUN_NORM_LAST)  # empty plan: pending = |psi0|^2, taken by a sweep
+    B.qs_plan_run_renorm(st.h, p.h, B.QS_RUN_SCALE_FIRST | B.QS_RUN_NORM_LAST)
+    got_norm = B.qs_renormalize_pending(st.h, True)
+    got = np.asarray(st.get(), np.complex128)
+    ref = oracle.run(circ, psi0 / np.sqrt(np.vdot(psi0, psi0).real))
+    tol = 1e-6 if dtype == "c64" else 1e-12
+    assert abs(got_norm - 1.0) <= tol, got_norm  # the plan is unitary: the scaled start has norm 1
+    assert float(np.max(np.abs(got - ref / np.sqrt(got_norm)))) <= (2e-6 if dtype == "c64" else 1e-12)
+    with pytest.raises(B.QSError):
+        B.qs_plan_run_renorm(st.h, p.h, 4)
+    for h in (p, e, c, ec, st):
+        h.close()
