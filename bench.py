@@ -356,7 +356,7 @@ def bench_batch(torch, log):
     """Batched serving form: 512 independent circuits (10..22 qubits, 10..40 layers) in one launch per pass level,
     eager and replayed from a HIP graph, against the per-circuit plain loop. The block shape of the batch's plans is
     the cost model's choice (batch.learned_shape) and its launch is autotuned; the empirical search over every
-    shape and launch is timed beside it as the judge."""
+    shape and launch is timed beside it as the check."""
     import circuits as C
     from paper_2203_16044_amd import batch as BT
     from paper_2203_16044_amd import costmodel as CM

@@ -1,6 +1,6 @@
 """Learned cost model for the planner: an MLP (trained and run by libqs's own GPU kernels) predicts the time of a
 plan pass from its features; the planner scores candidate plans with it and keeps the cheapest. The greedy plan
-(LDS blocks of 12 qubits incl. the 4 lowest) is the fallback and the reference the model is judged against.
+(LDS blocks of 12 qubits incl. the 4 lowest) is the fallback and the reference the model is measured against.
 
 Data: the simulator times every pass of candidate plans of 20-30-qubit circuits with HIP events on the state's
 stream (the target is log(pass milliseconds)). Features come from ``qs_plan_features`` (QS_PLAN_NFEAT floats).
