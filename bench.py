@@ -40,7 +40,7 @@ PMC_TRAFFIC = {
     "block_b12": {"fetch_kib": 33555046.96, "write_kib": 67111911.55, "fetch_scale": 2.0, "write_scale": 1.0,
                   "sources": ["paper_2203_16044_amd/csrc/qs_block.hip", "paper_2203_16044_amd/csrc/qs_internal.h",
                               "paper_2203_16044_amd/csrc/qs_index.h"],
-                  "sha1": "faf41da54bcc478b9fee8de9040c6c528ab3409f"},
+                  "sha1": "70250eeaa247997363b8599b73bcf1889b3d1eae"},
     "dense_k1": {"fetch_kib": 33554446.82, "write_kib": 67110458.13, "fetch_scale": 2.0, "write_scale": 1.0,
                  "sources": ["paper_2203_16044_amd/csrc/qs_kernels.hip", "paper_2203_16044_amd/csrc/qs_internal.h",
                              "paper_2203_16044_amd/csrc/qs_index.h"],

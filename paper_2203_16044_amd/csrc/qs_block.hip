@@ -728,7 +728,7 @@ __device__ __forceinline__ void run_stage_lanes(double2 *s, const BlkStageL &stg
     double2 x[8];
 #pragma unroll
     for (int a = 0; a < 8; ++a)
-        x[a] = lds_at(s, smr ^ stg.rd[a]);
+        x[a] = lds_get<double>(smr ^ stg.rd[a]);
     uint32_t moff = stg.mat_base;
     for (int o = 0; o < stg.nops; ++o) {
         switch ((stg.swaps >> (2 * o)) & 3u) {
@@ -751,7 +751,7 @@ __device__ __forceinline__ void run_stage_lanes(double2 *s, const BlkStageL &stg
     const uint32_t smw = sm ^ (up ? stg.wr_lane : 0u);
 #pragma unroll
     for (int a = 0; a < 8; ++a)
-        lds_at(s, smw ^ stg.wr[a]) = x[a];
+        lds_put<double>(smw ^ stg.wr[a], x[a]);
 }
 
 // The block loop of k_block (next block's loads issued into registers before the current block's stages, rotated
@@ -804,7 +804,7 @@ __global__ __launch_bounds__(512, 4) void k_block_lanes(double2 *__restrict__ ps
             C2 v;
             v.x = pre[it].x;
             v.y = pre[it].y;
-            lds_at(s, blk_phase_slot(sb, it, NT, (uint32_t)sizeof(C2))) = v;
+            lds_put<double>(blk_phase_slot(sb, it, NT, (uint32_t)sizeof(C2)), v);
         }
     }
     lds_barrier();
@@ -831,7 +831,7 @@ __global__ __launch_bounds__(512, 4) void k_block_lanes(double2 *__restrict__ ps
             const uint32_t sb = opaque_s();
 #pragma unroll
             for (int it = 0; it < PER; ++it) {
-                const C2 v = lds_at(s, blk_phase_slot(sb, it, NT, (uint32_t)sizeof(C2)));
+                const C2 v = lds_get<double>(blk_phase_slot(sb, it, NT, (uint32_t)sizeof(C2)));
                 NV w;
                 w.x = v.x;
                 w.y = v.y;
@@ -850,7 +850,7 @@ __global__ __launch_bounds__(512, 4) void k_block_lanes(double2 *__restrict__ ps
                 C2 v;
                 v.x = pre[it].x;
                 v.y = pre[it].y;
-                lds_at(s, blk_phase_slot(sb, it, NT, (uint32_t)sizeof(C2))) = v;
+                lds_put<double>(blk_phase_slot(sb, it, NT, (uint32_t)sizeof(C2)), v);
             }
         }
         lds_barrier();
@@ -1266,6 +1266,8 @@ hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const Bloc
     if constexpr (B == 12 && W == 4 && sizeof(R) == 8) {
         if (lstages) {
             if (hipError_t e = qs_allow_lds((const void *)k_block_lanes, data))
+                return e;
+            if (hipError_t e = qs_check_no_static_lds((const void *)k_block_lanes))  // absolute LDS addressing
                 return e;
             uint64_t g2 = cus * qs_tunables().block_wg_per_cu / 2;  // 512-thread workgroups
             if (g2 < cus)
