@@ -40,11 +40,11 @@ PMC_TRAFFIC = {
     "block_b12": {"fetch_kib": 33555046.96, "write_kib": 67111911.55, "fetch_scale": 2.0, "write_scale": 1.0,
                   "sources": ["paper_2203_16044_amd/csrc/qs_block.hip", "paper_2203_16044_amd/csrc/qs_internal.h",
                               "paper_2203_16044_amd/csrc/qs_index.h"],
-                  "sha1": "70250eeaa247997363b8599b73bcf1889b3d1eae"},
+                  "sha1": "bcea551a4820a7c066e5320f4ccb23a030821394"},
     "dense_k1": {"fetch_kib": 33554446.82, "write_kib": 67110458.13, "fetch_scale": 2.0, "write_scale": 1.0,
                  "sources": ["paper_2203_16044_amd/csrc/qs_kernels.hip", "paper_2203_16044_amd/csrc/qs_internal.h",
                              "paper_2203_16044_amd/csrc/qs_index.h"],
-                 "sha1": "1c50e970299b3b9370ca4eef27242a46e162c3e0"},
+                 "sha1": "efb0a8143d298d41669494079806e581b2822d18"},
 }
 
 
@@ -465,7 +465,7 @@ def main():
             model.close()
         head_v = learned or greedy
         key = lambda v: "learned_per_pass" if v == CM.LEARNED else (  # noqa: E731
-            f"{v[0]}{v[1]}" + (f"_low{v[2]}" if v[0] == "block" else ""))
+            f"{v[0]}{v[1]}" + (f"_low{v[2]}" if v[0] == "block" else "") + (f"_beam{v[3]}" if len(v) > 3 else ""))
         greedy_v = [] if args.no_compare_greedy else [greedy]
         variants = [head_v] + [v for v in greedy_v + [("fuse", k, 0) for k in args.compare_fuse] if v != head_v]
         for vi, v in enumerate(variants):
@@ -473,7 +473,7 @@ def main():
             if vi == 0 and head_plan is not None:
                 plan = head_plan
             else:
-                plan = Plan(cc, *v, "c128")
+                plan = CM.make_plan(cc, v, "c128")
             info = plan.info()
             passes = plan.passes()
             kinds = {0: "block_b{}", 1: "dense_k{}", 2: "fswap", 3: "other"}
@@ -535,7 +535,8 @@ def main():
                                f"(seed 32)", "n": n, "gates": gates, "mode": args.mode,
                    "plan": ("one pass per gate" if args.mode != "tuned" else
                             "learned: every pass chosen by the cost model" if learned == ("learned", 0, 0) else
-                            ("learned: " if learned else "greedy: ") + f"{head_v[0]} b={head_v[1]} low={head_v[2]}"),
+                            ("learned: " if learned else "greedy: ") + f"{head_v[0]} b={head_v[1]} low={head_v[2]}"
+                            + (f" beam={head_v[3]}" if len(head_v) > 3 else "")),
                    "parallelism": "none"},
         "roofline": dict(roof, traffic=pmc_traffic(dom), kernel=dom, avg_launch_ms=avg * 1e3,
                          launches_per_step=cnt // len(step_times), alg_bytes_per_launch=bsum // cnt,

@@ -400,9 +400,15 @@ QS_API int qs_probe_rmw(void *buf, size_t bytes, void *hip_stream);
  * "plan_beam"   beam width of pass formation for plans created afterwards (0..64, default 16): the local set of a
  *               pass grows one ready gate at a time, keeping the candidates that take the most gates; 0 selects
  *               the fewest-new-qubits greedy. Batches always plan with 4-position stages.
+ * "plan_beam_search" 0/1: plans created afterwards with qs_plan_create (not batches) also form their passes at
+ *               1.5x and 4x the beam width (at most 64) and keep the formation with the fewest passes, ties to
+ *               the smaller width (default 0: the learned planner prices candidate plans at several widths
+ *               instead, with the single-width greedy plan as its reference).
  * Process-wide; affects launches enqueued and plans created after the call. QS_EINVAL for an unknown name or
  * value. */
 QS_API int qs_set_tunable(const char *name, int64_t value);
+/* The current value of a tunable named as above. QS_EINVAL for a NULL argument or an unknown name. */
+QS_API int qs_get_tunable(const char *name, int64_t *value);
 
 #ifdef __cplusplus
 }

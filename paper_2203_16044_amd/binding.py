@@ -72,6 +72,7 @@ SIGNATURES = {
     "qs_probe_copy": [_P, _P, ctypes.c_size_t, _P],
     "qs_probe_rmw": [_P, ctypes.c_size_t, _P],
     "qs_set_tunable": [ctypes.c_char_p, ctypes.c_int64],
+    "qs_get_tunable": [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)],
     "qs_circuit_create": [ctypes.POINTER(_P), _I],
     "qs_circuit_free": [_P],
     "qs_circuit_add_gate": [_P, _IP, _I, _DP],
@@ -277,6 +278,12 @@ def qs_probe_rmw(buf: int, nbytes: int, hip_stream: Optional[int] = None) -> Non
 
 def qs_set_tunable(name: str, value: int) -> None:
     _check(lib().qs_set_tunable(name.encode(), int(value)), "qs_set_tunable")
+
+
+def qs_get_tunable(name: str) -> int:
+    v = ctypes.c_int64(0)
+    _check(lib().qs_get_tunable(name.encode(), ctypes.byref(v)), "qs_get_tunable")
+    return int(v.value)
 
 
 # ------------------------------------------------------------------------------------------------ circuits, plans

@@ -251,15 +251,36 @@ def learned_plan(circuit, dtype: str, model: CostModel, shapes=PASS_SHAPES, per_
     return Plan.learned(circuit, model, shapes, per_shape, dtype, gate_slack, lookahead)
 
 
+# pass-formation beam widths besides the planner's default that the whole-plan choice prices for every block-mode
+# candidate (the pass count is not monotone in the width); a candidate key (mode, bits, low, width) names one
+BEAMS = (24, 64)
+
+
+def make_plan(circuit, cand, dtype: str = "c128"):
+    """The plan a candidate key names: (mode, block bits, low bits) at the planner's beam width, or (mode, block
+    bits, low bits, width) at that pass-formation beam width (the process-wide tunable, restored afterwards)."""
+    from .plan import Plan
+    if len(cand) == 3:
+        return Plan(circuit, *cand, dtype)
+    mode, bits, low, width = cand
+    old = B.qs_get_tunable("plan_beam")
+    B.qs_set_tunable("plan_beam", width)
+    try:
+        return Plan(circuit, mode, bits, low, dtype)
+    finally:
+        B.qs_set_tunable("plan_beam", old)
+
+
 def choose_plan(circuit, dtype: str = "c128", model: Optional[CostModel] = None,
                 cands: Optional[Sequence[Tuple[str, int, int]]] = None, margin: float = MARGIN,
-                per_pass: bool = False):
+                per_pass: bool = False, beams: Sequence[int] = BEAMS):
     """The candidate with the lowest predicted time, if it beats the greedy plan's prediction by more than `margin`
     (default MARGIN); otherwise (and without a model) the greedy plan. Candidates: whole plans of one shape each (`cands`, default
-    candidates(n)) and, with per_pass, the plan whose passes the model chooses one by one (LEARNED). Per-pass
+    candidates(n)), every block-mode shape also formed at the pass-formation beam widths `beams`, and, with
+    per_pass, the plan whose passes the model chooses one by one (LEARNED). Per-pass
     choice is off by default: on held-out circuits it measured no faster than the best whole plan, and its
     predictions run low (the model is scored on the very passes it picked as cheapest). Returns
-    (plan, (mode, bits, low), predicted ms)."""
+    (plan, its candidate key (mode, bits, low) or (mode, bits, low, beam width), predicted ms)."""
     from .plan import Plan
     n = circuit.n
     g = greedy_for(n)
@@ -282,6 +303,10 @@ def choose_plan(circuit, dtype: str = "c128", model: Optional[CostModel] = None,
     for cand in (cands or candidates(n)):
         if cand != g:
             offer(Plan(circuit, *cand, dtype), cand)
+        if cand[0] == "block" and beams:
+            for width in beams:
+                if width != B.qs_get_tunable("plan_beam"):
+                    offer(make_plan(circuit, cand + (width,), dtype), cand + (width,))
     if per_pass:
         lp = learned_plan(circuit, dtype, model)
         if lp is not None:

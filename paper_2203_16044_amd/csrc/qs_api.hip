@@ -820,6 +820,27 @@ QS_API int qs_probe_rmw(void *buf, size_t bytes, void *hip_stream)
     return QS_OK;
 }
 
+QS_API int qs_get_tunable(const char *name, int64_t *value)
+{
+    qs_clear_error();
+    if (!name || !value)
+        return qs_fail(QS_EINVAL, "qs_get_tunable: NULL argument");
+    const Tunables &t = qs_tunables();
+    const std::pair<const char *, const std::atomic<int> *> all[] = {
+        {"dense_gpt", &t.dense_gpt},          {"nontemporal", &t.nontemporal},
+        {"mfma_wg_per_cu", &t.mfma_wg_per_cu}, {"block_wg_per_cu", &t.block_wg_per_cu},
+        {"block_stage_width", &t.block_stage_width}, {"plan_beam", &t.plan_beam},
+        {"plan_beam_search", &t.plan_beam_search}, {"block_async", &t.block_async},
+        {"block_lanes", &t.block_lanes},      {"mfma_stage_ops", &t.mfma_stage_ops},
+        {"stage_pack", &t.stage_pack}};
+    for (const auto &kv : all)
+        if (!std::strcmp(name, kv.first)) {
+            *value = kv.second->load();
+            return QS_OK;
+        }
+    return qs_fail(QS_EINVAL, "qs_get_tunable: unknown tunable '%s'", name);
+}
+
 QS_API int qs_set_tunable(const char *name, int64_t value)
 {
     qs_clear_error();
@@ -856,6 +877,10 @@ QS_API int qs_set_tunable(const char *name, int64_t value)
         if (value < 0 || value > 64)
             return qs_fail(QS_EINVAL, "plan_beam must be in [0, 64]");
         t.plan_beam = (int)value;
+    } else if (!std::strcmp(name, "plan_beam_search")) {
+        if (value != 0 && value != 1)
+            return qs_fail(QS_EINVAL, "plan_beam_search must be 0 or 1");
+        t.plan_beam_search = (int)value;
     } else if (!std::strcmp(name, "stage_pack")) {
         if (value != 0 && value != 1)
             return qs_fail(QS_EINVAL, "stage_pack must be 0 or 1");

@@ -248,6 +248,7 @@ struct Tunables {
     std::atomic<int> block_wg_per_cu{32}; // persistent workgroups per CU for the LDS block kernel (256-thread units)
     std::atomic<int> block_stage_width{4}; // register stage width of new block plans: 4, or 3 (512 threads, b = 12, 13)
     std::atomic<int> plan_beam{16};       // pass formation: beam width over local-set growth (0: fewest-new greedy)
+    std::atomic<int> plan_beam_search{0}; // plans (not batches): also 1.5x and 4x that width, fewest passes win
     std::atomic<int> block_async{0};      // 12-qubit block passes: double-buffered LDS with direct-to-LDS loads
     std::atomic<int> block_lanes{0};      // plans created afterwards: complex128 12-qubit lane-pair stages, 512 threads
     std::atomic<int> mfma_stage_ops{3};   // complex64 plans: stages of at least this many ops run fused on MFMA

@@ -685,13 +685,13 @@ QS_API int qs_circuit_run(qs_state *st, const qs_circuit *c)
 
 namespace {
 int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, int stage_width,
-                const qs_plan_model *model);
+                const qs_plan_model *model, bool beam_search = false);
 }
 
 extern "C" QS_API int qs_plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts)
 {
     qs_clear_error();
-    return plan_create(out, c, opts, qs_tunables().block_stage_width, nullptr);
+    return plan_create(out, c, opts, qs_tunables().block_stage_width, nullptr, qs_tunables().plan_beam_search != 0);
 }
 
 extern "C" QS_API int qs_plan_create_learned(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts,
@@ -1345,7 +1345,7 @@ int plan_remap(qs_plan *P, const qs_circuit &c, int b, int stage_width, const st
 }
 
 int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, int stage_width,
-                const qs_plan_model *model)
+                const qs_plan_model *model, bool beam_search)
 {
     if (model && c && c->n < 8)
         return qs_fail(QS_EINVAL, "qs_plan_create_learned: block passes need at least 8 qubits");
@@ -1390,12 +1390,27 @@ int plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts *opts, in
             return rc;
         }
     } else {
-        Former F(*c, b, w, maxq, qs_tunables().plan_beam);
-        std::vector<std::pair<std::vector<int>, std::vector<int>>> fp;
-        std::vector<int> singles;
-        F.run(fp, singles);
-        for (auto &pr : fp)
-            passes.push_back({pr.first, pr.second, b});
+        // pass formation at the tunable beam width and, with beam_search, at 1.5x and 4x that width as well (the
+        // pass count is not monotone in the width): the fewest passes win, ties going to the earlier width
+        const int base = qs_tunables().plan_beam;
+        std::vector<int> widths{base};
+        if (beam_search && base > 0)
+            for (int bw : {base * 3 / 2, std::min(64, base * 4)})
+                if (std::find(widths.begin(), widths.end(), bw) == widths.end())
+                    widths.push_back(bw);
+        bool have = false;
+        for (int bw : widths) {
+            Former F(*c, b, w, maxq, bw);
+            std::vector<std::pair<std::vector<int>, std::vector<int>>> fp;
+            std::vector<int> singles;
+            F.run(fp, singles);
+            if (!have || fp.size() < passes.size()) {
+                passes.clear();
+                for (auto &pr : fp)
+                    passes.push_back({pr.first, pr.second, b});
+                have = true;
+            }
+        }
     }
     if (mode == QS_PLAN_REMAP) {
         if (int rc = plan_remap(P, *c, b, stage_width, passes)) {

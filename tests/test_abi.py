@@ -73,10 +73,23 @@ def test_tunables_validate():
     for name, bad, good in (("block_wg_per_cu", 0, 32), ("block_wg_per_cu", 4097, 32), ("block_stage_width", 5, 4),
                             ("plan_beam", 65, 16), ("plan_beam", -1, 16), ("mfma_stage_ops", 9, 3),
                             ("mfma_stage_ops", -1, 3), ("block_async", 2, 0), ("block_lanes", 2, 0),
-                            ("stage_pack", 2, 1), ("stage_pack", -1, 1)):
+                            ("stage_pack", 2, 1), ("stage_pack", -1, 1), ("plan_beam_search", 2, 0)):
         with pytest.raises(qs.QSError):
             B.qs_set_tunable(name, bad)
         B.qs_set_tunable(name, good)  # the defaults
+
+
+def test_tunables_read_back():
+    """qs_get_tunable returns what qs_set_tunable stored (and the defaults), and rejects unknown names."""
+    assert B.qs_get_tunable("plan_beam") == 16 and B.qs_get_tunable("stage_pack") == 1
+    assert B.qs_get_tunable("plan_beam_search") == 0 and B.qs_get_tunable("block_wg_per_cu") == 32
+    B.qs_set_tunable("plan_beam", 24)
+    try:
+        assert B.qs_get_tunable("plan_beam") == 24
+    finally:
+        B.qs_set_tunable("plan_beam", 16)
+    with pytest.raises(qs.QSError):
+        B.qs_get_tunable("no_such_knob")
 
 
 def test_binding_rejects_matrix_shape_mismatch():

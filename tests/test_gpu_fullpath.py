@@ -27,7 +27,7 @@ TOL128 = 1e-12
 def tunables():
     """Set tunables for one test and restore the library defaults afterwards."""
     defaults = {"block_wg_per_cu": 32, "mfma_wg_per_cu": 2, "block_async": 0, "plan_beam": 16, "mfma_stage_ops": 3,
-                "block_lanes": 0, "stage_pack": 1}
+                "block_lanes": 0, "stage_pack": 1, "plan_beam_search": 0}
     touched = []
 
     def set_(name, value):

@@ -139,7 +139,7 @@ def _plan_for(c, shape):
         p = CM.learned_plan(c, "c128", model)
         model.close()
         return p
-    return Plan(c, *shape)
+    return CM.make_plan(c, shape)
 
 
 @pytest.mark.parametrize("shape", [("block", 12, 3), ("block", 12, 4), ("block", 13, 3), "learned"])
