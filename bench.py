@@ -37,7 +37,7 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector (= FP64 MFMA): 256 CUs x 4 SIMDs x
 # The readings hold for the kernel sources they were taken on: `sha1` fingerprints those files and the traffic is
 # reported as null once they differ.
 PMC_TRAFFIC = {
-    "block_b12": {"fetch_kib": 33555046.96, "write_kib": 67111911.55, "fetch_scale": 2.0, "write_scale": 1.0,
+    "block_b12": {"fetch_kib": 33555491.49, "write_kib": 67110167.04, "fetch_scale": 2.0, "write_scale": 1.0,
                   "sources": ["paper_2203_16044_amd/csrc/qs_block.hip", "paper_2203_16044_amd/csrc/qs_internal.h",
                               "paper_2203_16044_amd/csrc/qs_index.h"],
                   "sha1": "bcea551a4820a7c066e5320f4ccb23a030821394"},
