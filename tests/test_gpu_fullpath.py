@@ -77,6 +77,33 @@ def test_block_pass_many_blocks_per_workgroup(gpu, tunables, n, layers, dtype, l
     _check(np.asarray(got, np.complex128), oracle.run(circ, psi0), dtype)
 
 
+@pytest.mark.parametrize("beam", [24, 64])
+@pytest.mark.parametrize("low", [3, 4])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_block_plans_at_other_beam_widths(gpu, tunables, beam, low, dtype):
+    """Block plans whose passes are formed at the other beam widths the learned planner prices (the benchmark runs
+    12/3 at width 24), with 256 persistent workgroups so each walks 4 blocks per pass, element by element against
+    the oracle."""
+    from paper_2203_16044_amd import costmodel as CM
+    tunables("block_wg_per_cu", 1)
+    n = 22
+    circ = C.su4_u3_random(n=n, seed=940 + low, layers=10)
+    psi0 = C.random_state(n, 941 + low)
+    if dtype == "c64":
+        psi0 = psi0.astype(np.complex64).astype(np.complex128)
+    st = gpu.State(n, dtype)
+    st.set(psi0)
+    c = Circuit.from_ops(n, circ.ops)
+    p = CM.make_plan(c, ("block", 12, low, beam), dtype)
+    assert B.qs_get_tunable("plan_beam") == 16  # restored after the plan was formed
+    assert p.info()["block"] >= 2
+    p.run(st)
+    got = np.asarray(st.get(), np.complex128)
+    for h in (p, c, st):
+        h.close()
+    _check(got, oracle.run(circ, psi0), dtype)
+
+
 @pytest.mark.parametrize("low", [3, 4])
 def test_thirteen_qubit_blocks_many_per_workgroup(gpu, tunables, low):
     """complex128 13-qubit blocks run one 16-amplitude register group per thread (512 threads, a CU per 128 KB
