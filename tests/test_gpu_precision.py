@@ -110,3 +110,41 @@ def test_renorm_flags_on_one_plan(gpu, dtype, mode, bits):
         B.qs_plan_run_renorm(st.h, p.h, 4)
     for h in (p, e, c, ec, st):
         h.close()
+
+
+def test_renorm_flags_on_remapped_plans(gpu):
+    """qs_plan_run_renorm on remapped plans (fused-swap and relabel passes around the block passes: the relabels
+    launch nothing and are skipped when finding the first and last passes; fused-swaps take the sweeps): the state
+    equals the one from qs_plan_run with qs_renormalize around it."""
+    import paper_2203_16044_amd.binding as B
+    n = 18
+    circ = C.su4_u3_random(n=n, seed=980, layers=4)
+    psi0 = C.random_state(n, 981) * 1.2
+    c = Circuit.from_ops(n, circ.ops)
+    p = Plan(c, "remap", 12, 0, "c64")
+    assert p.info()["other"] >= 1  # fused-swaps (and relabels) besides block passes
+    out = []
+    for folded in (True, False):
+        st = gpu.State(n, "c64")
+        st.set(psi0)
+        if folded:
+            ec = Circuit.from_ops(n, [])
+            e = Plan(ec, "block", 12, 4, "c64")
+            B.qs_plan_run_renorm(st.h, e.h, B.QS_RUN_NORM_LAST)
+            B.qs_plan_run_renorm(st.h, p.h, B.QS_RUN_SCALE_FIRST | B.QS_RUN_NORM_LAST)
+            B.qs_renormalize_pending(st.h, False)
+            e.close()
+            ec.close()
+        else:
+            st.renormalize()
+            p.run(st)
+            st.renormalize()
+        out.append(np.asarray(st.get(), np.complex128))
+        st.close()
+    infid, maxd = oracle.error_metrics(out[0], out[1])
+    assert infid <= 1e-10 and maxd <= 1e-6, (infid, maxd)
+    ref = oracle.run(circ, psi0 / np.sqrt(np.vdot(psi0, psi0).real))
+    infid, maxd = oracle.error_metrics(out[0], ref)
+    assert infid <= 1e-8 and maxd <= 1e-6, (infid, maxd)
+    p.close()
+    c.close()
