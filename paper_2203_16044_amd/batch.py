@@ -111,15 +111,20 @@ def learned_shape(circuits, dtype: str, model, shapes=None, top: int = 64) -> Tu
     {shape: predicted ms})."""
     from .plan import Plan
     recorded = record(circuits)
-    big = sorted((c for c in recorded if c.n > 12), key=lambda c: (c.n, len(c)), reverse=True)[:top]
-    pred = {}
-    for bb, lb in (shapes or SHAPES):
-        tot = 0.0
-        for c in big:
-            p = Plan(c, "block", bb, lb, dtype)
-            tot += model.predict_plan_ms(p)
-            p.close()
-        pred[(bb, lb)] = tot
+    try:
+        big = sorted((c for c in recorded if c.n > 12), key=lambda c: (c.n, len(c)), reverse=True)[:top]
+        pred = {}
+        for bb, lb in (shapes or SHAPES):
+            tot = 0.0
+            for c in big:
+                p = Plan(c, "block", bb, lb, dtype)
+                tot += model.predict_plan_ms(p)
+                p.close()
+            pred[(bb, lb)] = tot
+    finally:
+        for c, orig in zip(recorded, circuits):
+            if c is not orig:  # recorded here: release it
+                c.close()
     return min(pred, key=pred.get), pred
 
 
