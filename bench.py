@@ -40,7 +40,7 @@ PMC_TRAFFIC = {
     "block_b12": {"fetch_kib": 33555491.49, "write_kib": 67110167.04, "fetch_scale": 2.0, "write_scale": 1.0,
                   "sources": ["paper_2203_16044_amd/csrc/qs_block.hip", "paper_2203_16044_amd/csrc/qs_internal.h",
                               "paper_2203_16044_amd/csrc/qs_index.h"],
-                  "sha1": "bcea551a4820a7c066e5320f4ccb23a030821394"},
+                  "sha1": "b3ddcbca772e1ce3187d75f0d5ebf2337aa1b5cf"},
     "dense_k1": {"fetch_kib": 33554446.82, "write_kib": 67110458.13, "fetch_scale": 2.0, "write_scale": 1.0,
                  "sources": ["paper_2203_16044_amd/csrc/qs_kernels.hip", "paper_2203_16044_amd/csrc/qs_internal.h",
                              "paper_2203_16044_amd/csrc/qs_index.h"],

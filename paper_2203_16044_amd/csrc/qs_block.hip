@@ -429,11 +429,12 @@ template <class R, int B, int W> struct BlockThreads {
     static constexpr int value = W == 3 ? 512 : (groups < 64 ? 64 : (groups > cap ? cap : groups));
 };
 
-template <class R, int B, int W, int NT>
-// Complex64 only, both optional: scale_norm (the state is first scaled by 1 / sqrt(*scale_norm), in FP64, as each
-// block is loaded) and norm_part (norm_part[blockIdx.x] = FP64 sum of |amplitude|^2 over every amplitude this
-// workgroup stores, each workgroup's blocks in their fixed order, then a fixed reduction tree): a renormalisation
-// folded into the passes on either side of it.
+// RNF (complex64 only; a renormalisation folded into the passes on either side of it), a compile-time choice so
+// that passes without it run the kernel without its registers: bit 1, the state is first scaled by
+// 1 / sqrt(*scale_norm), in FP64, as each block is loaded; bit 2, norm_part[blockIdx.x] = FP64 sum of |amplitude|^2
+// over every amplitude this workgroup stores (each workgroup's blocks in their fixed order, then a fixed reduction
+// tree).
+template <class R, int B, int W, int NT, int RNF = 0>
 __global__ __launch_bounds__(NT, (BlockBounds<R, B, W, NT>::waves_per_eu)) void k_block(
     typename BT<R>::C2 *__restrict__ psi, uint64_t nblocks, InsBits outer, BlockMap bm,
     const BlkStage *__restrict__ stages, int nstages, const R *__restrict__ mats, BlkMfma mf,
@@ -488,12 +489,11 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, B, W, NT>::waves_per_eu)) void 
     uint64_t blk = blockIdx.x;
     if (blk >= nblocks)
         return;
-    constexpr bool RN = sizeof(R) == 4;  // renormalisation folded in (complex64)
+    static_assert(RNF >= 0 && RNF <= 3 && (RNF == 0 || sizeof(R) == 4), "folded renormalisation: complex64 only");
+    constexpr bool SCL = (RNF & 1) != 0, NRM = (RNF & 2) != 0;
     double fsc = 1.0, nacc = 0.0;
-    if constexpr (RN) {
-        if (scale_norm)
-            fsc = 1.0 / sqrt(*scale_norm);
-    }
+    if constexpr (SCL)
+        fsc = 1.0 / sqrt(*scale_norm);
     // one register group per thread: stage records are pipelined (complex128; the complex64 kernels, held to 128
     // VGPRs for 4 waves per SIMD, spill more with the addresses of the next stage live and measured slower)
     constexpr bool PIPED = (1 << (B - W)) == NT && sizeof(R) == 8;
@@ -516,11 +516,9 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, B, W, NT>::waves_per_eu)) void 
             C2 v;
             v.x = pre[it].x;
             v.y = pre[it].y;
-            if constexpr (RN) {
-                if (scale_norm) {
-                    v.x = (R)((double)v.x * fsc);
-                    v.y = (R)((double)v.y * fsc);
-                }
+            if constexpr (SCL) {
+                v.x = (R)((double)v.x * fsc);
+                v.y = (R)((double)v.y * fsc);
             }
             lds_put<R>(slot_of(sb, it), v);
         }
@@ -577,10 +575,8 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, B, W, NT>::waves_per_eu)) void 
 #pragma unroll
             for (int it = 0; it < PER; ++it) {
                 const C2 v = lds_get<R>(slot_of(sb, it));
-                if constexpr (RN) {
-                    if (norm_part)
-                        nacc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
-                }
+                if constexpr (NRM)
+                    nacc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
                 NV w;
                 w.x = v.x;
                 w.y = v.y;
@@ -599,35 +595,31 @@ __global__ __launch_bounds__(NT, (BlockBounds<R, B, W, NT>::waves_per_eu)) void 
                 C2 v;
                 v.x = pre[it].x;
                 v.y = pre[it].y;
-                if constexpr (RN) {
-                    if (scale_norm) {
-                        v.x = (R)((double)v.x * fsc);
-                        v.y = (R)((double)v.y * fsc);
-                    }
+                if constexpr (SCL) {
+                    v.x = (R)((double)v.x * fsc);
+                    v.y = (R)((double)v.y * fsc);
                 }
                 lds_put<R>(slot_of(sb, it), v);
             }
         }
         lds_barrier();
     }
-    if constexpr (RN) {
-        if (norm_part) {
-            // the workgroup's sum: across each wave, then the waves' sums in wave order (LDS is free once every
-            // thread has read its last block's values out of it)
+    if constexpr (NRM) {
+        // the workgroup's sum: across each wave, then the waves' sums in wave order (LDS is free once every thread
+        // has read its last block's values out of it)
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1)
-                nacc += __shfl_xor(nacc, off);
-            lds_barrier();
-            double *wsum = reinterpret_cast<double *>(smem_blk);
-            if ((threadIdx.x & 63) == 0)
-                wsum[threadIdx.x >> 6] = nacc;
-            lds_barrier();
-            if (threadIdx.x == 0) {
-                double t = 0.0;
-                for (int w = 0; w < NT / 64; ++w)
-                    t += wsum[w];
-                norm_part[blockIdx.x] = t;
-            }
+        for (int off = 32; off > 0; off >>= 1)
+            nacc += __shfl_xor(nacc, off);
+        lds_barrier();
+        double *wsum = reinterpret_cast<double *>(smem_blk);
+        if ((threadIdx.x & 63) == 0)
+            wsum[threadIdx.x >> 6] = nacc;
+        lds_barrier();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int w = 0; w < NT / 64; ++w)
+                t += wsum[w];
+            norm_part[blockIdx.x] = t;
         }
     }
 }
@@ -1242,6 +1234,23 @@ uint64_t block_grid_nt(int nt, uint64_t nblocks)
     return grid;
 }
 
+// One k_block variant: its LDS allowance, the absolute-addressing check, the launch.
+template <class R, int B, int W, int NT, int RNF>
+hipError_t launch_k_block(uint64_t grid, size_t shm, size_t shm_max, void *psi, uint64_t nblocks,
+                          const InsBits &outer, const BlockMap &bm, const BlkStage *stages, int nstages,
+                          const void *mats, const BlkMfma &mf, const BlkRenorm &rn, hipStream_t s)
+{
+    using C2 = typename BT<R>::C2;
+    if (hipError_t e = qs_allow_lds((const void *)k_block<R, B, W, NT, RNF>, shm_max))
+        return e;
+    // the kernel addresses its LDS absolutely (lds_get / lds_put)
+    if (hipError_t e = qs_check_no_static_lds((const void *)k_block<R, B, W, NT, RNF>))
+        return e;
+    hipLaunchKernelGGL((k_block<R, B, W, NT, RNF>), dim3((unsigned)grid), dim3(NT), shm, s, (C2 *)psi, nblocks, outer,
+                       bm, stages, nstages, (const R *)mats, mf, rn.scale_norm, rn.norm_part);
+    return hipGetLastError();
+}
+
 template <class R, int B, int W>
 hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const BlockMap &bm, const BlkStage *stages,
                    int nstages, const void *mats, const BlkMfma &mf, const BlkStageL *lstages, const BlkRenorm &rn,
@@ -1252,14 +1261,12 @@ hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const Bloc
     static_assert((1 << B) >= NT, "block smaller than the workgroup");
     if (mf.n < 0 || mf.n > kMaxMfmaStages || (mf.n > 0 && (sizeof(R) != 4 || W != 4)))
         return hipErrorInvalidValue;
+    const int rnf = (rn.scale_norm ? 1 : 0) | (rn.norm_part ? 2 : 0);
+    if (rnf && sizeof(R) != 4)
+        return hipErrorInvalidValue;  // folded renormalisation: complex64 block passes only
     const size_t data = sizeof(C2) << B;
     const size_t shm = data + 256 * sizeof(C2) * mf.n;
     const size_t shm_max = data + (sizeof(R) == 4 && W == 4 ? 256 * sizeof(C2) * kMaxMfmaStages : 0);
-    if (hipError_t e = qs_allow_lds((const void *)k_block<R, B, W, NT>, shm_max))
-        return e;
-    // the kernel addresses its LDS absolutely (lds_get / lds_put)
-    if (hipError_t e = qs_check_no_static_lds((const void *)k_block<R, B, W, NT>))
-        return e;
     // persistent workgroups (each walks several blocks so its loads can run ahead of its arithmetic)
     const uint64_t cus = (uint64_t)qs_cu_count();
     const uint64_t grid = block_grid_nt(NT, nblocks);
@@ -1291,11 +1298,19 @@ hipError_t block_b(void *psi, uint64_t nblocks, const InsBits &outer, const Bloc
             return hipGetLastError();
         }
     }
-    if ((rn.scale_norm || rn.norm_part) && (sizeof(R) != 4 || lstages))
-        return hipErrorInvalidValue;  // folded renormalisation: complex64 block passes only
-    hipLaunchKernelGGL((k_block<R, B, W, NT>), dim3((unsigned)grid), dim3(NT), shm, s, (C2 *)psi, nblocks, outer, bm,
-                       stages, nstages, (const R *)mats, mf, rn.scale_norm, rn.norm_part);
-    return hipGetLastError();
+    if constexpr (sizeof(R) == 4) {
+        switch (rnf) {
+        case 1: return launch_k_block<R, B, W, NT, 1>(grid, shm, shm_max, psi, nblocks, outer, bm, stages, nstages,
+                                                      mats, mf, rn, s);
+        case 2: return launch_k_block<R, B, W, NT, 2>(grid, shm, shm_max, psi, nblocks, outer, bm, stages, nstages,
+                                                      mats, mf, rn, s);
+        case 3: return launch_k_block<R, B, W, NT, 3>(grid, shm, shm_max, psi, nblocks, outer, bm, stages, nstages,
+                                                      mats, mf, rn, s);
+        default: break;
+        }
+    }
+    return launch_k_block<R, B, W, NT, 0>(grid, shm, shm_max, psi, nblocks, outer, bm, stages, nstages, mats, mf, rn,
+                                          s);
 }
 
 template <class R>
