@@ -15,7 +15,8 @@ Modes: "plain" applies the circuit gate by gate (one HBM pass per gate); "tuned"
 paper_2203_16044_amd.plan) and also reports plain on a prefix of the circuit for the speedup.
 
 Further legs in the same JSON line: "c64" (the 33-qubit complex64 circuit of the same family with FP64
-renormalisation every 10 layers, and the complex64 error at 24 qubits) and "batch" (512 circuits of 10-22 qubits,
+renormalisation every 10 layers folded into the block passes, planned in the block shape the cost model predicts
+fastest, and the complex64 error at 24 qubits) and "batch" (512 circuits of 10-22 qubits,
 one persistent launch per pass level, autotuned, eager and graph-replayed, against the per-circuit plain loop).
 """
 import argparse
@@ -243,9 +244,16 @@ def bench_c64(head_rate, steps, torch):
     from paper_2203_16044_amd.metrics import state_error
     from paper_2203_16044_amd.plan import Circuit, Plan, SegmentedPlan
 
+    from paper_2203_16044_amd import costmodel as CM
+
     circ = C.su4_u3_renorm()
     st = qs.State(circ.n, "c64")
-    sp = SegmentedPlan(circ.n, circ.ops, circ.renorm_after, "block", 12, 4, "c64")
+    # the block shape and beam width whose segments the cost model predicts fastest (greedy 12/4 without weights)
+    model = CM.CostModel.load() if os.path.exists(CM.WEIGHTS) else None
+    sp, key, pred = CM.choose_segmented(circ.n, circ.ops, circ.renorm_after, "c64", model)
+    if model is not None:
+        model.close()
+    plan_s = f"block b={key[1]} low={key[2]} beam={key[3] if len(key) > 3 else qs.binding.qs_get_tunable('plan_beam')}"
     mk = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     st.init_zero()
     sp.run(st)
@@ -282,6 +290,7 @@ def bench_c64(head_rate, steps, torch):
     return {"workload": f"random SU(4)+U3 circuit, n={circ.n}, 40 layers, {len(circ.ops)} gates, complex64, "
                         f"renormalised after layers {list(circ.renorm_after)} (seed 33)",
             "gates_per_s": len(circ.ops) / t, "ms_per_step": t * 1e3, "passes": info["passes"],
+            "plan": plan_s, "plan_choice": "learned" if model is not None else "greedy", "predicted_ms": pred,
             "renormalisations": info["renormalisations"], "norm_after": nrm,
             "gates_per_s_vs_c128_headline": len(circ.ops) / t / head_rate,
             "error_24q": {"infidelity": infid, "max_abs_amp_diff": maxd,

@@ -148,3 +148,41 @@ def test_renorm_flags_on_remapped_plans(gpu):
     assert infid <= 1e-8 and maxd <= 1e-6, (infid, maxd)
     p.close()
     c.close()
+
+
+def test_learned_segmented_plan_against_fp64_oracle(gpu):
+    """The complex64 leg's planner: choose_segmented returns the candidate (block shape, beam width) whose segments
+    the cost model predicts fastest in sum (every candidate re-priced here), without weights the greedy shape; the
+    chosen plan, its renormalisations folded into its block passes, matches the FP64 oracle."""
+    import os
+
+    import paper_2203_16044_amd.binding as B
+    from paper_2203_16044_amd import costmodel as CM
+    if not os.path.exists(CM.WEIGHTS):
+        pytest.skip("no trained cost model in the package")
+    n = 20
+    circ = C.su4_u3_renorm(n=n, seed=980, layers=12)
+    circ.renorm_after = (4, 8, 12)
+    g, gkey, gpred = CM.choose_segmented(n, circ.ops, circ.renorm_after, "c64", None)
+    assert gkey == CM.greedy_for(n) and gpred is None
+    g.close()
+    model = CM.CostModel.load()
+    sp, key, pred = CM.choose_segmented(n, circ.ops, circ.renorm_after, "c64", model)
+    cur = B.qs_get_tunable("plan_beam")
+    preds = {}
+    for cand in [c for c in CM.candidates(n) if c[0] == "block"]:
+        for k in [cand] + [cand + (w,) for w in CM.BEAMS if w != cur]:
+            q = CM.make_segmented(n, circ.ops, circ.renorm_after, k, "c64")
+            preds[k] = sum(model.predict_plan_ms(p) for _, p, _ in q.parts)
+            q.close()
+    assert key in preds and preds[key] == pytest.approx(pred, rel=1e-6), (key, pred, preds)
+    assert pred == pytest.approx(min(preds.values()), rel=1e-6), (key, pred, preds)
+    assert B.qs_get_tunable("plan_beam") == cur
+    st = gpu.State(n, "c64")
+    sp.run(st)
+    infid, maxd = oracle.error_metrics(st.get(), oracle.run(circ))
+    assert infid <= 1e-8 and maxd <= 1e-6, (key, infid, maxd)
+    assert abs(st.norm() - 1.0) <= 1e-6
+    sp.close()
+    st.close()
+    model.close()
