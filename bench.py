@@ -15,8 +15,9 @@ Modes: "plain" applies the circuit gate by gate (one HBM pass per gate); "tuned"
 paper_2203_16044_amd.plan) and also reports plain on a prefix of the circuit for the speedup.
 
 Further legs in the same JSON line: "c64" (the 33-qubit complex64 circuit of the same family with FP64
-renormalisation every 10 layers folded into the block passes, planned in the block shape the cost model predicts
-fastest, and the complex64 error at 24 qubits) and "batch" (512 circuits of 10-22 qubits,
+renormalisation every 10 layers, planned once in the block shape the cost model predicts fastest and renormalised at
+the first pass boundary after each such layer completes, folded into the block passes; the layer-exact segmented
+form beside it; and the complex64 error at 24 qubits) and "batch" (512 circuits of 10-22 qubits,
 one persistent launch per pass level, autotuned, eager and graph-replayed, against the per-circuit plain loop).
 """
 import argparse
@@ -237,23 +238,27 @@ def cpu_baseline(circ, budget_s, torch):
 
 def bench_c64(head_rate, steps, torch):
     """complex64 engine: the 33-qubit circuit of the same family (64 GiB state, as large as the 32-qubit complex128
-    one) through the block plan with FP64 renormalisation after layers 10/20/30/40, and its error on the 24-qubit
-    run against the complex128 path (which matches the FP64 oracle to 1e-12 in the tests)."""
+    one) planned once, with an FP64 renormalisation once each of layers 10/20/30/40 has completed (at the next pass
+    boundary), and its error on the 24-qubit run against the complex128 path (which matches the FP64 oracle to
+    1e-12 in the tests)."""
     import circuits as C
     import paper_2203_16044_amd as qs
     from paper_2203_16044_amd.metrics import state_error
-    from paper_2203_16044_amd.plan import Circuit, Plan, SegmentedPlan
+    from paper_2203_16044_amd.plan import Circuit, LazyRenormPlan, Plan
 
     from paper_2203_16044_amd import costmodel as CM
 
     circ = C.su4_u3_renorm()
     st = qs.State(circ.n, "c64")
-    # the block shape and beam width whose segments the cost model predicts fastest (greedy 12/4 without weights)
+    # one plan over the whole circuit, renormalised at the first pass boundary after each renormalisation layer has
+    # completed, in the block shape and beam width the cost model predicts fastest (greedy 12/4 without weights)
     model = CM.CostModel.load() if os.path.exists(CM.WEIGHTS) else None
-    sp, key, pred = CM.choose_segmented(circ.n, circ.ops, circ.renorm_after, "c64", model)
+    sp, key, pred = CM.choose_segmented(circ.n, circ.ops, circ.renorm_after, "c64", model, lazy=True)
+    plan_s = f"block b={key[1]} low={key[2]} beam={key[3] if len(key) > 3 else qs.binding.qs_get_tunable('plan_beam')}"
+    # the check: the circuit cut after its renormalisation layers, each segment planned alone
+    seg, seg_key, _ = CM.choose_segmented(circ.n, circ.ops, circ.renorm_after, "c64", model, lazy=False)
     if model is not None:
         model.close()
-    plan_s = f"block b={key[1]} low={key[2]} beam={key[3] if len(key) > 3 else qs.binding.qs_get_tunable('plan_beam')}"
     mk = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     st.init_zero()
     sp.run(st)
@@ -270,7 +275,19 @@ def bench_c64(head_rate, steps, torch):
         times.append(e0.elapsed_time(e1) / 1e3)
     nrm = st.norm()
     info = sp.info()
+    bounds = list(sp.bounds)
     sp.close()
+    seg.run(st)  # warm
+    e0, e1 = mk(), mk()
+    e0.record(st.stream)
+    st.init_zero()
+    seg.run(st)
+    qs.binding.qs_probs(st.h, None, False)
+    e1.record(st.stream)
+    e1.synchronize()
+    t_seg = e0.elapsed_time(e1) / 1e3
+    seg_passes = seg.info()["passes"]
+    seg.close()
     st.close()
     del st
     torch.cuda.empty_cache()
@@ -278,7 +295,7 @@ def bench_c64(head_rate, steps, torch):
     # error of the complex64 engine on the 24-qubit run, against the complex128 path
     e = C.su4_u3_error_run()
     a = qs.State(e.n, "c64")
-    sp = SegmentedPlan(e.n, e.ops, e.renorm_after, "block", 12, 4, "c64")
+    sp = LazyRenormPlan(e.n, e.ops, e.renorm_after, "block", 12, 4, "c64")
     sp.run(a)
     b = qs.State(e.n, "c128")
     c = Circuit.from_ops(e.n, e.ops)
@@ -288,9 +305,13 @@ def bench_c64(head_rate, steps, torch):
     for h in (sp, p, c, a, b):
         h.close()
     return {"workload": f"random SU(4)+U3 circuit, n={circ.n}, 40 layers, {len(circ.ops)} gates, complex64, "
-                        f"renormalised after layers {list(circ.renorm_after)} (seed 33)",
+                        f"renormalised once layers {list(circ.renorm_after)} complete (seed 33)",
             "gates_per_s": len(circ.ops) / t, "ms_per_step": t * 1e3, "passes": info["passes"],
             "plan": plan_s, "plan_choice": "learned" if model is not None else "greedy", "predicted_ms": pred,
+            "renormalised_at_passes": bounds,
+            "layer_exact_segments": {"gates_per_s": len(circ.ops) / t_seg, "ms": t_seg * 1e3, "passes": seg_passes,
+                                     "plan": f"block b={seg_key[1]} low={seg_key[2]}"
+                                             + (f" beam={seg_key[3]}" if len(seg_key) > 3 else "")},
             "renormalisations": info["renormalisations"], "norm_after": nrm,
             "gates_per_s_vs_c128_headline": len(circ.ops) / t / head_rate,
             "error_24q": {"infidelity": infid, "max_abs_amp_diff": maxd,

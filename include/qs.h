@@ -257,6 +257,13 @@ QS_API int qs_plan_run_range(qs_state *st, qs_plan *p, int begin, int end);
  * qs_plan_run; QS_ENOMEM if that buffer cannot be allocated. */
 enum { QS_RUN_SCALE_FIRST = 1, QS_RUN_NORM_LAST = 2 };
 QS_API int qs_plan_run_renorm(qs_state *st, qs_plan *p, int flags);
+/* The same over passes [begin, end) of one plan: the scaling folds into the range's first data-moving pass, the
+ * norm into its last. A renormalisation is a scalar factor and commutes with every gate, so one plan over the
+ * whole circuit can renormalise at pass boundaries (placing them is the caller's choice: the first boundary by
+ * which every gate of the layers to be renormalised has run). QS_EINVAL for unknown flags, a range outside
+ * [0, passes] or begin > end, or as qs_plan_run; QS_ENOMEM as qs_plan_run_renorm. An empty range with both
+ * flags scales by the pending norm and then takes the norm of the scaled state, each in a sweep of its own. */
+QS_API int qs_plan_run_range_renorm(qs_state *st, qs_plan *p, int begin, int end, int flags);
 /* Scale the state by 1 / sqrt(N) for its pending norm N (the last renormalisation of a sequence of
  * qs_plan_run_renorm calls); optionally returns N. Synchronises when norm is non-null. */
 QS_API int qs_renormalize_pending(qs_state *st, double *norm);

@@ -86,6 +86,7 @@ SIGNATURES = {
     "qs_plan_run": [_P, _P],
     "qs_plan_run_range": [_P, _P, _I, _I],
     "qs_plan_run_renorm": [_P, _P, _I],
+    "qs_plan_run_range_renorm": [_P, _P, _I, _I, _I],
     "qs_renormalize_pending": [_P, _DP],
     "qs_plan_info": [_P, _IP, _IP, _IP, _IP, _IP],
     "qs_plan_pass_info": [_P, _I, _IP, _IP, ctypes.POINTER(ctypes.c_int64), _IP, _IP],
@@ -366,6 +367,10 @@ def qs_plan_run_range(h: int, p: int, begin: int, end: int) -> None:
 
 def qs_plan_run_renorm(h: int, p: int, flags: int) -> None:
     _check(lib().qs_plan_run_renorm(h, p, int(flags)), "qs_plan_run_renorm")
+
+
+def qs_plan_run_range_renorm(h: int, p: int, begin: int, end: int, flags: int) -> None:
+    _check(lib().qs_plan_run_range_renorm(h, p, int(begin), int(end), int(flags)), "qs_plan_run_range_renorm")
 
 
 def qs_renormalize_pending(h: int, want_norm: bool = False) -> Optional[float]:

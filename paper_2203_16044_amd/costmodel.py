@@ -317,37 +317,41 @@ def choose_plan(circuit, dtype: str = "c128", model: Optional[CostModel] = None,
 
 
 
-def make_segmented(n: int, ops, renorm_after, cand, dtype: str = "c64"):
-    """The segmented plan (the circuit cut after its renormalisation layers, each segment planned alone) of a
-    candidate key: (mode, block bits, low bits) at the planner's beam width, or with a fourth entry, that beam
-    width (the process-wide tunable, restored afterwards)."""
-    from .plan import SegmentedPlan
+def make_segmented(n: int, ops, renorm_after, cand, dtype: str = "c64", lazy: bool = False):
+    """The plan with renormalisations after given layers for a candidate key: (mode, block bits, low bits) at the
+    planner's beam width, or with a fourth entry, that beam width (the process-wide tunable, restored afterwards).
+    By default the circuit is cut after its renormalisation layers and each segment planned alone (SegmentedPlan);
+    with `lazy` it is planned once and renormalised at pass boundaries (LazyRenormPlan)."""
+    from .plan import LazyRenormPlan, SegmentedPlan
+    cls = LazyRenormPlan if lazy else SegmentedPlan
     mode, bits, low = cand[:3]
     if len(cand) == 3:
-        return SegmentedPlan(n, ops, renorm_after, mode, bits, low, dtype)
+        return cls(n, ops, renorm_after, mode, bits, low, dtype)
     old = B.qs_get_tunable("plan_beam")
     B.qs_set_tunable("plan_beam", cand[3])
     try:
-        return SegmentedPlan(n, ops, renorm_after, mode, bits, low, dtype)
+        return cls(n, ops, renorm_after, mode, bits, low, dtype)
     finally:
         B.qs_set_tunable("plan_beam", old)
 
 
 def choose_segmented(n: int, ops, renorm_after, dtype: str = "c64", model: Optional[CostModel] = None,
-                     cands: Optional[Sequence[Tuple[str, int, int]]] = None, beams: Sequence[int] = BEAMS):
-    """The segmented plan whose segments the model predicts fastest in sum: every block shape of candidates(n)
-    (or `cands`) at the planner's beam width and at each of `beams`; without a model, the greedy shape. Block
-    shapes only: the folded renormalisation rides on complex64 block passes, and fused-dense plans of these
-    circuits run at half the block plans' rate. Returns (plan, its candidate key, predicted ms or None)."""
+                     cands: Optional[Sequence[Tuple[str, int, int]]] = None, beams: Sequence[int] = BEAMS,
+                     lazy: bool = False):
+    """The renormalised plan (make_segmented; `lazy` selects the form) whose plans the model predicts fastest in
+    sum: every block shape of candidates(n) (or `cands`) at the planner's beam width and at each of `beams`;
+    without a model, the greedy shape. Block shapes only: the folded renormalisation rides on complex64 block
+    passes, and fused-dense plans of these circuits run at half the block plans' rate. Returns (plan, its
+    candidate key, predicted ms or None)."""
     g = greedy_for(n)
     if model is None:
-        return make_segmented(n, ops, renorm_after, g, dtype), g, None
+        return make_segmented(n, ops, renorm_after, g, dtype, lazy), g, None
     cur = B.qs_get_tunable("plan_beam")
     best = None
     for cand in (cands or [c for c in candidates(n) if c[0] == "block"]):
         for key in [cand] + [cand + (w,) for w in beams if w != cur]:
-            sp = make_segmented(n, ops, renorm_after, key, dtype)
-            t = sum(model.predict_plan_ms(p) for _, p, _ in sp.parts)
+            sp = make_segmented(n, ops, renorm_after, key, dtype, lazy)
+            t = sum(model.predict_plan_ms(p) for p in sp.plans())
             if best is None or t < best[2]:
                 if best is not None:
                     best[0].close()

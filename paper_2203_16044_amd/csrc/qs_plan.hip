@@ -1490,21 +1490,24 @@ QS_API int qs_plan_run_range(qs_state *st, qs_plan *P, int begin, int end)
     return QS_OK;
 }
 
-QS_API int qs_plan_run_renorm(qs_state *st, qs_plan *P, int flags)
+QS_API int qs_plan_run_range_renorm(qs_state *st, qs_plan *P, int begin, int end, int flags)
 {
     qs_clear_error();
-    if (int rc = check_run(st, P, "qs_plan_run_renorm"))
+    if (int rc = check_run(st, P, "qs_plan_run_range_renorm"))
         return rc;
     if (flags & ~(QS_RUN_SCALE_FIRST | QS_RUN_NORM_LAST))
-        return qs_fail(QS_EINVAL, "qs_plan_run_renorm: unknown flags 0x%x", flags);
+        return qs_fail(QS_EINVAL, "qs_plan_run_range_renorm: unknown flags 0x%x", flags);
+    const int np = (int)P->passes.size();
+    if (begin < 0 || end > np || begin > end)
+        return qs_fail(QS_EINVAL, "qs_plan_run_range_renorm: pass range [%d, %d) outside [0, %d]", begin, end, np);
     if (int rc = upload(P))
         return rc;
-    const int np = (int)P->passes.size();
     const uint64_t dim = (uint64_t)1 << st->n;
     double *pending = qs_pending_norm(st);
-    // the passes that move data (relabels launch nothing); a renormalisation folds into a complex64 block pass
+    // the range's passes that move data (relabels launch nothing); a renormalisation folds into a complex64 block
+    // pass
     int first = -1, last = -1;
-    for (int i = 0; i < np; ++i)
+    for (int i = begin; i < end; ++i)
         if (P->passes[i].type != 4) {
             if (first < 0)
                 first = i;
@@ -1522,12 +1525,13 @@ QS_API int qs_plan_run_renorm(qs_state *st, qs_plan *P, int flags)
         const PlanPass &pp = P->passes[last];
         nparts = launch_block_grid(st->dtype, pp.b, pp.sw, (uint64_t)1 << (P->n - pp.b));
         if (nparts == 0)
-            return qs_fail(QS_EUNSUPPORTED, "qs_plan_run_renorm: no block kernel for b = %d, w = %d", pp.b, pp.sw);
+            return qs_fail(QS_EUNSUPPORTED, "qs_plan_run_range_renorm: no block kernel for b = %d, w = %d", pp.b,
+                           pp.sw);
         parts = qs_block_partials(st, (size_t)nparts);
         if (!parts)
             return QS_ENOMEM;
     }
-    for (int i = 0; i < np; ++i) {
+    for (int i = begin; i < end; ++i) {
         BlkRenorm rn;
         if (scale_in && i == first)
             rn.scale_norm = pending;
@@ -1543,6 +1547,15 @@ QS_API int qs_plan_run_renorm(qs_state *st, qs_plan *P, int flags)
             QS_HIP(launch_probs(st->dtype, st->psi, dim, nullptr, st->red, probs_blocks(dim), pending, st->stream));
     }
     return QS_OK;
+}
+
+QS_API int qs_plan_run_renorm(qs_state *st, qs_plan *P, int flags)
+{
+    if (!P) {
+        qs_clear_error();
+        return qs_fail(QS_EINVAL, "qs_plan_run_renorm: NULL plan");
+    }
+    return qs_plan_run_range_renorm(st, P, 0, (int)P->passes.size(), flags);
 }
 
 QS_API int qs_renormalize_pending(qs_state *st, double *norm)

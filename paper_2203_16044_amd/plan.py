@@ -155,8 +155,73 @@ class SegmentedPlan:
         if pending:
             B.qs_renormalize_pending(state.h, False)
 
+    def plans(self) -> list:
+        return [p for _, p, _ in self.parts]
+
     def close(self) -> None:
         for c, p, _ in self.parts:
             p.close()
             c.close()
         self.parts = []
+
+
+def renorm_boundaries(plan, layers, marks) -> list:
+    """For each renormalisation layer L (ascending), the smallest pass index i such that every operation of a layer
+    <= L runs in passes 0..i: the renormalisation then follows pass i. Marks that no operation precedes are dropped
+    and marks that land on the same pass merge. `layers` holds each operation's layer, in the circuit's order."""
+    npass = plan.info()["passes"]
+    where = [-1] * len(layers)
+    for i in range(npass):
+        for g in B.qs_plan_pass_gates(plan.h, i):
+            where[g] = i
+    if min(where, default=0) < 0:
+        raise RuntimeError("plan does not place every operation of the circuit")
+    out = []
+    for L in sorted(set(marks)):
+        idx = [where[g] for g in range(len(layers)) if layers[g] <= L]
+        if idx and (not out or max(idx) > out[-1]):
+            out.append(max(idx))
+    return out
+
+
+class LazyRenormPlan:
+    """A circuit planned once, with the state renormalised (FP64 norm, FP64 factor) at pass boundaries: after each
+    renormalisation layer L, at the first boundary by which every operation of the layers <= L has run (some of
+    the next layers' operations may already have run there). A renormalisation multiplies the state by a scalar and
+    so commutes with every gate; it differs from renormalising exactly after layer L only through the rounding
+    drift of the norm it divides by. Each renormalisation is folded into the block passes on either side of its
+    boundary (qs_plan_run_range_renorm), the last one scaled in a sweep of its own if it ends the plan."""
+
+    def __init__(self, n: int, ops, renorm_after, mode: str = "block", block_bits: int = 12, low_bits: int = 4,
+                 dtype: str = "c64"):
+        ops = list(ops)
+        self.n = n
+        self.circuit = Circuit.from_ops(n, ops)
+        self.plan = Plan(self.circuit, mode, block_bits, low_bits, dtype)
+        self.bounds = renorm_boundaries(self.plan, [o.layer for o in ops], renorm_after)
+
+    def info(self) -> dict:
+        d = dict(self.plan.info())
+        d["renormalisations"] = len(self.bounds)
+        return d
+
+    def plans(self) -> list:
+        return [self.plan]
+
+    def run(self, state) -> None:
+        npass = self.plan.info()["passes"]
+        start, pending = 0, False
+        for b in self.bounds:
+            flags = (B.QS_RUN_SCALE_FIRST if pending else 0) | B.QS_RUN_NORM_LAST
+            B.qs_plan_run_range_renorm(state.h, self.plan.h, start, b + 1, flags)
+            start, pending = b + 1, True
+        if start < npass:
+            B.qs_plan_run_range_renorm(state.h, self.plan.h, start, npass, B.QS_RUN_SCALE_FIRST if pending else 0)
+        elif pending:
+            B.qs_renormalize_pending(state.h, False)
+
+    def close(self) -> None:
+        if getattr(self, "plan", None) is not None:
+            self.plan.close()
+            self.circuit.close()
+            self.plan = None

@@ -47,6 +47,7 @@ def test_null_handles_are_rejected_without_device_work():
     assert L.qs_fused_swap(None, 0, 1, 1) == B.QS_EINVAL
     assert L.qs_probs(None, None, None) == B.QS_EINVAL
     assert L.qs_plan_run_renorm(None, None, B.QS_RUN_NORM_LAST) == B.QS_EINVAL
+    assert L.qs_plan_run_range_renorm(None, None, 0, 0, B.QS_RUN_NORM_LAST) == B.QS_EINVAL
     assert L.qs_renormalize_pending(None, None) == B.QS_EINVAL
     assert L.qs_free(None) == B.QS_EINVAL
     assert "NULL" in qs.qs_last_error()

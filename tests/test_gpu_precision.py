@@ -173,7 +173,7 @@ def test_learned_segmented_plan_against_fp64_oracle(gpu):
     for cand in [c for c in CM.candidates(n) if c[0] == "block"]:
         for k in [cand] + [cand + (w,) for w in CM.BEAMS if w != cur]:
             q = CM.make_segmented(n, circ.ops, circ.renorm_after, k, "c64")
-            preds[k] = sum(model.predict_plan_ms(p) for _, p, _ in q.parts)
+            preds[k] = sum(model.predict_plan_ms(p) for p in q.plans())
             q.close()
     assert key in preds and preds[key] == pytest.approx(pred, rel=1e-6), (key, pred, preds)
     assert pred == pytest.approx(min(preds.values()), rel=1e-6), (key, pred, preds)
@@ -186,3 +186,46 @@ def test_learned_segmented_plan_against_fp64_oracle(gpu):
     sp.close()
     st.close()
     model.close()
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("mode,bits,low", [("block", 12, 4), ("block", 10, 3), ("fuse", 4, 0)])
+def test_lazy_renormalisation_against_fp64_oracle(gpu, dtype, mode, bits, low):
+    """One plan renormalised at pass boundaries (LazyRenormPlan; folded into complex64 block passes, sweeps
+    otherwise), from an unnormalised start: a unitary circuit keeps the norm, so the final state is the oracle's
+    run of the normalised start; it also equals the layer-exact segmented form up to rounding."""
+    import paper_2203_16044_amd.binding as B
+    from paper_2203_16044_amd.plan import LazyRenormPlan
+    n = 20
+    circ = C.su4_u3_renorm(n=n, seed=995, layers=12)
+    circ.renorm_after = (4, 8, 12)
+    psi0 = C.random_state(n, 996) * 1.3
+    ref = oracle.run(circ, psi0 / np.linalg.norm(psi0))
+    out = {}
+    for form in ("lazy", "segments"):
+        cls = LazyRenormPlan if form == "lazy" else SegmentedPlan
+        p = cls(n, circ.ops, circ.renorm_after, mode, bits, low, dtype)
+        if form == "lazy":
+            assert 1 <= len(p.bounds) <= 3 and p.info()["renormalisations"] == len(p.bounds)
+        st = gpu.State(n, dtype)
+        st.set(psi0)
+        p.run(st)
+        out[form] = np.asarray(st.get(), np.complex128)
+        assert abs(st.norm() - 1.0) <= (1e-6 if dtype == "c64" else 1e-12), form
+        if form == "lazy":
+            np_ = p.info()["passes"]
+            for a, b in ((1, 0), (0, np_ + 1), (-1, 0)):
+                with pytest.raises(B.QSError):
+                    B.qs_plan_run_range_renorm(st.h, p.plan.h, a, b, 0)
+            with pytest.raises(B.QSError):
+                B.qs_plan_run_range_renorm(st.h, p.plan.h, 0, 0, 4)
+        p.close()
+        st.close()
+    if dtype == "c64":
+        infid, maxd = oracle.error_metrics(out["lazy"], ref)
+        assert infid <= 1e-8 and maxd <= 1e-6, (infid, maxd)
+        infid, maxd = oracle.error_metrics(out["lazy"], out["segments"])
+        assert infid <= 1e-10 and maxd <= 1e-6, (infid, maxd)
+    else:
+        assert float(np.max(np.abs(out["lazy"] - ref))) <= 1e-12
+        assert float(np.max(np.abs(out["lazy"] - out["segments"]))) <= 1e-12

@@ -323,3 +323,31 @@ def test_remap_plan_executes_the_circuit(bits, low):
             assert 4 in kinds  # circuit fused-swaps became relabels
         p.close()
         c.close()
+
+
+@pytest.mark.parametrize("bits,low", [(12, 4), (12, 3), (10, 3)])
+def test_lazy_renormalisation_boundaries(bits, low):
+    """LazyRenormPlan's boundaries, checked by replaying the plan's passes: after boundary pass b of mark L every
+    operation of a layer <= L has run, before it some had not (b is the first such pass), boundaries strictly
+    increase, and a mark no operation precedes is dropped."""
+    from paper_2203_16044_amd.plan import LazyRenormPlan
+    circ = C.su4_u3_renorm(n=20, seed=990, layers=12)
+    marks = (0, 4, 8, 12)  # layers count from 1: nothing precedes mark 0
+    lp = LazyRenormPlan(circ.n, circ.ops, marks, "block", bits, low, "c64")
+    layers = [o.layer for o in circ.ops]
+    assert min(layers) >= 1
+    gates = lp.plan.pass_gates()
+    assert sorted(g for ps in gates for g in ps) == list(range(len(circ.ops)))
+    done, complete_after = set(), []
+    for ps in gates:
+        done.update(ps)
+        complete_after.append(lambda L, d=frozenset(done): all(g in d for g in range(len(layers)) if layers[g] <= L))
+    want = []
+    for L in (4, 8, 12):
+        b = next(i for i in range(len(gates)) if complete_after[i](L))
+        if not want or b > want[-1]:
+            want.append(b)
+    assert lp.bounds == want and all(x < y for x, y in zip(lp.bounds, lp.bounds[1:]))
+    assert lp.bounds[-1] == max(i for i, ps in enumerate(gates) if ps)  # the last mark is the last layer
+    assert lp.info()["renormalisations"] == len(want)
+    lp.close()
