@@ -243,8 +243,9 @@ QS_API int qs_plan_create(qs_plan **out, const qs_circuit *c, const qs_plan_opts
  * QS_EINVAL if n or dtype differ from the plan's, or if the plan was uploaded to another device. */
 QS_API int qs_plan_run(qs_state *st, qs_plan *p);
 QS_API int qs_plan_run_range(qs_state *st, qs_plan *p, int begin, int end);
-/* Periodic renormalisation between plans (the complex64 cadence: a state renormalised after given layers, each
- * stretch of layers its own plan). Runs every pass of p like qs_plan_run, and:
+/* Periodic renormalisation (the complex64 cadence: a state renormalised after given layers), here between plans,
+ * each stretch of layers its own plan (inside one plan: qs_plan_run_range_renorm). Runs every pass of p like
+ * qs_plan_run, and:
  *   QS_RUN_SCALE_FIRST  first scales the state by 1 / sqrt(N), N the state's pending norm (left by an earlier
  *                       QS_RUN_NORM_LAST run), the factor formed and applied in FP64 (complex64: rounded to FP32);
  *   QS_RUN_NORM_LAST    then sets the pending norm to sum_i |a_i|^2 (FP64, fixed-order reduction) of the state
@@ -265,7 +266,8 @@ QS_API int qs_plan_run_renorm(qs_state *st, qs_plan *p, int flags);
  * flags scales by the pending norm and then takes the norm of the scaled state, each in a sweep of its own. */
 QS_API int qs_plan_run_range_renorm(qs_state *st, qs_plan *p, int begin, int end, int flags);
 /* Scale the state by 1 / sqrt(N) for its pending norm N (the last renormalisation of a sequence of
- * qs_plan_run_renorm calls); optionally returns N. Synchronises when norm is non-null. */
+ * qs_plan_run_renorm or qs_plan_run_range_renorm calls); optionally returns N. Synchronises when norm is
+ * non-null. */
 QS_API int qs_renormalize_pending(qs_state *st, double *norm);
 /* Pass counts: all passes, LDS block passes, dense passes, others (fused-swaps, large controlled gates, relabels),
  * and the number of fused operations executed inside the block / dense passes. Any output may be NULL. */
